@@ -1,0 +1,130 @@
+"""Brute-force reference for the oracle pins: no splitting, no Romberg.
+
+Integrates Hamilton's equations of the general Hamiltonian of §2.1
+(eq. generalH)
+
+    H = -(1 + hX) Ps - (q/p0)(1 + hX) A_s + Pt/β0,
+
+together with the spin equation dS/ds = Ω × S (eq. t-bmt.s), with an
+adaptive 8th-order Runge–Kutta method (scipy's DOP853) at tolerances near
+double-precision round-off.  Hamilton's equations are written here directly
+from H, term by term:
+
+    X'  =  (1 + hX) Px/Ps          Px' = h Ps - ∂V/∂X
+    Y'  =  (1 + hX) Py/Ps          Py' = -∂V/∂Y
+    T'  = -(1 + hX)(1/β0 + Pt)/Ps + 1/β0,    Pt' = 0
+
+with V = -(q/p0)(1 + hX) A_s:  sector bend V = (η/2)(1 + hX)^2, quadrupole
+V = (k1/2)(X^2 - Y^2), sextupole V = (k2/6)(X^3 - 3 X Y^2).
+
+Thin multipoles are the limit of a kick flow over a unit pseudo-length with
+no drift term: X, Y fixed, Px and Py changing linearly, the spin precessing
+about the integrated Ω evaluated along the changing momenta.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.integrate import solve_ivp
+
+
+def _omega(X, Px, Py, Pt, h, b, beam):
+    b0 = beam.beta0
+    P = math.sqrt(1.0 + 2.0 * Pt / b0 + Pt * Pt)
+    Ps = math.sqrt(1.0 + 2.0 * Pt / b0 + Pt * Pt - Px * Px - Py * Py)
+    u = np.array([Px, Py, Ps]) / P
+    gamma = beam.gamma0 * (1.0 + b0 * Pt)
+    a1, a2 = 1.0 + beam.G * gamma, beam.G * (gamma - 1.0)
+    ub = float(u @ b)
+    om = -(1.0 + h * X) / Ps * (a1 * b - a2 * ub * u)
+    om[1] += h
+    return om
+
+
+def _rhs_thick(kind, par, beam):
+    b0 = beam.beta0
+    h = par.get("h", 0.0)
+    eta = par.get("eta", 1.0)
+    k1 = par.get("k1", 0.0)
+    k2 = par.get("k2", 0.0)
+
+    def f(s, y):
+        X, Px, Y, Py, T, Pt, Sx, Sy, Sz = y
+        Ps = math.sqrt(1.0 + 2.0 * Pt / b0 + Pt * Pt - Px * Px - Py * Py)
+        w = 1.0 + h * X
+        if kind == "sbend":
+            dVx, dVy = eta * h * w, 0.0
+            b = np.array([0.0, eta * h, 0.0])
+        elif kind == "quad":
+            dVx, dVy = k1 * X, -k1 * Y
+            b = np.array([k1 * Y, k1 * X, 0.0])
+        elif kind == "sext":
+            dVx, dVy = 0.5 * k2 * (X * X - Y * Y), -k2 * X * Y
+            b = np.array([k2 * X * Y, 0.5 * k2 * (X * X - Y * Y), 0.0])
+        else:  # drift
+            dVx = dVy = 0.0
+            b = np.zeros(3)
+        om = _omega(X, Px, Py, Pt, h, b, beam)
+        S = np.array([Sx, Sy, Sz])
+        dS = np.cross(om, S)
+        return [w * Px / Ps, h * Ps - dVx, w * Py / Ps, -dVy,
+                -w * (1.0 / b0 + Pt) / Ps + 1.0 / b0, 0.0, dS[0], dS[1], dS[2]]
+    return f
+
+
+def _rhs_thin(k1l, k2l, X, Y, beam):
+    # integrated field of the thin multipole at the (fixed) position
+    b = np.array([k1l * Y + k2l * X * Y, k1l * X + 0.5 * k2l * (X * X - Y * Y), 0.0])
+    dPx = -(k1l * X + 0.5 * k2l * (X * X - Y * Y))
+    dPy = k1l * Y + k2l * X * Y
+
+    def f(t, y):
+        Xs, Px, Ys, Py, T, Pt, Sx, Sy, Sz = y
+        om = _omega(X, Px, Py, Pt, 0.0, b, beam)
+        dS = np.cross(om, np.array([Sx, Sy, Sz]))
+        return [0.0, dPx, 0.0, dPy, 0.0, 0.0, dS[0], dS[1], dS[2]]
+    return f
+
+
+def track_element(e, beam, z, s, rtol=1e-13, atol=1e-16):
+    """Brute-force map of one element (workloads.Element) on one particle."""
+    y0 = np.concatenate([np.asarray(z, float), np.asarray(s, float)])
+    if e.kind == "snake":
+        hp = e.snake_phi / 2.0
+        ax = np.array([math.sin(e.snake_mu), 0.0, math.cos(e.snake_mu)])
+        S = np.asarray(s, float)
+        # Rodrigues' rotation formula
+        th = e.snake_phi
+        Sr = S * math.cos(th) + np.cross(ax, S) * math.sin(th) + ax * (ax @ S) * (1 - math.cos(th))
+        del hp
+        return np.asarray(z, float).copy(), Sr
+    if e.kind == "marker":
+        return np.asarray(z, float).copy(), np.asarray(s, float).copy()
+    if e.kind == "thin":
+        f = _rhs_thin(e.k1l, e.k2l, z[0], z[2], beam)
+        L = 1.0
+    else:
+        par = {}
+        if e.kind == "sbend":
+            par = {"h": e.angle / e.L, "eta": e.eta}
+            kind = "sbend"
+        elif e.kind == "quad":
+            par = {"k1": e.k1}
+            kind = "quad"
+        else:
+            kind = "drift"
+        f = _rhs_thick(kind, par, beam)
+        L = e.L
+    sol = solve_ivp(f, (0.0, L), y0, method="DOP853", rtol=rtol, atol=atol)
+    y = sol.y[:, -1]
+    return y[:6].copy(), y[6:].copy()
+
+
+def track_line(elements, beam, z, s, **kw):
+    z = np.asarray(z, float).copy()
+    s = np.asarray(s, float).copy()
+    for e in elements:
+        z, s = track_element(e, beam, z, s, **kw)
+    return z, s
