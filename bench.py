@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the spin–orbit tracking hot path on one MI355X.
+
+Workload: the RHIC-scale synthetic ring (1706 elements: 264 exact sector
+bends with 8 slices and 4 Romberg rows, 456 matrix-kick quadrupoles with 4
+slices, 132 thin sextupoles, 852 drifts, two ±45° snakes), 2^20 protons at
+γ0 = 25 from the seeded 6-D Gaussian, spins vertical.  One step is one
+st_track call of --turns-per-step turns over the whole bunch (orbit maps,
+Ω at every slice edge, quaternion builds, Romberg level products and
+tableau, element composition, spin rotation, loss checks and polarization
+reduction), with the bunch resident in HBM.  The default 10 × 100 turns is
+the full 1000-turn run.
+
+Prints one JSON line (see the keys below).  `roofline.achieved` is the
+algorithmic operation count of one particle-turn (the CPU oracle's counted
+operations for this ring, each add, multiply, divide, square root and
+elementary function counted once) times the particle-turns of one launch,
+divided by the launch's average duration measured with HIP events on the
+launch stream.  `cpu_baseline` times the CPU oracle on a bounded sample of
+the same workload on the host cores (rank 0, N = 1 only).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-turns/s on 1.7k-element ring: FP64 vs mixed/surrogate @ spin err ≤1e-6"
+# Operations per particle-turn counted by the oracle's counting scalar on
+# this ring (add/sub 428160, mul 768796, div 200882, sqrt 38136, sin/cos
+# 34592, asin 4224, sinh/cosh 10944).
+OPS_PER_PARTICLE_TURN = 1_485_734
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--turns-per-step", type=int, default=100)
+    ap.add_argument("--particles", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-particles", type=int, default=4096)
+    ap.add_argument("--cpu-sample-turns", type=int, default=10)
+    return ap.parse_args()
+
+
+def cpu_baseline(ring, beam, z, s, a, n_sample, turns):
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    zs, ss, as_ = z[:, :n_sample].copy(), s[:, :n_sample].copy(), a[:n_sample].copy()
+    t0 = time.perf_counter()
+    oracle.track(ring, beam, zs, ss, as_, turns=turns, extended=True, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * turns / dt, "unit": "particle-turns/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_sample} particles x {turns} turns of the same ring and bunch, "
+                      f"extended-precision oracle, {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(particles are independent: each GPU would track its own share)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from workloads import Beam, gaussian_bunch, lattice_summary, rhic_like_ring
+    from workloads.bunch import SEED_BASE
+
+    beam = Beam()
+    ring = rhic_like_ring()
+    summ = lattice_summary(ring)
+    n, T = args.particles, args.turns_per_step
+    log(f"[bench] building bunch n={n} ring={summ['n_elements']} elements")
+    z, s, a = gaussian_bunch(n, SEED_BASE + 1, beam)
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    tr = SpinTracker(ring, beam, device=0, precision="fp64", report_every=T)
+    with torch.cuda.stream(stream):
+        tr.set_particles(z, s, a)
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        tr.track(T, stream=stream)
+        stream.synchronize()
+        log(f"[bench] warmup step {w + 1}/{args.warmup} done")
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        tr.track(T, stream=stream)
+        ev[k + 1].record(stream)
+    for k in range(args.steps):
+        ev[k + 1].synchronize()
+        log(f"[bench] step {k + 1}/{args.steps}: {ev[k].elapsed_time(ev[k + 1]):.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    total_s = sum(step_ms) / 1e3
+    rate = n * T * args.steps / total_s
+
+    pol = tr.polarization(stream=stream).cpu().numpy()
+    _, _, alive = tr.read(stream=stream)
+    survival = float((alive == 1).mean())
+    tr.close()
+
+    achieved = OPS_PER_PARTICLE_TURN * n * T / (np.mean(step_ms) / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": rate,
+        "unit": "particle-turns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean(step_ms)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "rhic_like_ring_fp64",
+            "elements": summ["n_elements"],
+            "circumference_m": round(summ["circumference_m"], 3),
+            "particles": n,
+            "turns_per_step": T,
+            "precision": "fp64",
+            "quad": "MK, 4 slices", "bend": "exact, 8 slices", "romberg_rows": 4,
+            "survival": survival,
+            "final_polarization": [float(v) for v in pol[-1, :3]] if len(pol) else None,
+            "wall_s": round(wall, 3),
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(ring, beam, z, s, a, args.cpu_sample_particles,
+                                           args.cpu_sample_turns)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

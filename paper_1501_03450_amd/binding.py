@@ -1,0 +1,149 @@
+"""ctypes binding of libspintrack.so: the C ABI of include/spintrack.h.
+
+Argument marshalling only.  Functions keep the C names; each raises
+SpinTrackError when the library returns a non-zero status.  Device memory
+and streams come from PyTorch (tensor.data_ptr(), stream.cuda_stream).
+The library must have been built (paper_1501_03450_amd/build.py); importing
+this module fails loudly if it is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspintrack.so")
+
+ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDEVICE, ST_ESTATE = 0, -1, -2, -3, -4
+ST_MARKER, ST_DRIFT, ST_SBEND, ST_QUAD, ST_THIN, ST_SNAKE = range(6)
+ST_ORB_EXACT, ST_ORB_DKD, ST_ORB_MK = range(3)
+ST_FP64, ST_MIXED = 0, 1
+
+KIND_CODES = {"marker": ST_MARKER, "drift": ST_DRIFT, "sbend": ST_SBEND, "quad": ST_QUAD,
+              "thin": ST_THIN, "snake": ST_SNAKE}
+ORBIT_CODES = {"exact": ST_ORB_EXACT, "dkd": ST_ORB_DKD, "mk": ST_ORB_MK}
+PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED}
+
+EXPORTS = ("st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
+           "st_bind_quaternions", "st_track", "st_polarization", "st_read_particles",
+           "st_last_error")
+
+
+class st_element(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("orbit", ctypes.c_int32),
+                ("n_slices", ctypes.c_int32), ("romberg_rows", ctypes.c_int32),
+                ("L", ctypes.c_double), ("angle", ctypes.c_double), ("eta", ctypes.c_double),
+                ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
+                ("snake_phi", ctypes.c_double), ("snake_mu", ctypes.c_double)]
+
+
+class st_beam(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("gamma0", ctypes.c_double), ("aperture", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("report_every", ctypes.c_int32)]
+
+
+class SpinTrackError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"spintrack status {status}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1501_03450_amd/build.py "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.st_create.argtypes = [P(vp), i32]
+    lib.st_destroy.argtypes = [vp]
+    lib.st_load_lattice.argtypes = [vp, P(st_element), i64, P(st_beam)]
+    lib.st_bind_particles.argtypes = [vp, i64, vp, vp, vp]
+    lib.st_bind_quaternions.argtypes = [vp, vp]
+    lib.st_track.argtypes = [vp, i64, vp]
+    lib.st_polarization.argtypes = [vp, vp, i64, P(i64), vp]
+    lib.st_read_particles.argtypes = [vp, vp, vp, vp, vp]
+    lib.st_last_error.argtypes = [vp]
+    lib.st_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "st_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+LIB = _load()
+
+
+def _check(ctx, status):
+    if status != ST_OK:
+        msg = LIB.st_last_error(ctx).decode() if ctx else "invalid argument"
+        raise SpinTrackError(status, msg)
+
+
+def st_last_error(ctx) -> str:
+    return LIB.st_last_error(ctx).decode()
+
+
+def st_create(device: int = 0):
+    h = ctypes.c_void_p()
+    st = LIB.st_create(ctypes.byref(h), int(device))
+    if st != ST_OK:
+        raise SpinTrackError(st, f"cannot create a context on device {device}")
+    return h
+
+
+def st_destroy(ctx) -> None:
+    LIB.st_destroy(ctx)
+
+
+def element_array(elements):
+    """Marshal element records (objects with the st_element field names,
+    string kind/method) into a ctypes array."""
+    arr = (st_element * max(len(elements), 1))()
+    for i, e in enumerate(elements):
+        a = arr[i]
+        a.kind = KIND_CODES[e.kind] if isinstance(e.kind, str) else int(e.kind)
+        method = getattr(e, "method", getattr(e, "orbit", "exact"))
+        a.orbit = ORBIT_CODES[method] if isinstance(method, str) else int(method)
+        a.n_slices = int(e.n_slices)
+        a.romberg_rows = int(getattr(e, "rows", getattr(e, "romberg_rows", 1)))
+        a.L, a.angle, a.eta = float(e.L), float(e.angle), float(e.eta)
+        a.k1, a.k1l, a.k2l = float(e.k1), float(e.k1l), float(e.k2l)
+        a.snake_phi, a.snake_mu = float(e.snake_phi), float(e.snake_mu)
+    return arr
+
+
+def st_load_lattice(ctx, elements, G, gamma0, aperture, precision="fp64", report_every=0):
+    arr = element_array(elements)
+    b = st_beam(G=float(G), gamma0=float(gamma0), aperture=float(aperture),
+                precision=PRECISION_CODES[precision] if isinstance(precision, str) else int(precision),
+                report_every=int(report_every))
+    _check(ctx, LIB.st_load_lattice(ctx, arr, len(elements), ctypes.byref(b)))
+
+
+def st_load_lattice_raw(ctx, arr, n, beam):
+    """Pass an already marshalled st_element array and st_beam (validation tests)."""
+    return LIB.st_load_lattice(ctx, arr, int(n), ctypes.byref(beam) if beam is not None else None)
+
+
+def st_bind_particles(ctx, n, z_ptr, spin_ptr, alive_ptr):
+    _check(ctx, LIB.st_bind_particles(ctx, int(n), z_ptr, spin_ptr, alive_ptr))
+
+
+def st_bind_quaternions(ctx, q_ptr):
+    _check(ctx, LIB.st_bind_quaternions(ctx, q_ptr))
+
+
+def st_track(ctx, turns, stream=None):
+    _check(ctx, LIB.st_track(ctx, int(turns), stream))
+
+
+def st_polarization(ctx, d_out_ptr=None, capacity=0, stream=None) -> int:
+    n = ctypes.c_int64(0)
+    _check(ctx, LIB.st_polarization(ctx, d_out_ptr, int(capacity), ctypes.byref(n), stream))
+    return int(n.value)
+
+
+def st_read_particles(ctx, h_z_ptr, h_spin_ptr, h_alive_ptr, stream=None):
+    _check(ctx, LIB.st_read_particles(ctx, h_z_ptr, h_spin_ptr, h_alive_ptr, stream))

@@ -1,0 +1,397 @@
+// C ABI of the tracking library: context, validation, lattice compression
+// and kernel launches.  See include/spintrack.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "lattice_table.h"
+#include "spintrack.h"
+#include "track_kernels.h"
+
+struct st_ctx {
+  int device = 0;
+  std::string err;
+  // lattice
+  bool have_lattice = false;
+  st_beam beam{};
+  double beta0 = 0.0;
+  int n_elems = 0;
+  int n_unique = 0;
+  int nt = 16;             // quaternion series terms
+  double ymax = 0.0;
+  st::DevElem* d_tab = nullptr;
+  uint16_t* d_seq = nullptr;
+  // particles
+  int64_t n = 0;
+  double* z = nullptr;
+  double* spin = nullptr;
+  int32_t* alive = nullptr;
+  double* qout = nullptr;
+  bool have_particles = false;
+  // polarization
+  double* d_partials = nullptr;
+  size_t partials_cap = 0;     // doubles
+  double* d_pol = nullptr;
+  size_t pol_cap = 0;          // doubles
+  int64_t n_reports = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int old = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+  }
+};
+
+st_status fail(st_ctx* c, st_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+st_status hip_fail(st_ctx* c, hipError_t e, const char* what) {
+  return fail(c, ST_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite_all(const st_element& e) {
+  const double v[] = {e.L, e.angle, e.eta, e.k1, e.k1l, e.k2l, e.snake_phi, e.snake_mu};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+int v2(int n) {
+  int k = 0;
+  while ((n & 1) == 0) { n >>= 1; ++k; }
+  return k;
+}
+
+// Largest (θ/2)² for which NT terms of the cos series stay below 2^-56.
+double series_ymax(int nt) {
+  return std::exp((-56.0 * std::log(2.0) + std::lgamma(2.0 * nt + 1.0)) / nt);
+}
+
+std::string validate(const st_element& e, int64_t i) {
+  const std::string at = "element " + std::to_string(i) + ": ";
+  if (!finite_all(e)) return at + "non-finite parameter";
+  if (e.kind < ST_MARKER || e.kind > ST_SNAKE) return at + "unknown kind " + std::to_string(e.kind);
+  if (e.orbit < ST_ORB_EXACT || e.orbit > ST_ORB_MK) return at + "unknown orbit method";
+  if (e.L < 0.0) return at + "negative length";
+  switch (e.kind) {
+    case ST_DRIFT:
+      if (e.orbit != ST_ORB_EXACT) return at + "drifts use the exact method";
+      break;
+    case ST_SBEND:
+      if (e.orbit != ST_ORB_EXACT) return at + "sector bends use the exact method";
+      if (!(e.L > 0.0)) return at + "sector bend needs L > 0";
+      if (e.angle == 0.0) return at + "sector bend needs a non-zero angle";
+      if (!(e.eta > 0.0)) return at + "sector bend needs eta > 0";
+      break;
+    case ST_QUAD:
+      if (e.orbit != ST_ORB_DKD && e.orbit != ST_ORB_MK) return at + "quadrupoles use DKD or MK";
+      if (!(e.L > 0.0)) return at + "quadrupole needs L > 0";
+      break;
+    default:
+      break;
+  }
+  if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
+    if (e.n_slices < 1) return at + "n_slices must be >= 1";
+    if (e.romberg_rows < 1 || e.romberg_rows > st::kMaxRows)
+      return at + "romberg_rows must be in 1.." + std::to_string(st::kMaxRows);
+  }
+  return std::string();
+}
+
+st::DevElem derive(const st_element& e, const st_beam& b, double beta0) {
+  st::DevElem d;
+  std::memset(&d, 0, sizeof(d));
+  d.kind = e.kind;
+  d.orbit = e.orbit;
+  d.L = e.L;
+  d.nsl = 1;
+  d.K = 0;
+  if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
+    d.nsl = e.n_slices;
+    const int re = std::min(e.romberg_rows, 1 + v2(e.n_slices));
+    d.K = re - 1;
+    d.ds = e.L / e.n_slices;
+    d.hds = 0.5 * d.ds;
+  }
+  if (e.kind == ST_SBEND) {
+    d.h = e.angle / e.L;
+    d.eta = e.eta;
+    d.eta_h = e.eta * d.h;
+    d.inv_eta_h = 1.0 / (e.eta * d.h);
+    d.cs = std::cos(d.h * d.ds);
+    d.sn = std::sin(d.h * d.ds);
+    const double s2 = std::sin(0.5 * d.h * d.ds);
+    d.omc = 2.0 * s2 * s2;
+    d.one_m_eta2 = (1.0 - e.eta) * (1.0 + e.eta);
+    d.ds_eta = d.ds / e.eta;
+    d.tconst = (1.0 - 1.0 / e.eta) * d.ds / beta0;
+  } else if (e.kind == ST_QUAD) {
+    d.k1 = e.k1;
+    d.k1ds = e.k1 * d.ds;
+    d.kabs_hds2 = std::fabs(e.k1) * d.hds * d.hds;
+  } else if (e.kind == ST_THIN) {
+    d.k1l = e.k1l;
+    d.k2l = e.k2l;
+  } else if (e.kind == ST_SNAKE) {
+    const double hp = 0.5 * e.snake_phi;
+    d.qw = std::cos(hp);
+    d.qx = std::sin(hp) * std::sin(e.snake_mu);
+    d.qy = 0.0;
+    d.qz = std::sin(hp) * std::cos(e.snake_mu);
+  }
+  (void)b;
+  return d;
+}
+
+// Largest rotation angle a design-amplitude particle meets in one
+// quaternion build of this element (used to size the series).
+double design_angle(const st_element& e, const st_beam& b) {
+  const double a1 = 1.0 + b.G * b.gamma0;
+  const double r_ref = 0.02;
+  if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
+    const int N = e.n_slices;
+    const int K = std::min(e.romberg_rows, 1 + v2(N)) - 1;
+    const double ds = e.L / N;
+    const int stride = 1 << K;
+    const double f = stride < N ? stride * ds : 0.5 * stride * ds;
+    double om;
+    if (e.kind == ST_SBEND) {
+      const double h = e.angle / e.L;
+      om = std::fabs(a1 * e.eta * h - h);
+    } else {
+      om = a1 * std::fabs(e.k1) * r_ref;
+    }
+    return f * om;
+  }
+  if (e.kind == ST_THIN) return a1 * (std::fabs(e.k1l) * r_ref + 0.5 * std::fabs(e.k2l) * r_ref * r_ref);
+  return 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+st_status st_create(st_ctx** out, int device) {
+  if (!out) return ST_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return ST_EINVAL;
+  st_ctx* c = new (std::nothrow) st_ctx();
+  if (!c) return ST_ENOMEM;
+  c->device = device;
+  *out = c;
+  return ST_OK;
+}
+
+st_status st_destroy(st_ctx* c) {
+  if (!c) return ST_OK;
+  {
+    DeviceGuard g(c->device);
+    if (c->d_tab) (void)hipFree(c->d_tab);
+    if (c->d_seq) (void)hipFree(c->d_seq);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_pol) (void)hipFree(c->d_pol);
+  }
+  delete c;
+  return ST_OK;
+}
+
+const char* st_last_error(const st_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_beam* b) {
+  if (!c) return ST_EINVAL;
+  if (!b) return fail(c, ST_EINVAL, "beam is NULL");
+  if (n < 0 || n > std::numeric_limits<int32_t>::max()) return fail(c, ST_EINVAL, "bad element count");
+  if (n > 0 && !els) return fail(c, ST_EINVAL, "elements are NULL");
+  if (!std::isfinite(b->G) || !std::isfinite(b->gamma0) || !(b->gamma0 > 1.0))
+    return fail(c, ST_EINVAL, "gamma0 must be finite and > 1, G finite");
+  if (!(b->aperture > 0.0)) return fail(c, ST_EINVAL, "aperture must be > 0");
+  if (b->precision != ST_FP64 && b->precision != ST_MIXED) return fail(c, ST_EINVAL, "unknown precision");
+  if (b->report_every < 0) return fail(c, ST_EINVAL, "report_every must be >= 0");
+  for (int64_t i = 0; i < n; ++i) {
+    std::string m = validate(els[i], i);
+    if (!m.empty()) return fail(c, ST_EINVAL, m);
+  }
+  const double beta0 = std::sqrt(1.0 - 1.0 / (b->gamma0 * b->gamma0));
+
+  // compress: unique elements + index sequence
+  std::vector<st_element> uniq;
+  std::vector<uint16_t> seq((size_t)n);
+  double theta = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    int k = -1;
+    for (size_t u = 0; u < uniq.size(); ++u)
+      if (std::memcmp(&uniq[u], &els[i], sizeof(st_element)) == 0) { k = (int)u; break; }
+    if (k < 0) {
+      if (uniq.size() >= 65535) return fail(c, ST_EINVAL, "more than 65535 distinct elements");
+      uniq.push_back(els[i]);
+      k = (int)uniq.size() - 1;
+    }
+    seq[(size_t)i] = (uint16_t)k;
+    theta = std::max(theta, design_angle(els[i], *b));
+  }
+  std::vector<st::DevElem> tab(std::max<size_t>(uniq.size(), 1));
+  for (size_t u = 0; u < uniq.size(); ++u) tab[u] = derive(uniq[u], *b, beta0);
+
+  DeviceGuard g(c->device);
+  if (c->d_tab) { (void)hipFree(c->d_tab); c->d_tab = nullptr; }
+  if (c->d_seq) { (void)hipFree(c->d_seq); c->d_seq = nullptr; }
+  c->have_lattice = false;
+  hipError_t e;
+  if ((e = hipMalloc(&c->d_tab, tab.size() * sizeof(st::DevElem))) != hipSuccess)
+    return fail(c, ST_ENOMEM, std::string("lattice table: ") + hipGetErrorString(e));
+  if ((e = hipMalloc(&c->d_seq, std::max<size_t>(seq.size(), 1) * sizeof(uint16_t))) != hipSuccess)
+    return fail(c, ST_ENOMEM, std::string("lattice sequence: ") + hipGetErrorString(e));
+  if ((e = hipMemcpy(c->d_tab, tab.data(), tab.size() * sizeof(st::DevElem), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(c, e, "upload lattice table");
+  if (n > 0 && (e = hipMemcpy(c->d_seq, seq.data(), seq.size() * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(c, e, "upload lattice sequence");
+
+  // series terms: cover the design angles with 10% margin; lanes beyond use sincos
+  const double y = 1.21 * 0.25 * theta * theta;
+  c->nt = 16;
+  for (int nt : {8, 12, 16})
+    if (series_ymax(nt) >= y) { c->nt = nt; break; }
+  c->ymax = series_ymax(c->nt);
+  c->beam = *b;
+  c->beta0 = beta0;
+  c->n_elems = (int)n;
+  c->n_unique = (int)uniq.size();
+  c->have_lattice = true;
+  c->err.clear();
+  return ST_OK;
+}
+
+st_status st_bind_particles(st_ctx* c, int64_t n, double* z, double* spin, int32_t* alive) {
+  if (!c) return ST_EINVAL;
+  if (n < 0) return fail(c, ST_EINVAL, "negative particle count");
+  if (n > (int64_t)std::numeric_limits<int32_t>::max() * 256)
+    return fail(c, ST_EINVAL, "too many particles");
+  if (n > 0 && (!z || !spin || !alive)) return fail(c, ST_EINVAL, "particle pointers are NULL");
+  c->n = n;
+  c->z = z;
+  c->spin = spin;
+  c->alive = alive;
+  c->qout = nullptr;
+  c->have_particles = true;
+  c->err.clear();
+  return ST_OK;
+}
+
+st_status st_bind_quaternions(st_ctx* c, double* q) {
+  if (!c) return ST_EINVAL;
+  if (!c->have_particles) return fail(c, ST_ESTATE, "bind particles first");
+  c->qout = q;
+  return ST_OK;
+}
+
+st_status st_track(st_ctx* c, int64_t turns, void* stream) {
+  if (!c) return ST_EINVAL;
+  if (!c->have_lattice) return fail(c, ST_ESTATE, "no lattice loaded");
+  if (!c->have_particles) return fail(c, ST_ESTATE, "no particles bound");
+  if (turns < 0 || turns > std::numeric_limits<int32_t>::max())
+    return fail(c, ST_EINVAL, "turns must be in 0..2^31-1");
+  if (c->beam.precision != ST_FP64) return fail(c, ST_EINVAL, "mixed precision is not built yet");
+  c->n_reports = 0;
+  if (turns == 0 || c->n == 0) return ST_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int bs = st::track_block_size();
+  const int64_t nb = (c->n + bs - 1) / bs;
+  const int rep_every = c->beam.report_every;
+  const int64_t n_rep = rep_every > 0 ? turns / rep_every : 0;
+  hipError_t e;
+  if (n_rep > 0) {
+    const size_t need = (size_t)n_rep * (size_t)nb * 4;
+    if (need > c->partials_cap) {
+      if (c->d_partials) { (void)hipFree(c->d_partials); c->d_partials = nullptr; c->partials_cap = 0; }
+      if ((e = hipMalloc(&c->d_partials, need * sizeof(double))) != hipSuccess)
+        return fail(c, ST_ENOMEM, std::string("polarization partials: ") + hipGetErrorString(e));
+      c->partials_cap = need;
+    }
+    if ((size_t)n_rep * 4 > c->pol_cap) {
+      if (c->d_pol) { (void)hipFree(c->d_pol); c->d_pol = nullptr; c->pol_cap = 0; }
+      if ((e = hipMalloc(&c->d_pol, (size_t)n_rep * 4 * sizeof(double))) != hipSuccess)
+        return fail(c, ST_ENOMEM, std::string("polarization history: ") + hipGetErrorString(e));
+      c->pol_cap = (size_t)n_rep * 4;
+    }
+  }
+  st::TrackArgs a;
+  a.z = c->z;
+  a.spin = c->spin;
+  a.alive = c->alive;
+  a.qout = c->qout;
+  a.n = c->n;
+  a.tab = c->d_tab;
+  a.seq = c->d_seq;
+  a.n_elems = c->n_elems;
+  a.turns = (int32_t)turns;
+  a.report_every = rep_every;
+  a.n_blocks = (int32_t)nb;
+  a.partials = c->d_partials;
+  a.beta0 = c->beta0;
+  a.inv_beta0 = 1.0 / c->beta0;
+  a.gamma0 = c->beam.gamma0;
+  a.inv_gamma0_sq = 1.0 / (c->beam.gamma0 * c->beam.gamma0);
+  a.G = c->beam.G;
+  a.aperture = c->beam.aperture;
+  a.ymax = c->ymax;
+  if ((e = st::launch_track_fp64(a, c->nt, s)) != hipSuccess) return hip_fail(c, e, "launch track");
+  if (n_rep > 0) {
+    if ((e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol, s)) != hipSuccess)
+      return hip_fail(c, e, "launch polarization reduction");
+  }
+  c->n_reports = n_rep;
+  c->err.clear();
+  return ST_OK;
+}
+
+st_status st_polarization(st_ctx* c, double* d_out, int64_t capacity, int64_t* n_reports,
+                          void* stream) {
+  if (!c) return ST_EINVAL;
+  if (capacity < 0) return fail(c, ST_EINVAL, "negative capacity");
+  if (n_reports) *n_reports = c->n_reports;
+  if (!d_out || capacity == 0 || c->n_reports == 0) return ST_OK;
+  DeviceGuard g(c->device);
+  const int64_t k = std::min(capacity, c->n_reports);
+  hipError_t e = hipMemcpyAsync(d_out, c->d_pol, (size_t)k * 4 * sizeof(double),
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "copy polarization");
+  return ST_OK;
+}
+
+st_status st_read_particles(st_ctx* c, double* h_z, double* h_spin, int32_t* h_alive, void* stream) {
+  if (!c) return ST_EINVAL;
+  if (!c->have_particles) return fail(c, ST_ESTATE, "no particles bound");
+  if (c->n == 0) return ST_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (h_z && (e = hipMemcpyAsync(h_z, c->z, (size_t)c->n * 6 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "read z");
+  if (h_spin && (e = hipMemcpyAsync(h_spin, c->spin, (size_t)c->n * 3 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "read spin");
+  if (h_alive && (e = hipMemcpyAsync(h_alive, c->alive, (size_t)c->n * sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "read alive");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "synchronise");
+  return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Device math for the tracking kernels.
+//
+// FP64 transcendentals are multi-instruction sequences on CDNA, so the hot
+// path evaluates the few functions it needs as truncated Taylor series on
+// the small arguments the method produces, and falls back to the library
+// function on the rare lane whose argument leaves the range where the
+// truncation error stays below 2^-56 of the leading term.  Coefficients are
+// reciprocal factorials and binomial ratios generated at compile time.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace st {
+
+constexpr double inv_fact(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= (double)i;
+  return 1.0 / f;
+}
+
+// Taylor coefficient of x^(2n+1) in asin(x): C(2n, n) / (4^n (2n + 1)).
+constexpr double asin_coef(int n) {
+  double c = 1.0;                      // C(2n, n) / 4^n, built as a product
+  for (int i = 1; i <= n; ++i) c *= (double)(2 * i - 1) / (double)(2 * i);
+  return c / (double)(2 * n + 1);
+}
+
+template <int K> struct IF { static constexpr double v = inv_fact(K); };
+template <int K> struct AC { static constexpr double v = asin_coef(K); };
+
+// cos(x) and sin(x)/x as series in t = x², NT terms each (u = -t), or
+// cosh(x) and sinh(x)/x with u = +t.
+template <int NT, int N = NT - 1>
+struct Series {
+  __device__ __forceinline__ static void eval(double u, double& c, double& s) {
+    Series<NT, N - 1>::eval(u, c, s);
+    c = fma(c, u, IF<2 * (NT - 1 - N)>::v);
+    s = fma(s, u, IF<2 * (NT - 1 - N) + 1>::v);
+  }
+};
+template <int NT>
+struct Series<NT, 0> {
+  __device__ __forceinline__ static void eval(double u, double& c, double& s) {
+    c = IF<2 * (NT - 1)>::v;
+    s = IF<2 * (NT - 1) + 1>::v;
+  }
+};
+
+template <int NT>
+__device__ __forceinline__ void cos_sinc_series(double t, double& c, double& s) {
+  Series<NT>::eval(-t, c, s);
+}
+template <int NT>
+__device__ __forceinline__ void cosh_sinhc_series(double t, double& c, double& s) {
+  Series<NT>::eval(t, c, s);
+}
+
+// asin(x) for |x| <= kAsinPolyMax: 8 Taylor terms, truncation < 1e-23 |x|.
+constexpr double kAsinPolyMax = 0.05;
+template <int N = 7>
+struct AsinSeries {
+  __device__ __forceinline__ static double eval(double t) {
+    return fma(AsinSeries<N - 1>::eval(t), t, AC<7 - N>::v);
+  }
+};
+template <>
+struct AsinSeries<0> {
+  __device__ __forceinline__ static double eval(double) { return AC<7>::v; }
+};
+
+__device__ __forceinline__ double asin_small(double x) {
+  if (fabs(x) <= kAsinPolyMax) return x * AsinSeries<>::eval(x * x);
+  return asin(x);
+}
+
+// 1/x and 1/sqrt(x): hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double hx = 0.5 * x;
+  double e = fma(-hx * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-hx * y, y, 0.5);
+  return fma(y, e, y);
+}
+
+// Quaternion terms of a rotation by θ = |ω|, ω = f Ω: with y = (θ/2)²,
+// cos(θ/2) and sin(θ/2)/θ.  NT series terms cover y <= ymax.
+template <int NT>
+__device__ __forceinline__ void rot_half_angle(double y, double ymax, double& c, double& sfac) {
+  if (y <= ymax) {
+    double s;
+    cos_sinc_series<NT>(y, c, s);
+    sfac = 0.5 * s;
+  } else {
+    double h = sqrt(y);
+    double s;
+    sincos(h, &s, &c);
+    sfac = s / (2.0 * h);
+  }
+}
+
+}  // namespace st

@@ -1,0 +1,214 @@
+// Orbit maps, the T-BMT precession vector and quaternion algebra in double
+// precision, one lane per particle.
+//
+// The maps are the exact flows of §3 evaluated in forms that avoid
+// cancellation.  Pt is constant in every element of this model (no RF), so
+// every quantity that depends only on Pt is computed once per particle.
+#pragma once
+
+#include "device_math.h"
+#include "lattice_table.h"
+
+namespace st {
+
+struct Quat {
+  double w, x, y, z;
+};
+
+__device__ __forceinline__ Quat qident() { return {1.0, 0.0, 0.0, 0.0}; }
+
+// Hamilton product a ⊗ b (i j = k).
+__device__ __forceinline__ Quat qmul(const Quat& a, const Quat& b) {
+  Quat r;
+  r.w = a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z;
+  r.x = a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y;
+  r.y = a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x;
+  r.z = a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w;
+  return r;
+}
+
+// S <- q S q*: t = 2 v × S, S += w t + v × t.
+__device__ __forceinline__ void qrotate(const Quat& q, double& sx, double& sy, double& sz) {
+  double tx = 2.0 * (q.y * sz - q.z * sy);
+  double ty = 2.0 * (q.z * sx - q.x * sz);
+  double tz = 2.0 * (q.x * sy - q.y * sx);
+  sx += q.w * tx + (q.y * tz - q.z * ty);
+  sy += q.w * ty + (q.z * tx - q.x * tz);
+  sz += q.w * tz + (q.x * ty - q.y * tx);
+}
+
+// Quantities of one particle that depend on Pt only (eq. pt, eq. ps,
+// eq. quadSclP): P² = 1 + 2Pt/β0 + Pt², γ = γ0 (1 + β0 Pt), and the
+// T-BMT factors a1 = 1 + Gγ, a2 = G(γ - 1).
+struct Particle {
+  double Pt, P2, P, invP, invP2;
+  double c1;       // P² - (1 + β0 Pt)² = (2Pt/β0 + Pt²)/γ0²
+  double c2;       // 1 + β0 Pt
+  double c3;       // P² - 1 = 2Pt/β0 + Pt²
+  double ib;       // 1/β0 + Pt  (E / p0 c)
+  double invbeta;  // (1/β0 + Pt)/P = 1/β of the particle
+  double dib;      // 1/β - 1/β0
+  double a1, a2;
+};
+
+__device__ __forceinline__ Particle make_particle(double Pt, const TrackArgs& a) {
+  Particle p;
+  p.Pt = Pt;
+  p.c3 = Pt * fma(2.0, a.inv_beta0, Pt);
+  p.P2 = 1.0 + p.c3;
+  p.invP = rsqrt_nr(p.P2);
+  p.P = p.P2 * p.invP;
+  p.invP2 = p.invP * p.invP;
+  p.c1 = p.c3 * a.inv_gamma0_sq;
+  p.c2 = fma(a.beta0, Pt, 1.0);
+  p.ib = a.inv_beta0 + Pt;
+  p.invbeta = p.ib * p.invP;
+  p.dib = -p.c1 * a.inv_beta0 * p.invP * rcp_nr(p.c2 + p.P);
+  double gamma = a.gamma0 * p.c2;
+  p.a1 = fma(a.G, gamma, 1.0);
+  p.a2 = a.G * (gamma - 1.0);
+  return p;
+}
+
+// Exact drift of length L (flow of -Ps + Pt/β0).  The flight-time change
+// L/β0 - L(1/β0 + Pt)/Ps is evaluated as
+// L (c1 - Px² - Py²) / (β0 Ps (Ps + 1 + β0 Pt)), free of cancellation.
+__device__ __forceinline__ void drift(double L, double& X, double Px, double& Y, double Py,
+                                      double& T, const Particle& p, double inv_beta0) {
+  double pp = fma(Px, Px, Py * Py);
+  double ps2 = p.P2 - pp;
+  double r = rsqrt_nr(ps2);
+  double ps = ps2 * r;
+  X = fma(L * Px, r, X);
+  Y = fma(L * Py, r, Y);
+  T = fma(L * (p.c1 - pp) * r * inv_beta0, rcp_nr(ps + p.c2), T);
+}
+
+// Precession vector of eq. t-bmt.so for a field b = (bx, by, 0) without
+// curvature (quadrupoles, thin multipoles):
+// Ω = -(1/Ps) [a1 b - a2 (ũ·b)/P² ũ], ũ = (Px, Py, Ps).  r = 1/Ps.
+__device__ __forceinline__ void omega_straight(double bx, double by, double Px, double Py,
+                                               double r, const Particle& p,
+                                               double& ox, double& oy, double& oz) {
+  double k = p.a2 * fma(Px, bx, Py * by) * p.invP2;
+  ox = -r * fma(p.a1, bx, -k * Px);
+  oy = -r * fma(p.a1, by, -k * Py);
+  oz = k;
+}
+
+// Precession vector in a sector bend, b = (0, ηh, 0), with the frame term h ŷ.
+__device__ __forceinline__ void omega_bend(const DevElem& e, double X, double Px, double Py,
+                                           double r, const Particle& p,
+                                           double& ox, double& oy, double& oz) {
+  double w = fma(e.h, X, 1.0) * e.eta_h;
+  double g = w * r;
+  double a2py = p.a2 * Py * p.invP2;
+  ox = g * a2py * Px;
+  oy = fma(-g, fma(-a2py, Py, p.a1), e.h);
+  oz = w * a2py;
+}
+
+// One step of the exact sector bend over the slice length (§3.1 eq. sbend),
+// from the state (X, Px) with Ps = W0 to the next slice edge.  Pα² = P² - Py²
+// is passed in; W1 = sqrt(Pα² - Px(s)²) is returned through W0/r0 (it is Ps
+// at the new edge).  X(s) is evaluated as
+//   X cos(hs) + [(Px - Px(s))(Px + Px(s))/(W0 + W1) + (W0 - η)(1 - cos hs)
+//                + Px sin(hs)] / (η h),
+// and asin(Px/Pα) - asin(Px(s)/Pα) = asin((Px W1 - Px(s) W0)/Pα²), both
+// algebraically identical to the printed forms and free of cancellation.
+__device__ __forceinline__ void bend_step(const DevElem& e, double& X, double& Px, double Py,
+                                          double& Y, double& T, double& W0, double& r0,
+                                          double Pa2, double invPa2, double c3py,
+                                          const Particle& p) {
+  double w0me = (e.one_m_eta2 + c3py - Px * Px) * rcp_nr(W0 + e.eta);
+  double A = fma(-e.eta_h, X, w0me);
+  double px1 = fma(Px, e.cs, A * e.sn);
+  double ps2n = fma(-px1, px1, Pa2);
+  double r1 = rsqrt_nr(ps2n);
+  double W1 = ps2n * r1;
+  double bracket = fma((Px - px1) * (Px + px1), rcp_nr(W0 + W1), fma(w0me, e.omc, Px * e.sn));
+  double X1 = fma(X, e.cs, bracket * e.inv_eta_h);
+  double D = asin_small(fma(Px, W1, -px1 * W0) * invPa2);
+  Y = fma(Py, e.ds_eta, fma(Py * D, e.inv_eta_h, Y));
+  T = T - p.Pt * e.ds_eta - p.ib * D * e.inv_eta_h + e.tconst;
+  X = X1;
+  Px = px1;
+  W0 = W1;
+  r0 = r1;
+}
+
+// Matrix-kick quadrupole constants of one particle (§3.3 eq. quadL over
+// s = ds/2): κ² = |k1|/P; cos, sin(κs)/κ, κP sin(κs) and their hyperbolic
+// twins, all functions of (κs)² = |k1| s²/P.
+struct MKConst {
+  double cf, sf, kf;     // focusing plane:   cos κs, sin κs / κ, κ P sin κs
+  double cd, sd, kd;     // defocusing plane: cosh κs, sinh κs / κ, κ P sinh κs
+  double kap2;           // κ²
+  double A1, A2, A3, A4, A5;   // coefficients of the flight-time formula
+};
+
+__device__ __forceinline__ MKConst mk_const(const DevElem& e, const Particle& p) {
+  MKConst m;
+  double t = e.kabs_hds2 * p.invP;       // (κ s)²
+  double kabs = fabs(e.k1);
+  double C, Sc, Ch, Sh;
+  if (t <= 0.04) {
+    cos_sinc_series<7>(t, C, Sc);
+    cosh_sinhc_series<7>(t, Ch, Sh);
+  } else {
+    double x = sqrt(t);
+    double s, c;
+    sincos(x, &s, &c);
+    C = c; Sc = s / x;
+    Ch = cosh(x); Sh = sinh(x) / x;
+  }
+  double hs = e.hds;
+  m.cf = C;  m.sf = hs * Sc;  m.kf = kabs * hs * Sc;
+  m.cd = Ch; m.sd = hs * Sh;  m.kd = kabs * hs * Sh;
+  m.kap2 = kabs * p.invP;
+  m.A1 = 0.25 * hs;
+  m.A2 = 0.25 * m.sf * m.cf;
+  m.A3 = 0.25 * m.sd * m.cd;
+  m.A4 = 0.5 * m.kap2 * m.sf * m.sf;
+  m.A5 = 0.5 * m.kap2 * m.sd * m.sd;
+  return m;
+}
+
+// Linear part of the matrix-kick quadrupole over ds/2 in (focusing,
+// defocusing) coordinates.
+__device__ __forceinline__ void mk_linear(const MKConst& m, double& xf, double& pxf, double& yd,
+                                          double& pyd, double& T, const Particle& p) {
+  double px = pxf * p.invP, py = pyd * p.invP;
+  double x0 = xf, y0 = yd;
+  double k2x2 = m.kap2 * x0 * x0, k2y2 = m.kap2 * y0 * y0;
+  double brace = m.A1 * (px * px + py * py + k2x2 - k2y2)
+               + m.A2 * (px * px - k2x2)
+               + m.A3 * (py * py + k2y2)
+               - m.A4 * x0 * px
+               + m.A5 * y0 * py;
+  xf = fma(x0, m.cf, px * m.sf);
+  pxf = fma(pxf, m.cf, -x0 * m.kf);
+  yd = fma(y0, m.cd, py * m.sd);
+  pyd = fma(pyd, m.cd, y0 * m.kd);
+  T = fma(-p.invbeta, brace, T);
+}
+
+// Nonlinear "kick of positions" over ds (§3.3 eq. quadNL).  The flight-time
+// term is written as -ds/β [P/Ps - 1 - u/2] - ds (1/β - 1/β0) with
+// u = (Px² + Py²)/P² and P/Ps - 1 - u/2 = u²(2 + ρ)/(2ρ(1 + ρ)²), ρ = Ps/P.
+__device__ __forceinline__ void mk_nonlinear(double ds, double& X, double Px, double& Y,
+                                             double Py, double& T, const Particle& p) {
+  double pp = fma(Px, Px, Py * Py);
+  double ps2 = p.P2 - pp;
+  double r = rsqrt_nr(ps2);
+  double d = r - p.invP;
+  X = fma(ds * Px, d, X);
+  Y = fma(ds * Py, d, Y);
+  double u = pp * p.invP2;
+  double rho = ps2 * r * p.invP;
+  double opr = 1.0 + rho;
+  double g = u * u * (2.0 + rho) * (p.P * r) * 0.5 * rcp_nr(opr * opr);
+  T = T - ds * fma(p.invbeta, g, p.dib);
+}
+
+}  // namespace st

@@ -1,0 +1,282 @@
+// Persistent FP64 tracking kernel: one lane per particle, all turns and all
+// elements of the ring in one launch, state in registers.
+//
+// Per element (wave-uniform walk of the lattice index sequence):
+//   drift            exact flow, no spin
+//   sector bend      exact steps of ds between slice edges (§3.1)
+//   quadrupole       DKD or MK slices (§3.4, §3.3)
+//   thin multipole   half kick, rotation by the integrated Ω, half kick
+//   snake            fixed rotation
+// Thick elements with spin evaluate Ω at the N + 1 slice edges (§4.3) and
+// fold each edge into the running product of every Romberg level that keeps
+// it, so no Ω record ever leaves the registers.  The tableau and the
+// normalisation follow at the element exit, and the element quaternion is
+// composed into the turn quaternion, which rotates the spin once per turn.
+#include <hip/hip_runtime.h>
+
+#include "fp64_maps.h"
+#include "track_kernels.h"
+
+namespace st {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Romberg spin integration through one thick element, fused with its orbit
+// slices (KIND: 0 sector bend, 1 MK quadrupole, 2 DKD quadrupole).  Returns
+// the normalised element quaternion.
+template <int NT, int KIND>
+__device__ __forceinline__ Quat thick_element(const DevElem& e, double& X, double& Px, double& Y,
+                                              double& Py, double& T, const Particle& p,
+                                              const TrackArgs& a) {
+  const int N = e.nsl;
+  const int K = e.K;
+  Quat Q[kMaxRows];
+#pragma unroll
+  for (int m = 0; m < kMaxRows; ++m) Q[m] = qident();
+
+  // bend invariants of this particle: Py and Pt do not change in a bend
+  double Pa2 = p.P2 - Py * Py;
+  double invPa2 = 0.0, c3py = 0.0;
+  if (KIND == 0) {
+    invPa2 = rcp_nr(Pa2);
+    c3py = p.c3 - Py * Py;
+  }
+  MKConst mc;
+  if (KIND == 1) mc = mk_const(e, p);
+  const bool foc = e.k1 >= 0.0;
+
+  // Ps and 1/Ps at the entrance edge
+  double ps2 = fma(-Px, Px, Pa2);
+  double r = rsqrt_nr(ps2);
+  double W = ps2 * r;
+
+  for (int j = 0; j <= N; ++j) {
+    if (j > 0) {
+      if (KIND == 0) {
+        bend_step(e, X, Px, Py, Y, T, W, r, Pa2, invPa2, c3py, p);
+      } else {
+        if (KIND == 1) {
+          if (foc) mk_linear(mc, X, Px, Y, Py, T, p);
+          else     mk_linear(mc, Y, Py, X, Px, T, p);
+          mk_nonlinear(e.ds, X, Px, Y, Py, T, p);
+          if (foc) mk_linear(mc, X, Px, Y, Py, T, p);
+          else     mk_linear(mc, Y, Py, X, Px, T, p);
+        } else {
+          drift(e.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+          Px = fma(-e.k1ds, X, Px);
+          Py = fma(e.k1ds, Y, Py);
+          drift(e.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+        }
+        ps2 = p.P2 - fma(Px, Px, Py * Py);
+        r = rsqrt_nr(ps2);
+      }
+    }
+    double ox, oy, oz;
+    if (KIND == 0) omega_bend(e, X, Px, Py, r, p, ox, oy, oz);
+    else           omega_straight(e.k1 * Y, e.k1 * X, Px, Py, r, p, ox, oy, oz);
+    const double om2 = fma(ox, ox, fma(oy, oy, oz * oz));
+    const double w = (j == 0 || j == N) ? 0.5 : 1.0;
+#pragma unroll
+    for (int m = 0; m < kMaxRows; ++m) {
+      if (m <= K && (j & ((1 << m) - 1)) == 0) {
+        const double f = w * (double)(1 << m) * e.ds;
+        double c, sfac;
+        rot_half_angle<NT>(0.25 * f * f * om2, a.ymax, c, sfac);
+        const double g = sfac * f;
+        const Quat q = {c, g * ox, g * oy, g * oz};
+        Q[m] = qmul(q, Q[m]);
+      }
+    }
+  }
+
+  // Romberg tableau (§4.3 eq. romberg) with levels indexed by stride 2^m:
+  // V_j[m] = (4^j V_{j-1}[m] - V_{j-1}[m+1]) / (4^j - 1), limit V_K[0].
+  double four = 1.0;
+#pragma unroll
+  for (int jj = 1; jj < kMaxRows; ++jj) {
+    four *= 4.0;
+    if (jj <= K) {
+      const double inv = 1.0 / (four - 1.0);
+#pragma unroll
+      for (int m = 0; m < kMaxRows - 1; ++m) {
+        if (m <= K - jj) {
+          Q[m].w = (four * Q[m].w - Q[m + 1].w) * inv;
+          Q[m].x = (four * Q[m].x - Q[m + 1].x) * inv;
+          Q[m].y = (four * Q[m].y - Q[m + 1].y) * inv;
+          Q[m].z = (four * Q[m].z - Q[m + 1].z) * inv;
+        }
+      }
+    }
+  }
+  Quat q = Q[0];
+  const double inv = rsqrt_nr(fma(q.w, q.w, fma(q.x, q.x, fma(q.y, q.y, q.z * q.z))));
+  q.w *= inv; q.x *= inv; q.y *= inv; q.z *= inv;
+  return q;
+}
+
+template <int NT>
+__device__ __forceinline__ Quat thin_element(const DevElem& e, double X, double& Px, double Y,
+                                             double& Py, const Particle& p, const TrackArgs& a) {
+  const double hk1 = 0.5 * e.k1l, hk2 = 0.5 * e.k2l;
+  Px -= fma(hk1, X, 0.5 * hk2 * (X * X - Y * Y));
+  Py += fma(hk1, Y, hk2 * X * Y);
+  double ps2 = p.P2 - fma(Px, Px, Py * Py);
+  double r = rsqrt_nr(ps2);
+  double bx = fma(e.k2l * X, Y, e.k1l * Y);
+  double by = fma(e.k1l, X, 0.5 * e.k2l * (X * X - Y * Y));
+  double ox, oy, oz;
+  omega_straight(bx, by, Px, Py, r, p, ox, oy, oz);
+  double c, sfac;
+  rot_half_angle<NT>(0.25 * fma(ox, ox, fma(oy, oy, oz * oz)), a.ymax, c, sfac);
+  Px -= fma(hk1, X, 0.5 * hk2 * (X * X - Y * Y));
+  Py += fma(hk1, Y, hk2 * X * Y);
+  return {c, sfac * ox, sfac * oy, sfac * oz};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) track_fp64_kernel(const TrackArgs a) {
+  __shared__ double red[kBlock / 64][4];
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = j < a.n;
+  int32_t status = valid ? a.alive[j] : 0;
+  bool live = status == 1;
+  const int64_t n = a.n;
+
+  double X = 0, Px = 0, Y = 0, Py = 0, T = 0, Pt = 0, sx = 0, sy = 0, sz = 0;
+  if (valid) {
+    X = a.z[j]; Px = a.z[n + j]; Y = a.z[2 * n + j]; Py = a.z[3 * n + j];
+    T = a.z[4 * n + j]; Pt = a.z[5 * n + j];
+    sx = a.spin[j]; sy = a.spin[n + j]; sz = a.spin[2 * n + j];
+  }
+  const Particle p = make_particle(Pt, a);
+  Quat qturn = qident();
+
+  for (int t = 1; t <= a.turns; ++t) {
+    const bool was_live = live;
+    if (was_live) qturn = qident();
+    for (int ie = 0; ie < a.n_elems; ++ie) {
+      const DevElem& e = a.tab[a.seq[ie]];
+      if (!live) continue;
+      const double X0 = X, Px0 = Px, Y0 = Y, Py0 = Py, T0 = T;
+      Quat q;
+      bool spin = true;
+      switch (e.kind) {
+        case K_DRIFT:
+          drift(e.L, X, Px, Y, Py, T, p, a.inv_beta0);
+          spin = false;
+          break;
+        case K_SBEND:
+          q = thick_element<NT, 0>(e, X, Px, Y, Py, T, p, a);
+          break;
+        case K_QUAD:
+          if (e.orbit == M_MK) q = thick_element<NT, 1>(e, X, Px, Y, Py, T, p, a);
+          else                 q = thick_element<NT, 2>(e, X, Px, Y, Py, T, p, a);
+          break;
+        case K_THIN:
+          q = thin_element<NT>(e, X, Px, Y, Py, p, a);
+          break;
+        case K_SNAKE:
+          q = {e.qw, e.qx, e.qy, e.qz};
+          break;
+        default:
+          spin = false;
+          break;
+      }
+      const bool ok = fabs(X) <= a.aperture && fabs(Y) <= a.aperture && isfinite(Px) &&
+                      isfinite(Py) && isfinite(T);
+      if (!ok) {
+        X = X0; Px = Px0; Y = Y0; Py = Py0; T = T0;
+        live = false;
+        status = -(1 + ie);
+        continue;
+      }
+      if (spin) qturn = qmul(q, qturn);
+    }
+    // A particle lost during this turn still receives the rotation of the
+    // elements it completed before the loss.
+    if (was_live) qrotate(qturn, sx, sy, sz);
+    if (a.report_every > 0 && t % a.report_every == 0) {
+      double v0 = live ? sx : 0.0, v1 = live ? sy : 0.0, v2 = live ? sz : 0.0;
+      double v3 = live ? 1.0 : 0.0;
+      v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2); v3 = wave_sum(v3);
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      if (lane == 0) { red[wv][0] = v0; red[wv][1] = v1; red[wv][2] = v2; red[wv][3] = v3; }
+      __syncthreads();
+      if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int k = 0; k < kBlock / 64; ++k) s += red[k][threadIdx.x];
+        const int rep = t / a.report_every - 1;
+        a.partials[((int64_t)rep * a.n_blocks + blockIdx.x) * 4 + threadIdx.x] = s;
+      }
+      __syncthreads();
+    }
+  }
+
+  if (valid && a.alive[j] == 1) {
+    a.z[j] = X; a.z[n + j] = Px; a.z[2 * n + j] = Y; a.z[3 * n + j] = Py; a.z[4 * n + j] = T;
+    a.spin[j] = sx; a.spin[n + j] = sy; a.spin[2 * n + j] = sz;
+    a.alive[j] = status;
+    if (a.qout) {
+      a.qout[j] = qturn.w; a.qout[n + j] = qturn.x; a.qout[2 * n + j] = qturn.y;
+      a.qout[3 * n + j] = qturn.z;
+    }
+  }
+}
+
+// Deterministic second pass of the polarization reduction: one block per
+// report sums the per-block partials in a fixed order.
+__global__ void __launch_bounds__(256) reduce_polarization_kernel(const double* partials,
+                                                                  int n_blocks, double* out) {
+  __shared__ double acc[256][4];
+  const int rep = blockIdx.x;
+  double s[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < n_blocks; b += 256)
+    for (int c = 0; c < 4; ++c) s[c] += partials[((int64_t)rep * n_blocks + b) * 4 + c];
+  for (int c = 0; c < 4; ++c) acc[threadIdx.x][c] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 4; ++c) acc[threadIdx.x][c] += acc[threadIdx.x + w][c];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nal = acc[0][3];
+    const double inv = nal > 0 ? 1.0 / nal : 0.0;
+    out[rep * 4 + 0] = acc[0][0] * inv;
+    out[rep * 4 + 1] = acc[0][1] * inv;
+    out[rep * 4 + 2] = acc[0][2] * inv;
+    out[rep * 4 + 3] = nal;
+  }
+}
+
+}  // namespace
+
+int track_block_size() { return kBlock; }
+
+hipError_t launch_track_fp64(const TrackArgs& a, int nt, hipStream_t stream) {
+  const dim3 grid((unsigned)a.n_blocks), block(kBlock);
+  switch (nt) {
+    case 8:  hipLaunchKernelGGL(track_fp64_kernel<8>, grid, block, 0, stream, a); break;
+    case 12: hipLaunchKernelGGL(track_fp64_kernel<12>, grid, block, 0, stream, a); break;
+    default: hipLaunchKernelGGL(track_fp64_kernel<16>, grid, block, 0, stream, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_polarization(const double* partials, int n_blocks, int n_reports,
+                                      double* out, hipStream_t stream) {
+  if (n_reports <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_polarization_kernel, dim3(n_reports), dim3(256), 0, stream, partials,
+                     n_blocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace st

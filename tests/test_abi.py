@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports every symbol its header declares; the
+ctypes mirrors of its structs match the header; calls that must fail before
+touching a device do so.  CPU only: no compute calls."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spintrack.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:st_status|const char\*)\s+(st_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    assert names == sorted(["st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
+                            "st_bind_quaternions", "st_track", "st_polarization",
+                            "st_read_particles", "st_last_error"])
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1501_03450_amd import binding
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(binding.EXPORTS) == set(declared_functions())
+
+
+def test_struct_layouts_match_the_header():
+    from paper_1501_03450_amd import binding
+    # st_element: 4 int32 then 8 doubles; st_beam: 3 doubles then 2 int32
+    assert ctypes.sizeof(binding.st_element) == 4 * 4 + 8 * 8
+    assert binding.st_element.L.offset == 16
+    assert ctypes.sizeof(binding.st_beam) == 3 * 8 + 2 * 4
+    text = open(HEADER).read()
+    assert "int32_t kind, orbit, n_slices, romberg_rows;" in text
+    assert "double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu;" in text
+    assert "double G, gamma0, aperture;" in text
+    assert "int32_t precision, report_every;" in text
+
+
+def test_null_context_and_bad_device_are_rejected_without_device_work():
+    from paper_1501_03450_amd import binding as B
+    lib = B.LIB
+    assert lib.st_track(None, 1, None) == B.ST_EINVAL
+    assert lib.st_load_lattice(None, None, 0, None) == B.ST_EINVAL
+    assert lib.st_bind_particles(None, 0, None, None, None) == B.ST_EINVAL
+    assert lib.st_polarization(None, None, 0, None, None) == B.ST_EINVAL
+    assert lib.st_read_particles(None, None, None, None, None) == B.ST_EINVAL
+    assert lib.st_destroy(None) == B.ST_OK
+    assert B.st_last_error(None) == "null context"
+    with pytest.raises(B.SpinTrackError):
+        B.st_create(-1)
+
+
+def test_element_marshalling_follows_the_workload_records():
+    from paper_1501_03450_amd import binding as B
+    from workloads import rhic_like_ring
+    ring = rhic_like_ring()
+    arr = B.element_array(ring)
+    kinds = [arr[i].kind for i in range(len(ring))]
+    assert kinds.count(B.ST_SBEND) == 264 and kinds.count(B.ST_QUAD) == 456
+    assert kinds.count(B.ST_THIN) == 132 and kinds.count(B.ST_SNAKE) == 2
+    assert all(arr[i].orbit == B.ST_ORB_MK for i in range(len(ring)) if arr[i].kind == B.ST_QUAD)
