@@ -13,7 +13,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libspintrack.so")
+# SPINTRACK_LIB selects another build of the same library (e.g. a different
+# occupancy target); the default is the in-tree build.
+LIB_PATH = os.environ.get("SPINTRACK_LIB", os.path.join(_HERE, "libspintrack.so"))
 
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDEVICE, ST_ESTATE = 0, -1, -2, -3, -4
 ST_MARKER, ST_DRIFT, ST_SBEND, ST_QUAD, ST_THIN, ST_SNAKE = range(6)

@@ -24,7 +24,7 @@ struct st_ctx {
   int nt = 16;             // quaternion series terms
   double ymax = 0.0;
   st::DevElem* d_tab = nullptr;
-  uint16_t* d_seq = nullptr;
+  uint32_t* d_seq = nullptr;
   // particles
   int64_t n = 0;
   double* z = nullptr;
@@ -112,62 +112,63 @@ std::string validate(const st_element& e, int64_t i) {
   return std::string();
 }
 
-st::DevElem derive(const st_element& e, const st_beam& b, double beta0) {
+st::DevElem derive(const st_element& e, double beta0) {
   st::DevElem d;
   std::memset(&d, 0, sizeof(d));
   d.kind = e.kind;
   d.orbit = e.orbit;
-  d.L = e.L;
   d.nsl = 1;
   d.K = 0;
   if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
     d.nsl = e.n_slices;
     const int re = std::min(e.romberg_rows, 1 + v2(e.n_slices));
     d.K = re - 1;
-    d.ds = e.L / e.n_slices;
-    d.hds = 0.5 * d.ds;
   }
   if (e.kind == ST_SBEND) {
-    d.h = e.angle / e.L;
-    d.eta = e.eta;
-    d.eta_h = e.eta * d.h;
-    d.inv_eta_h = 1.0 / (e.eta * d.h);
-    d.cs = std::cos(d.h * d.ds);
-    d.sn = std::sin(d.h * d.ds);
-    const double s2 = std::sin(0.5 * d.h * d.ds);
-    d.omc = 2.0 * s2 * s2;
-    d.one_m_eta2 = (1.0 - e.eta) * (1.0 + e.eta);
-    d.ds_eta = d.ds / e.eta;
-    d.tconst = (1.0 - 1.0 / e.eta) * d.ds / beta0;
+    st::BendParams& b = d.b;
+    b.ds = e.L / e.n_slices;
+    b.h = e.angle / e.L;
+    b.eta = e.eta;
+    b.eta_h = e.eta * b.h;
+    b.inv_eta_h = 1.0 / (e.eta * b.h);
+    b.cs = std::cos(b.h * b.ds);
+    b.sn = std::sin(b.h * b.ds);
+    const double s2 = std::sin(0.5 * b.h * b.ds);
+    b.omc = 2.0 * s2 * s2;
+    b.one_m_eta2 = (1.0 - e.eta) * (1.0 + e.eta);
+    b.ds_eta = b.ds / e.eta;
+    b.tconst = (1.0 - 1.0 / e.eta) * b.ds / beta0;
   } else if (e.kind == ST_QUAD) {
-    d.k1 = e.k1;
-    d.k1ds = e.k1 * d.ds;
-    d.kabs_hds2 = std::fabs(e.k1) * d.hds * d.hds;
+    st::QuadParams& q = d.q;
+    q.ds = e.L / e.n_slices;
+    q.hds = 0.5 * q.ds;
+    q.k1 = e.k1;
+    q.k1ds = e.k1 * q.ds;
+    q.kabs_hds2 = std::fabs(e.k1) * q.hds * q.hds;
+  } else if (e.kind == ST_DRIFT) {
+    d.d.L = e.L;
   } else if (e.kind == ST_THIN) {
-    d.k1l = e.k1l;
-    d.k2l = e.k2l;
+    d.t.k1l = e.k1l;
+    d.t.k2l = e.k2l;
   } else if (e.kind == ST_SNAKE) {
     const double hp = 0.5 * e.snake_phi;
-    d.qw = std::cos(hp);
-    d.qx = std::sin(hp) * std::sin(e.snake_mu);
-    d.qy = 0.0;
-    d.qz = std::sin(hp) * std::cos(e.snake_mu);
+    d.s.qw = std::cos(hp);
+    d.s.qx = std::sin(hp) * std::sin(e.snake_mu);
+    d.s.qy = 0.0;
+    d.s.qz = std::sin(hp) * std::cos(e.snake_mu);
   }
-  (void)b;
   return d;
 }
 
-// Largest rotation angle a design-amplitude particle meets in one
-// quaternion build of this element (used to size the series).
+// Largest rotation angle a design-amplitude particle meets in one series
+// evaluation of this element: the finest Romberg level, w ds |Ω| with w = 1
+// at interior edges (coarser levels are obtained by squaring).
 double design_angle(const st_element& e, const st_beam& b) {
   const double a1 = 1.0 + b.G * b.gamma0;
   const double r_ref = 0.02;
   if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
-    const int N = e.n_slices;
-    const int K = std::min(e.romberg_rows, 1 + v2(N)) - 1;
-    const double ds = e.L / N;
-    const int stride = 1 << K;
-    const double f = stride < N ? stride * ds : 0.5 * stride * ds;
+    const double ds = e.L / e.n_slices;
+    const double f = e.n_slices > 1 ? ds : 0.5 * ds;
     double om;
     if (e.kind == ST_SBEND) {
       const double h = e.angle / e.L;
@@ -233,7 +234,7 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
 
   // compress: unique elements + index sequence
   std::vector<st_element> uniq;
-  std::vector<uint16_t> seq((size_t)n);
+  std::vector<uint32_t> seq((size_t)n);
   double theta = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     int k = -1;
@@ -244,11 +245,11 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
       uniq.push_back(els[i]);
       k = (int)uniq.size() - 1;
     }
-    seq[(size_t)i] = (uint16_t)k;
+    seq[(size_t)i] = (uint32_t)k;
     theta = std::max(theta, design_angle(els[i], *b));
   }
   std::vector<st::DevElem> tab(std::max<size_t>(uniq.size(), 1));
-  for (size_t u = 0; u < uniq.size(); ++u) tab[u] = derive(uniq[u], *b, beta0);
+  for (size_t u = 0; u < uniq.size(); ++u) tab[u] = derive(uniq[u], beta0);
 
   DeviceGuard g(c->device);
   if (c->d_tab) { (void)hipFree(c->d_tab); c->d_tab = nullptr; }
@@ -257,17 +258,17 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   hipError_t e;
   if ((e = hipMalloc(&c->d_tab, tab.size() * sizeof(st::DevElem))) != hipSuccess)
     return fail(c, ST_ENOMEM, std::string("lattice table: ") + hipGetErrorString(e));
-  if ((e = hipMalloc(&c->d_seq, std::max<size_t>(seq.size(), 1) * sizeof(uint16_t))) != hipSuccess)
+  if ((e = hipMalloc(&c->d_seq, std::max<size_t>(seq.size(), 1) * sizeof(uint32_t))) != hipSuccess)
     return fail(c, ST_ENOMEM, std::string("lattice sequence: ") + hipGetErrorString(e));
   if ((e = hipMemcpy(c->d_tab, tab.data(), tab.size() * sizeof(st::DevElem), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(c, e, "upload lattice table");
-  if (n > 0 && (e = hipMemcpy(c->d_seq, seq.data(), seq.size() * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess)
+  if (n > 0 && (e = hipMemcpy(c->d_seq, seq.data(), seq.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(c, e, "upload lattice sequence");
 
   // series terms: cover the design angles with 10% margin; lanes beyond use sincos
   const double y = 1.21 * 0.25 * theta * theta;
   c->nt = 16;
-  for (int nt : {8, 12, 16})
+  for (int nt : {6, 8, 12, 16})
     if (series_ymax(nt) >= y) { c->nt = nt; break; }
   c->ymax = series_ymax(c->nt);
   c->beam = *b;

@@ -68,9 +68,37 @@ struct AsinSeries<0> {
   __device__ __forceinline__ static double eval(double) { return AC<7>::v; }
 };
 
+// Beyond the series range the argument is reduced by halving, which keeps
+// every lane on the same inline code (no calls, so no registers are spilled
+// around them): with t = x², evaluate the series at t/4^k and apply the
+// double-angle identities k times,
+//   cos 2x = cos² x - t sinc² x,   sinc 2x = sinc x · cos x,
+//   cosh 2x = cosh² x + t sinhc² x, sinhc 2x = sinhc x · cosh x.
+// Non-finite or negative t gives NaN.
+template <int NT, bool HYP>
+__device__ __forceinline__ void halving_series(double t, double tmax, double& c, double& s) {
+  int k = 0;
+  while (t > tmax && k < 64) { t *= 0.25; ++k; }
+  if (!(t <= tmax)) { c = s = __builtin_nan(""); return; }
+  Series<NT>::eval(HYP ? t : -t, c, s);
+  for (int i = 0; i < k; ++i) {
+    const double c2 = HYP ? fma(t * s, s, c * c) : fma(-t * s, s, c * c);
+    s = s * c;
+    c = c2;
+    t *= 4.0;
+  }
+}
+
+// asin x = 2 asin(x / (sqrt 2 · sqrt(1 + sqrt(1 - x²)))) halves the argument.
 __device__ __forceinline__ double asin_small(double x) {
-  if (fabs(x) <= kAsinPolyMax) return x * AsinSeries<>::eval(x * x);
-  return asin(x);
+  double scale = 1.0;
+  int k = 0;
+  while (!(fabs(x) <= kAsinPolyMax) && k < 8) {
+    x = x * rsqrt(2.0 * (1.0 + sqrt(1.0 - x * x)));
+    scale *= 2.0;
+    ++k;
+  }
+  return scale * (x * AsinSeries<>::eval(x * x));
 }
 
 // 1/x and 1/sqrt(x): hardware estimate refined by two Newton steps.
@@ -95,16 +123,13 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // cos(θ/2) and sin(θ/2)/θ.  NT series terms cover y <= ymax.
 template <int NT>
 __device__ __forceinline__ void rot_half_angle(double y, double ymax, double& c, double& sfac) {
+  double s;
   if (y <= ymax) {
-    double s;
     cos_sinc_series<NT>(y, c, s);
-    sfac = 0.5 * s;
   } else {
-    double h = sqrt(y);
-    double s;
-    sincos(h, &s, &c);
-    sfac = s / (2.0 * h);
+    halving_series<NT, false>(y, ymax, c, s);
   }
+  sfac = 0.5 * s;
 }
 
 }  // namespace st

@@ -27,6 +27,20 @@ __device__ __forceinline__ Quat qmul(const Quat& a, const Quat& b) {
   return r;
 }
 
+// q ⊗ q for a rotation quaternion: the rotation about the same axis by
+// twice the angle, (w² - |v|², 2 w v).
+__device__ __forceinline__ Quat qsquare(const Quat& q) {
+  const double tw = 2.0 * q.w;
+  return {fma(q.w, q.w, -fma(q.x, q.x, fma(q.y, q.y, q.z * q.z))), tw * q.x, tw * q.y, tw * q.z};
+}
+
+// One Romberg step on quaternions: (c A - B) / (c - 1).
+__device__ __forceinline__ Quat qextrapolate(const Quat& A, const Quat& B, double c) {
+  const double inv = 1.0 / (c - 1.0);
+  return {fma(c, A.w, -B.w) * inv, fma(c, A.x, -B.x) * inv, fma(c, A.y, -B.y) * inv,
+          fma(c, A.z, -B.z) * inv};
+}
+
 // S <- q S q*: t = 2 v × S, S += w t + v × t.
 __device__ __forceinline__ void qrotate(const Quat& q, double& sx, double& sy, double& sz) {
   double tx = 2.0 * (q.y * sz - q.z * sy);
@@ -38,35 +52,41 @@ __device__ __forceinline__ void qrotate(const Quat& q, double& sx, double& sy, d
 }
 
 // Quantities of one particle that depend on Pt only (eq. pt, eq. ps,
-// eq. quadSclP): P² = 1 + 2Pt/β0 + Pt², γ = γ0 (1 + β0 Pt), and the
-// T-BMT factors a1 = 1 + Gγ, a2 = G(γ - 1).
+// eq. quadSclP): P² = 1 + 2Pt/β0 + Pt², γ = γ0 (1 + β0 Pt), and the T-BMT
+// factors a1 = 1 + Gγ, a2 = G(γ - 1).  Four values stay in registers; the
+// others cost one instruction each where they are used, which keeps the
+// register footprint of the persistent loop small.
 struct Particle {
-  double Pt, P2, P, invP, invP2;
-  double c1;       // P² - (1 + β0 Pt)² = (2Pt/β0 + Pt²)/γ0²
-  double c2;       // 1 + β0 Pt
-  double c3;       // P² - 1 = 2Pt/β0 + Pt²
-  double ib;       // 1/β0 + Pt  (E / p0 c)
-  double invbeta;  // (1/β0 + Pt)/P = 1/β of the particle
+  double Pt;
+  double c3;       // P² - 1 = 2Pt/β0 + Pt², kept exactly (P² itself rounds it)
+  double invP;
   double dib;      // 1/β - 1/β0
-  double a1, a2;
+  // beam constants (kernel arguments, uniform)
+  double ib0, beta0, ig2, Gg0b0, a1_0, a2_0;
+
+  __device__ __forceinline__ double P2() const { return 1.0 + c3; }
+  __device__ __forceinline__ double P() const { return (1.0 + c3) * invP; }
+  __device__ __forceinline__ double invP2() const { return invP * invP; }
+  __device__ __forceinline__ double c1() const { return c3 * ig2; }           // P² - (1 + β0 Pt)²
+  __device__ __forceinline__ double c2() const { return fma(beta0, Pt, 1.0); }  // 1 + β0 Pt
+  __device__ __forceinline__ double ib() const { return ib0 + Pt; }           // 1/β0 + Pt
+  __device__ __forceinline__ double invbeta() const { return (ib0 + Pt) * invP; }
+  __device__ __forceinline__ double a1() const { return fma(Gg0b0, Pt, a1_0); }  // 1 + Gγ
+  __device__ __forceinline__ double a2() const { return fma(Gg0b0, Pt, a2_0); }  // G(γ - 1)
 };
 
 __device__ __forceinline__ Particle make_particle(double Pt, const TrackArgs& a) {
   Particle p;
   p.Pt = Pt;
+  p.ib0 = a.inv_beta0;
+  p.beta0 = a.beta0;
+  p.ig2 = a.inv_gamma0_sq;
+  p.Gg0b0 = a.G * a.gamma0 * a.beta0;
+  p.a1_0 = fma(a.G, a.gamma0, 1.0);
+  p.a2_0 = a.G * (a.gamma0 - 1.0);
   p.c3 = Pt * fma(2.0, a.inv_beta0, Pt);
-  p.P2 = 1.0 + p.c3;
-  p.invP = rsqrt_nr(p.P2);
-  p.P = p.P2 * p.invP;
-  p.invP2 = p.invP * p.invP;
-  p.c1 = p.c3 * a.inv_gamma0_sq;
-  p.c2 = fma(a.beta0, Pt, 1.0);
-  p.ib = a.inv_beta0 + Pt;
-  p.invbeta = p.ib * p.invP;
-  p.dib = -p.c1 * a.inv_beta0 * p.invP * rcp_nr(p.c2 + p.P);
-  double gamma = a.gamma0 * p.c2;
-  p.a1 = fma(a.G, gamma, 1.0);
-  p.a2 = a.G * (gamma - 1.0);
+  p.invP = rsqrt_nr(p.P2());
+  p.dib = -p.c1() * a.inv_beta0 * p.invP * rcp_nr(p.c2() + p.P());
   return p;
 }
 
@@ -76,12 +96,12 @@ __device__ __forceinline__ Particle make_particle(double Pt, const TrackArgs& a)
 __device__ __forceinline__ void drift(double L, double& X, double Px, double& Y, double Py,
                                       double& T, const Particle& p, double inv_beta0) {
   double pp = fma(Px, Px, Py * Py);
-  double ps2 = p.P2 - pp;
+  double ps2 = p.P2() - pp;
   double r = rsqrt_nr(ps2);
   double ps = ps2 * r;
   X = fma(L * Px, r, X);
   Y = fma(L * Py, r, Y);
-  T = fma(L * (p.c1 - pp) * r * inv_beta0, rcp_nr(ps + p.c2), T);
+  T = fma(L * (p.c1() - pp) * r * inv_beta0, rcp_nr(ps + p.c2()), T);
 }
 
 // Precession vector of eq. t-bmt.so for a field b = (bx, by, 0) without
@@ -90,47 +110,49 @@ __device__ __forceinline__ void drift(double L, double& X, double Px, double& Y,
 __device__ __forceinline__ void omega_straight(double bx, double by, double Px, double Py,
                                                double r, const Particle& p,
                                                double& ox, double& oy, double& oz) {
-  double k = p.a2 * fma(Px, bx, Py * by) * p.invP2;
-  ox = -r * fma(p.a1, bx, -k * Px);
-  oy = -r * fma(p.a1, by, -k * Py);
+  const double a1 = p.a1();
+  double k = p.a2() * fma(Px, bx, Py * by) * p.invP2();
+  ox = -r * fma(a1, bx, -k * Px);
+  oy = -r * fma(a1, by, -k * Py);
   oz = k;
 }
 
 // Precession vector in a sector bend, b = (0, ηh, 0), with the frame term h ŷ.
-__device__ __forceinline__ void omega_bend(const DevElem& e, double X, double Px, double Py,
+__device__ __forceinline__ void omega_bend(const BendParams& e, double X, double Px, double Py,
                                            double r, const Particle& p,
                                            double& ox, double& oy, double& oz) {
   double w = fma(e.h, X, 1.0) * e.eta_h;
   double g = w * r;
-  double a2py = p.a2 * Py * p.invP2;
+  double a2py = p.a2() * Py * p.invP2();
   ox = g * a2py * Px;
-  oy = fma(-g, fma(-a2py, Py, p.a1), e.h);
+  oy = fma(-g, fma(-a2py, Py, p.a1()), e.h);
   oz = w * a2py;
 }
 
 // One step of the exact sector bend over the slice length (§3.1 eq. sbend),
 // from the state (X, Px) with Ps = W0 to the next slice edge.  Pα² = P² - Py²
 // is passed in; W1 = sqrt(Pα² - Px(s)²) is returned through W0/r0 (it is Ps
-// at the new edge).  X(s) is evaluated as
-//   X cos(hs) + [(Px - Px(s))(Px + Px(s))/(W0 + W1) + (W0 - η)(1 - cos hs)
-//                + Px sin(hs)] / (η h),
-// and asin(Px/Pα) - asin(Px(s)/Pα) = asin((Px W1 - Px(s) W0)/Pα²), both
+// at the new edge) and wme = W - η is carried from edge to edge.  X(s) is
+// evaluated as
+//   X cos(hs) + [(W1 - W0) + (W0 - η)(1 - cos hs) + Px sin(hs)] / (η h),
+// with W1 - W0 = (Px - Px(s))(Px + Px(s))/(W0 + W1), and
+// asin(Px/Pα) - asin(Px(s)/Pα) = asin((Px W1 - Px(s) W0)/Pα²): both
 // algebraically identical to the printed forms and free of cancellation.
-__device__ __forceinline__ void bend_step(const DevElem& e, double& X, double& Px, double Py,
+__device__ __forceinline__ void bend_step(const BendParams& e, double& X, double& Px, double Py,
                                           double& Y, double& T, double& W0, double& r0,
-                                          double Pa2, double invPa2, double c3py,
+                                          double& wme, double Pa2, double invPa2,
                                           const Particle& p) {
-  double w0me = (e.one_m_eta2 + c3py - Px * Px) * rcp_nr(W0 + e.eta);
-  double A = fma(-e.eta_h, X, w0me);
+  double A = fma(-e.eta_h, X, wme);
   double px1 = fma(Px, e.cs, A * e.sn);
   double ps2n = fma(-px1, px1, Pa2);
   double r1 = rsqrt_nr(ps2n);
   double W1 = ps2n * r1;
-  double bracket = fma((Px - px1) * (Px + px1), rcp_nr(W0 + W1), fma(w0me, e.omc, Px * e.sn));
-  double X1 = fma(X, e.cs, bracket * e.inv_eta_h);
+  double dW = (Px - px1) * (Px + px1) * rcp_nr(W0 + W1);
+  double X1 = fma(X, e.cs, fma(wme, e.omc, fma(Px, e.sn, dW)) * e.inv_eta_h);
   double D = asin_small(fma(Px, W1, -px1 * W0) * invPa2);
   Y = fma(Py, e.ds_eta, fma(Py * D, e.inv_eta_h, Y));
-  T = T - p.Pt * e.ds_eta - p.ib * D * e.inv_eta_h + e.tconst;
+  T = T - p.Pt * e.ds_eta - p.ib() * D * e.inv_eta_h + e.tconst;
+  wme += dW;
   X = X1;
   Px = px1;
   W0 = W1;
@@ -147,7 +169,7 @@ struct MKConst {
   double A1, A2, A3, A4, A5;   // coefficients of the flight-time formula
 };
 
-__device__ __forceinline__ MKConst mk_const(const DevElem& e, const Particle& p) {
+__device__ __forceinline__ MKConst mk_const(const QuadParams& e, const Particle& p) {
   MKConst m;
   double t = e.kabs_hds2 * p.invP;       // (κ s)²
   double kabs = fabs(e.k1);
@@ -156,11 +178,8 @@ __device__ __forceinline__ MKConst mk_const(const DevElem& e, const Particle& p)
     cos_sinc_series<7>(t, C, Sc);
     cosh_sinhc_series<7>(t, Ch, Sh);
   } else {
-    double x = sqrt(t);
-    double s, c;
-    sincos(x, &s, &c);
-    C = c; Sc = s / x;
-    Ch = cosh(x); Sh = sinh(x) / x;
+    halving_series<7, false>(t, 0.04, C, Sc);
+    halving_series<7, true>(t, 0.04, Ch, Sh);
   }
   double hs = e.hds;
   m.cf = C;  m.sf = hs * Sc;  m.kf = kabs * hs * Sc;
@@ -190,7 +209,7 @@ __device__ __forceinline__ void mk_linear(const MKConst& m, double& xf, double& 
   pxf = fma(pxf, m.cf, -x0 * m.kf);
   yd = fma(y0, m.cd, py * m.sd);
   pyd = fma(pyd, m.cd, y0 * m.kd);
-  T = fma(-p.invbeta, brace, T);
+  T = fma(-p.invbeta(), brace, T);
 }
 
 // Nonlinear "kick of positions" over ds (§3.3 eq. quadNL).  The flight-time
@@ -199,16 +218,16 @@ __device__ __forceinline__ void mk_linear(const MKConst& m, double& xf, double& 
 __device__ __forceinline__ void mk_nonlinear(double ds, double& X, double Px, double& Y,
                                              double Py, double& T, const Particle& p) {
   double pp = fma(Px, Px, Py * Py);
-  double ps2 = p.P2 - pp;
+  double ps2 = p.P2() - pp;
   double r = rsqrt_nr(ps2);
   double d = r - p.invP;
   X = fma(ds * Px, d, X);
   Y = fma(ds * Py, d, Y);
-  double u = pp * p.invP2;
+  double u = pp * p.invP2();
   double rho = ps2 * r * p.invP;
   double opr = 1.0 + rho;
-  double g = u * u * (2.0 + rho) * (p.P * r) * 0.5 * rcp_nr(opr * opr);
-  T = T - ds * fma(p.invbeta, g, p.dib);
+  double g = u * u * (2.0 + rho) * (p.P() * r) * 0.5 * rcp_nr(opr * opr);
+  T = T - ds * fma(p.invbeta(), g, p.dib);
 }
 
 }  // namespace st

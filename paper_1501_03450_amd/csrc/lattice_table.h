@@ -4,7 +4,7 @@
 // A ring of ~1.7k elements repeats a handful of distinct magnets, so the
 // lattice is stored as a small table of unique elements with every per-element
 // constant precomputed on the host (trigonometry of the bend angle per slice,
-// reciprocals, snake quaternions), plus a 16-bit index sequence.  The kernels
+// reciprocals, snake quaternions), plus a 32-bit index sequence.  The kernels
 // walk the sequence with wave-uniform loads, so the table is read through the
 // scalar cache and every branch on the element kind is uniform.
 #pragma once
@@ -18,22 +18,36 @@ enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2 };
 
 constexpr int kMaxRows = 4;   // Romberg tableau rows supported by the kernels
 
+// Per-kind parameters, precomputed on the host.
+struct BendParams {        // sector bend (§3.1)
+  double ds;               // slice length L/N
+  double h, eta, eta_h, inv_eta_h;
+  double cs, sn, omc;      // cos(h ds), sin(h ds), 1 - cos(h ds)
+  double one_m_eta2;       // 1 - η²
+  double ds_eta;           // ds / η
+  double tconst;           // (1 - 1/η) ds / β0
+};
+struct QuadParams {        // quadrupole (§3.3, §3.4)
+  double ds, hds;          // slice length and half of it
+  double k1, k1ds;         // gradient, DKD kick k1·ds
+  double kabs_hds2;        // |k1| (ds/2)²: (κ ds/2)² times P
+};
+struct DriftParams { double L; };
+struct ThinParams { double k1l, k2l; };             // thin multipole (§3.5)
+struct SnakeParams { double qw, qx, qy, qz; };      // fixed rotation quaternion
+
+constexpr int kElemWords = sizeof(BendParams) / sizeof(double);   // largest member
+
 struct DevElem {
   int32_t kind, orbit, nsl, K;   // K = R_e - 1: Romberg levels minus one
-  double L;                      // element length
-  double ds, hds;                // slice length L/N and half of it
-  // sector bend (§3.1): curvature, field, per-slice trigonometry
-  double h, eta, eta_h, inv_eta_h;
-  double cs, sn, omc;            // cos(h ds), sin(h ds), 1 - cos(h ds)
-  double one_m_eta2;             // 1 - η²
-  double ds_eta;                 // ds / η
-  double tconst;                 // (1 - 1/η) ds / β0
-  // quadrupole (§3.3, §3.4)
-  double k1, k1ds, kabs_hds2;    // k1, k1·ds (DKD kick), |k1|·(ds/2)² (MK phase² · P)
-  // thin multipole (§3.5)
-  double k1l, k2l;
-  // snake quaternion (w, x, y, z)
-  double qw, qx, qy, qz;
+  union {
+    BendParams b;
+    QuadParams q;
+    DriftParams d;
+    ThinParams t;
+    SnakeParams s;
+    double v[kElemWords];
+  };
 };
 
 struct TrackArgs {
@@ -43,7 +57,7 @@ struct TrackArgs {
   double* qout;       // 4 × n SoA or null
   int64_t n;
   const DevElem* tab;
-  const uint16_t* seq;
+  const uint32_t* seq;
   int32_t n_elems;
   int32_t turns;
   int32_t report_every;

@@ -23,109 +23,135 @@ namespace {
 
 constexpr int kBlock = 256;
 
+typedef const DevElem __attribute__((address_space(4))) ConstElem;
+typedef const uint32_t __attribute__((address_space(4))) ConstSeq;
+
+// Member-wise copy of one element record out of the constant address space
+// (uniform address: scalar loads).
+__device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
+  DevElem d;
+  d.kind = p->kind;
+  d.orbit = p->orbit;
+  d.nsl = p->nsl;
+  d.K = p->K;
+#pragma unroll
+  for (int i = 0; i < kElemWords; ++i) d.v[i] = p->v[i];
+  return d;
+}
+
+#ifndef ST_WAVES_PER_EU
+#define ST_WAVES_PER_EU 2
+#endif
+
 // Romberg spin integration through one thick element, fused with its orbit
-// slices (KIND: 0 sector bend, 1 MK quadrupole, 2 DKD quadrupole).  Returns
-// the normalised element quaternion.
+// slices (KIND: 0 sector bend, 1 MK quadrupole focusing in x, 3 MK
+// quadrupole focusing in y, 2 DKD quadrupole).  Returns the normalised
+// element quaternion.
 template <int NT, int KIND>
-__device__ __forceinline__ Quat thick_element(const DevElem& e, double& X, double& Px, double& Y,
+__device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, double& Px, double& Y,
                                               double& Py, double& T, const Particle& p,
                                               const TrackArgs& a) {
-  const int N = e.nsl;
-  const int K = e.K;
-  Quat Q[kMaxRows];
-#pragma unroll
-  for (int m = 0; m < kMaxRows; ++m) Q[m] = qident();
+  static_assert(kMaxRows == 4, "the level products below are written out for four rows");
+  const int N = el.nsl;
+  const int K = el.K;
+  const double ds = KIND == 0 ? el.b.ds : el.q.ds;
+  // running products of the Romberg levels: level m keeps every 2^m-th edge
+  Quat Q0 = qident(), Q1 = qident(), Q2 = qident(), Q3 = qident();
 
   // bend invariants of this particle: Py and Pt do not change in a bend
-  double Pa2 = p.P2 - Py * Py;
-  double invPa2 = 0.0, c3py = 0.0;
-  if (KIND == 0) {
-    invPa2 = rcp_nr(Pa2);
-    c3py = p.c3 - Py * Py;
-  }
+  double Pa2 = p.P2() - Py * Py;
   MKConst mc;
-  if (KIND == 1) mc = mk_const(e, p);
-  const bool foc = e.k1 >= 0.0;
+  if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
 
   // Ps and 1/Ps at the entrance edge
   double ps2 = fma(-Px, Px, Pa2);
   double r = rsqrt_nr(ps2);
   double W = ps2 * r;
+  double invPa2 = 0.0, wme = 0.0;
+  if (KIND == 0) {
+    invPa2 = rcp_nr(Pa2);
+    // W - η = (W² - η²)/(W + η) with W² - η² = (1 - η²) + (P² - 1) - Py² - Px²
+    wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
+  }
 
   for (int j = 0; j <= N; ++j) {
     if (j > 0) {
       if (KIND == 0) {
-        bend_step(e, X, Px, Py, Y, T, W, r, Pa2, invPa2, c3py, p);
+        bend_step(el.b, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
       } else {
         if (KIND == 1) {
-          if (foc) mk_linear(mc, X, Px, Y, Py, T, p);
-          else     mk_linear(mc, Y, Py, X, Px, T, p);
-          mk_nonlinear(e.ds, X, Px, Y, Py, T, p);
-          if (foc) mk_linear(mc, X, Px, Y, Py, T, p);
-          else     mk_linear(mc, Y, Py, X, Px, T, p);
+          mk_linear(mc, X, Px, Y, Py, T, p);
+          mk_nonlinear(ds, X, Px, Y, Py, T, p);
+          mk_linear(mc, X, Px, Y, Py, T, p);
+        } else if (KIND == 3) {
+          mk_linear(mc, Y, Py, X, Px, T, p);
+          mk_nonlinear(ds, X, Px, Y, Py, T, p);
+          mk_linear(mc, Y, Py, X, Px, T, p);
         } else {
-          drift(e.hds, X, Px, Y, Py, T, p, a.inv_beta0);
-          Px = fma(-e.k1ds, X, Px);
-          Py = fma(e.k1ds, Y, Py);
-          drift(e.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+          drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+          Px = fma(-el.q.k1ds, X, Px);
+          Py = fma(el.q.k1ds, Y, Py);
+          drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
         }
-        ps2 = p.P2 - fma(Px, Px, Py * Py);
+        ps2 = p.P2() - fma(Px, Px, Py * Py);
         r = rsqrt_nr(ps2);
       }
     }
     double ox, oy, oz;
-    if (KIND == 0) omega_bend(e, X, Px, Py, r, p, ox, oy, oz);
-    else           omega_straight(e.k1 * Y, e.k1 * X, Px, Py, r, p, ox, oy, oz);
+    if (KIND == 0) omega_bend(el.b, X, Px, Py, r, p, ox, oy, oz);
+    else           omega_straight(el.q.k1 * Y, el.q.k1 * X, Px, Py, r, p, ox, oy, oz);
     const double om2 = fma(ox, ox, fma(oy, oy, oz * oz));
-    const double w = (j == 0 || j == N) ? 0.5 : 1.0;
-#pragma unroll
-    for (int m = 0; m < kMaxRows; ++m) {
-      if (m <= K && (j & ((1 << m) - 1)) == 0) {
-        const double f = w * (double)(1 << m) * e.ds;
-        double c, sfac;
-        rot_half_angle<NT>(0.25 * f * f * om2, a.ymax, c, sfac);
-        const double g = sfac * f;
-        const Quat q = {c, g * ox, g * oy, g * oz};
-        Q[m] = qmul(q, Q[m]);
+    // Level m keeps this edge when 2^m divides j, with step w 2^m ds: the
+    // rotation about Ω by 2^m times the finest angle, i.e. the finest
+    // quaternion squared m times.
+    const double f = ((j == 0 || j == N) ? 0.5 : 1.0) * ds;
+    double c, sfac;
+    rot_half_angle<NT>(0.25 * f * f * om2, a.ymax, c, sfac);
+    const double g = sfac * f;
+    Quat qb = {c, g * ox, g * oy, g * oz};
+    Q0 = qmul(qb, Q0);
+    if (K >= 1 && (j & 1) == 0) {
+      qb = qsquare(qb);
+      Q1 = qmul(qb, Q1);
+      if (K >= 2 && (j & 3) == 0) {
+        qb = qsquare(qb);
+        Q2 = qmul(qb, Q2);
+        if (K >= 3 && (j & 7) == 0) {
+          qb = qsquare(qb);
+          Q3 = qmul(qb, Q3);
+        }
       }
     }
   }
 
   // Romberg tableau (§4.3 eq. romberg) with levels indexed by stride 2^m:
   // V_j[m] = (4^j V_{j-1}[m] - V_{j-1}[m+1]) / (4^j - 1), limit V_K[0].
-  double four = 1.0;
-#pragma unroll
-  for (int jj = 1; jj < kMaxRows; ++jj) {
-    four *= 4.0;
-    if (jj <= K) {
-      const double inv = 1.0 / (four - 1.0);
-#pragma unroll
-      for (int m = 0; m < kMaxRows - 1; ++m) {
-        if (m <= K - jj) {
-          Q[m].w = (four * Q[m].w - Q[m + 1].w) * inv;
-          Q[m].x = (four * Q[m].x - Q[m + 1].x) * inv;
-          Q[m].y = (four * Q[m].y - Q[m + 1].y) * inv;
-          Q[m].z = (four * Q[m].z - Q[m + 1].z) * inv;
-        }
+  if (K >= 1) {
+    Q0 = qextrapolate(Q0, Q1, 4.0);
+    if (K >= 2) {
+      Q1 = qextrapolate(Q1, Q2, 4.0);
+      if (K >= 3) Q2 = qextrapolate(Q2, Q3, 4.0);
+      Q0 = qextrapolate(Q0, Q1, 16.0);
+      if (K >= 3) {
+        Q1 = qextrapolate(Q1, Q2, 16.0);
+        Q0 = qextrapolate(Q0, Q1, 64.0);
       }
     }
   }
-  Quat q = Q[0];
-  const double inv = rsqrt_nr(fma(q.w, q.w, fma(q.x, q.x, fma(q.y, q.y, q.z * q.z))));
-  q.w *= inv; q.x *= inv; q.y *= inv; q.z *= inv;
-  return q;
+  const double inv = rsqrt_nr(fma(Q0.w, Q0.w, fma(Q0.x, Q0.x, fma(Q0.y, Q0.y, Q0.z * Q0.z))));
+  return {Q0.w * inv, Q0.x * inv, Q0.y * inv, Q0.z * inv};
 }
 
 template <int NT>
 __device__ __forceinline__ Quat thin_element(const DevElem& e, double X, double& Px, double Y,
                                              double& Py, const Particle& p, const TrackArgs& a) {
-  const double hk1 = 0.5 * e.k1l, hk2 = 0.5 * e.k2l;
+  const double hk1 = 0.5 * e.t.k1l, hk2 = 0.5 * e.t.k2l;
   Px -= fma(hk1, X, 0.5 * hk2 * (X * X - Y * Y));
   Py += fma(hk1, Y, hk2 * X * Y);
-  double ps2 = p.P2 - fma(Px, Px, Py * Py);
+  double ps2 = p.P2() - fma(Px, Px, Py * Py);
   double r = rsqrt_nr(ps2);
-  double bx = fma(e.k2l * X, Y, e.k1l * Y);
-  double by = fma(e.k1l, X, 0.5 * e.k2l * (X * X - Y * Y));
+  double bx = fma(e.t.k2l * X, Y, e.t.k1l * Y);
+  double by = fma(e.t.k1l, X, 0.5 * e.t.k2l * (X * X - Y * Y));
   double ox, oy, oz;
   omega_straight(bx, by, Px, Py, r, p, ox, oy, oz);
   double c, sfac;
@@ -142,49 +168,66 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int NT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) track_fp64_kernel(const TrackArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ST_WAVES_PER_EU)))
+track_fp64_kernel(const TrackArgs a) {
   __shared__ double red[kBlock / 64][4];
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // Cold per-lane data in LDS: the spin (touched once per turn) and the
+  // orbit at the current element's entrance (read back only on a loss).
+  __shared__ double cold[8][kBlock];
+  const int tid = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + tid;
   const bool valid = j < a.n;
   int32_t status = valid ? a.alive[j] : 0;
   bool live = status == 1;
   const int64_t n = a.n;
 
-  double X = 0, Px = 0, Y = 0, Py = 0, T = 0, Pt = 0, sx = 0, sy = 0, sz = 0;
+  double X = 0, Px = 0, Y = 0, Py = 0, T = 0, Pt = 0;
+  cold[0][tid] = 0.0; cold[1][tid] = 0.0; cold[2][tid] = 0.0;
   if (valid) {
     X = a.z[j]; Px = a.z[n + j]; Y = a.z[2 * n + j]; Py = a.z[3 * n + j];
     T = a.z[4 * n + j]; Pt = a.z[5 * n + j];
-    sx = a.spin[j]; sy = a.spin[n + j]; sz = a.spin[2 * n + j];
+    cold[0][tid] = a.spin[j]; cold[1][tid] = a.spin[n + j]; cold[2][tid] = a.spin[2 * n + j];
   }
   const Particle p = make_particle(Pt, a);
   Quat qturn = qident();
+  // The lattice is read-only for the whole launch: reading it through the
+  // constant address space lets the uniform loads go through the scalar cache.
+  const ConstElem* tab = (const ConstElem*)(a.tab);
+  const ConstSeq* seq = (const ConstSeq*)(a.seq);
 
   for (int t = 1; t <= a.turns; ++t) {
     const bool was_live = live;
     if (was_live) qturn = qident();
     for (int ie = 0; ie < a.n_elems; ++ie) {
-      const DevElem& e = a.tab[a.seq[ie]];
+      const DevElem e = load_elem(tab + seq[ie]);
       if (!live) continue;
-      const double X0 = X, Px0 = Px, Y0 = Y, Py0 = Py, T0 = T;
+      if (e.kind == K_DRIFT) {           // no spin; the entrance state is cheap to keep
+        const double X0 = X, Y0 = Y, T0 = T;
+        drift(e.d.L, X, Px, Y, Py, T, p, a.inv_beta0);
+        if (!(fabs(X) <= a.aperture && fabs(Y) <= a.aperture && isfinite(T))) {
+          X = X0; Y = Y0; T = T0;
+          live = false;
+          status = -(1 + ie);
+        }
+        continue;
+      }
+      cold[3][tid] = X; cold[4][tid] = Px; cold[5][tid] = Y; cold[6][tid] = Py; cold[7][tid] = T;
       Quat q;
       bool spin = true;
       switch (e.kind) {
-        case K_DRIFT:
-          drift(e.L, X, Px, Y, Py, T, p, a.inv_beta0);
-          spin = false;
-          break;
         case K_SBEND:
           q = thick_element<NT, 0>(e, X, Px, Y, Py, T, p, a);
           break;
         case K_QUAD:
-          if (e.orbit == M_MK) q = thick_element<NT, 1>(e, X, Px, Y, Py, T, p, a);
-          else                 q = thick_element<NT, 2>(e, X, Px, Y, Py, T, p, a);
+          if (e.orbit != M_MK)   q = thick_element<NT, 2>(e, X, Px, Y, Py, T, p, a);
+          else if (e.q.k1 >= 0.0) q = thick_element<NT, 1>(e, X, Px, Y, Py, T, p, a);
+          else                   q = thick_element<NT, 3>(e, X, Px, Y, Py, T, p, a);
           break;
         case K_THIN:
           q = thin_element<NT>(e, X, Px, Y, Py, p, a);
           break;
         case K_SNAKE:
-          q = {e.qw, e.qx, e.qy, e.qz};
+          q = {e.s.qw, e.s.qx, e.s.qy, e.s.qz};
           break;
         default:
           spin = false;
@@ -193,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       const bool ok = fabs(X) <= a.aperture && fabs(Y) <= a.aperture && isfinite(Px) &&
                       isfinite(Py) && isfinite(T);
       if (!ok) {
-        X = X0; Px = Px0; Y = Y0; Py = Py0; T = T0;
+        X = cold[3][tid]; Px = cold[4][tid]; Y = cold[5][tid]; Py = cold[6][tid]; T = cold[7][tid];
         live = false;
         status = -(1 + ie);
         continue;
@@ -202,19 +245,23 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     }
     // A particle lost during this turn still receives the rotation of the
     // elements it completed before the loss.
-    if (was_live) qrotate(qturn, sx, sy, sz);
+    double sx = cold[0][tid], sy = cold[1][tid], sz = cold[2][tid];
+    if (was_live) {
+      qrotate(qturn, sx, sy, sz);
+      cold[0][tid] = sx; cold[1][tid] = sy; cold[2][tid] = sz;
+    }
     if (a.report_every > 0 && t % a.report_every == 0) {
       double v0 = live ? sx : 0.0, v1 = live ? sy : 0.0, v2 = live ? sz : 0.0;
       double v3 = live ? 1.0 : 0.0;
       v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2); v3 = wave_sum(v3);
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      const int lane = tid & 63, wv = tid >> 6;
       if (lane == 0) { red[wv][0] = v0; red[wv][1] = v1; red[wv][2] = v2; red[wv][3] = v3; }
       __syncthreads();
-      if (threadIdx.x < 4) {
+      if (tid < 4) {
         double s = 0.0;
-        for (int k = 0; k < kBlock / 64; ++k) s += red[k][threadIdx.x];
+        for (int k = 0; k < kBlock / 64; ++k) s += red[k][tid];
         const int rep = t / a.report_every - 1;
-        a.partials[((int64_t)rep * a.n_blocks + blockIdx.x) * 4 + threadIdx.x] = s;
+        a.partials[((int64_t)rep * a.n_blocks + blockIdx.x) * 4 + tid] = s;
       }
       __syncthreads();
     }
@@ -222,7 +269,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 
   if (valid && a.alive[j] == 1) {
     a.z[j] = X; a.z[n + j] = Px; a.z[2 * n + j] = Y; a.z[3 * n + j] = Py; a.z[4 * n + j] = T;
-    a.spin[j] = sx; a.spin[n + j] = sy; a.spin[2 * n + j] = sz;
+    a.spin[j] = cold[0][tid]; a.spin[n + j] = cold[1][tid]; a.spin[2 * n + j] = cold[2][tid];
     a.alive[j] = status;
     if (a.qout) {
       a.qout[j] = qturn.w; a.qout[n + j] = qturn.x; a.qout[2 * n + j] = qturn.y;
@@ -264,6 +311,7 @@ int track_block_size() { return kBlock; }
 hipError_t launch_track_fp64(const TrackArgs& a, int nt, hipStream_t stream) {
   const dim3 grid((unsigned)a.n_blocks), block(kBlock);
   switch (nt) {
+    case 6:  hipLaunchKernelGGL(track_fp64_kernel<6>, grid, block, 0, stream, a); break;
     case 8:  hipLaunchKernelGGL(track_fp64_kernel<8>, grid, block, 0, stream, a); break;
     case 12: hipLaunchKernelGGL(track_fp64_kernel<12>, grid, block, 0, stream, a); break;
     default: hipLaunchKernelGGL(track_fp64_kernel<16>, grid, block, 0, stream, a); break;

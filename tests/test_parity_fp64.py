@@ -92,6 +92,12 @@ ELEMENTS = {
     "quad_mk_d": [quad(1.1, -0.08, "mk", 6, 2)],
     "quad_dkd_f": [quad(1.0, 0.05, "dkd", 8, 3)],
     "quad_dkd_d": [quad(1.0, -0.05, "dkd", 3, 1)],
+    # beyond the series ranges: the halving fallbacks for the quaternion
+    # half angle (|Ω| ds ≈ 13 rad), asin (η = 1.2, 0.3 rad per step) and the
+    # MK phase (κ ds/2 ≈ 0.39)
+    "sbend_strong_mispowered": [sbend(2.0, 0.6, 2, 2, eta=1.2)],
+    "quad_mk_strong": [quad(1.1, 2.0, "mk", 2, 2)],
+    "quad_mk_strong_d": [quad(1.1, -2.0, "mk", 2, 2)],
     "thin": [thin(k1l=0.01, k2l=-0.5)],
     "snake": [snake(math.pi, math.pi / 4)],
 }
@@ -115,7 +121,7 @@ def test_small_ring_full_configuration():
     assert_parity(g, o, "small ring 1 turn")
     g, o = both(small_ring(), BEAM, z, s, a, turns=256, report_every=32)
     assert_multiturn_parity(g, o, small_ring(), BEAM, z, s, a, 256, "small ring 256 turns")
-    np.testing.assert_allclose(g["pol"], o["pol"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g["pol"], o["pol"], rtol=0, atol=SPIN_TOL)
 
 
 @pytest.mark.parametrize("variant", ["mk_quads", "rows1", "rows4_n16"])
@@ -139,7 +145,7 @@ def test_rhic_ring_ten_turns():
     z, s, a = gaussian_bunch(256, 1501034501, BEAM)
     g, o = both(rhic_like_ring(), BEAM, z, s, a, turns=10, report_every=5)
     assert_multiturn_parity(g, o, rhic_like_ring(), BEAM, z, s, a, 10, "rhic 10 turns")
-    np.testing.assert_allclose(g["pol"], o["pol"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g["pol"], o["pol"], rtol=0, atol=SPIN_TOL)
 
 
 def test_rhic_full_bunch_sampled_against_the_oracle():
