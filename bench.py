@@ -42,8 +42,39 @@ OPS_PER_PARTICLE_TURN = 1_485_734
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "track_fp64_rhic_ring_traffic.md")
+COPY_BYTES = 1 << 30
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    """Hash of the library sources: a recorded traffic figure is only valid
+    for the kernel it was measured on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1501_03450_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(n, turns):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record, or None when the record is for another kernel or workload."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    for line in open(TRAFFIC_RECORD):
+        if line.startswith("traffic-record:"):
+            rec = json.loads(line.split(":", 1)[1])
+            if rec["source_sha"] == kernel_source_hash() and rec["particles"] == n \
+                    and rec["turns_per_launch"] == turns:
+                return rec["bytes_per_launch"]
+    return None
 
 
 def parse():
@@ -56,6 +87,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-particles", type=int, default=4096)
     ap.add_argument("--cpu-sample-turns", type=int, default=10)
+    ap.add_argument("--mixed-particles", type=int, default=4 << 20)
+    ap.add_argument("--mixed-turns", type=int, default=20)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run one device copy of 1 GiB and one tracking launch "
+                         "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print the source hash")
     return ap.parse_args()
 
 
@@ -70,6 +107,57 @@ def cpu_baseline(ring, beam, z, s, a, n_sample, turns):
             "kind": "oracle",
             "sample": f"{n_sample} particles x {turns} turns of the same ring and bunch, "
                       f"extended-precision oracle, {threads} threads, {dt:.1f} s"}
+
+
+def timed_tracking(tracker, turns, steps, stream):
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        tracker.track(turns, stream=stream)
+        ev[k + 1].record(stream)
+    ev[-1].synchronize()
+    return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+
+
+def mixed_leg(ring, beam, n, turns, stream):
+    """Mixed precision against FP64 on the same GPU, bunch and turns."""
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from workloads import gaussian_bunch
+    from workloads.bunch import SEED_BASE
+    z, s, a = gaussian_bunch(n, SEED_BASE + 2, beam)
+    out = {"workload": f"rhic_like_ring, {n} protons, {turns} turns from the same start"}
+    res = {}
+    for prec in ("fp64", "mixed", "mixed_all"):
+        tr = SpinTracker(ring, beam, device=0, precision=prec, report_every=turns)
+        with torch.cuda.stream(stream):
+            tr.set_particles(z, s, a)
+        tr.track(1, stream=stream)                  # warm-up and one-turn state
+        stream.synchronize()
+        z1, s1, _ = tr.read(stream=stream)
+        with torch.cuda.stream(stream):
+            tr.set_particles(z, s, a)
+        ms = timed_tracking(tr, turns, 1, stream)[0]
+        zt, st_, at = tr.read(stream=stream)
+        pol = tr.polarization(stream=stream).cpu().numpy()
+        tr.close()
+        res[prec] = dict(ms=ms, s1=s1, z1=z1, zt=zt, st=st_, pol=pol)
+        log(f"[bench] mixed leg: {prec} {n} x {turns} turns in {ms:.1f} ms")
+    f = res["fp64"]
+    out["fp64_value"] = n * turns / (f["ms"] / 1e3)
+    out["unit"] = "particle-turns/s"
+    for prec, key in (("mixed", "single_where_small_rotation"), ("mixed_all", "single_everywhere")):
+        m = res[prec]
+        out[key] = {
+            "value": n * turns / (m["ms"] / 1e3),
+            "speedup_vs_fp64": f["ms"] / m["ms"],
+            "spin_err_one_turn_max": float(np.abs(m["s1"] - f["s1"]).max()),
+            "orbit_identical_to_fp64": bool(np.array_equal(m["z1"], f["z1"])),
+            f"mean_spin_err_after_{turns}_turns": float(np.linalg.norm(m["st"] - f["st"], axis=0).mean()),
+            "polarization_err": float(np.abs(m["pol"][-1, :3] - f["pol"][-1, :3]).max()),
+        }
+    return out
 
 
 def main():
@@ -96,6 +184,19 @@ def main():
     with torch.cuda.stream(stream):
         tr.set_particles(z, s, a)
     torch.cuda.synchronize()
+
+    if args.traffic_probe:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+        stream.synchronize()
+        tr.track(T, stream=stream)
+        stream.synchronize()
+        print(json.dumps({"source_sha": kernel_source_hash(), "particles": n,
+                          "turns_per_launch": T, "copy_bytes": COPY_BYTES}), flush=True)
+        tr.close()
+        return
 
     for w in range(args.warmup):
         tr.track(T, stream=stream)
@@ -155,9 +256,11 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": recorded_traffic(n, T),
         },
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(ring, beam, args.mixed_particles, args.mixed_turns, stream)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(ring, beam, z, s, a, args.cpu_sample_particles,

@@ -67,9 +67,12 @@ typedef enum {
 
 typedef enum {
   ST_FP64 = 0,      /* every step in double precision                          */
-  ST_MIXED = 1      /* orbit and final Romberg step in double; per-slice
-                       quaternions, level products and the Romberg tableau in
-                       single precision with compensated sums                  */
+  ST_MIXED = 1,     /* orbit, Ω, tableau, normalisation and element composition
+                       in double; the edge quaternions and Romberg level
+                       products in single precision with compensated sums, in
+                       the elements whose finest-slice design rotation is at
+                       most 0.02 rad (at 5 mm amplitude); double elsewhere     */
+  ST_MIXED_ALL = 2  /* as ST_MIXED, single precision in every element          */
 } st_precision;
 
 /* One lattice element.  SI units; strengths normalised to (Bρ)0.
@@ -151,6 +154,78 @@ st_status st_read_particles(st_ctx* ctx, double* h_z, double* h_spin, int32_t* h
 /* Human-readable description of the last error on this context (owned by
  * the context; valid until the next call).  Never NULL. */
 const char* st_last_error(const st_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Spin surrogate (not part of the paper's method): an MLP
+ * n_in -> 256 -> 256 -> 256 -> 4 with SiLU activations and normalised output
+ * q = y/|y| that maps a particle's turn-start coordinates to its one-turn spin
+ * quaternion.  The two 256×256 layers run in bf16 on the matrix cores with
+ * fp32 accumulation; the first and last layers in fp32.  Training minimises
+ * the mean of |q - t|² over a batch with Adam (β1 0.9, β2 0.999, ε 1e-8) on
+ * fp32 master weights.  The flat parameter layout is W1 [256][n_in], b1 [256],
+ * W2 [256][256], b2, W3 [256][256], b3, W4 [4][256], b4 [4] (W row-major
+ * [out][in]).  Device arrays are row-major per sample: inputs x [n][n_in],
+ * quaternions [n][4] (w, x, y, z).
+ * ------------------------------------------------------------------------ */
+typedef struct st_mlp st_mlp;
+
+/* Create a network on HIP device `device` with n_in inputs (1..8) and hidden
+ * width 256 (the only width supported).  Weights are uniform in
+ * ±1/sqrt(fan_in) from a counter-based generator keyed by `seed`; biases 0. */
+st_status st_mlp_create(st_mlp** out, int device, int32_t n_in, int32_t width, uint64_t seed);
+
+/* Release the network.  NULL is accepted. */
+st_status st_mlp_destroy(st_mlp* m);
+
+/* Last error on this network (owned by it; never NULL). */
+const char* st_mlp_last_error(const st_mlp* m);
+
+/* Copy the fp32 master parameters to h_get and/or replace them from h_set
+ * (host memory, *n_params floats; either pointer may be NULL).  *n_params
+ * (host, may be NULL) receives the count.  Synchronous. */
+st_status st_mlp_params(st_mlp* m, float* h_get, const float* h_set, int64_t* n_params);
+
+/* One Adam step (learning rate lr > 0) on `batch` samples: inputs d_x, unit
+ * quaternion targets d_t (device).  d_loss (device, 1 float, may be NULL)
+ * receives the batch's mean loss before the step.  Queued on `stream`. */
+st_status st_mlp_train_step(st_mlp* m, const float* d_x, const float* d_t, int64_t batch,
+                            float lr, float* d_loss, void* stream);
+
+/* Gradient of the batch's mean loss into d_grad (device, n_params floats)
+ * without updating the weights; d_loss as in st_mlp_train_step. */
+st_status st_mlp_gradient(st_mlp* m, const float* d_x, const float* d_t, int64_t batch,
+                          float* d_grad, float* d_loss, void* stream);
+
+/* Inference: d_q [n][4] (device) from d_x [n][n_in] (device). */
+st_status st_mlp_infer(st_mlp* m, const float* d_x, float* d_q, int64_t n, void* stream);
+
+/* Network inputs from particle coordinates (d_z: device 6×n SoA doubles):
+ * x[j][i] = (z[i][j] - center[i]) * inv_scale[i] for i < 6 and, when
+ * n_in == 7, x[j][6] = extra.  center, inv_scale: host, 6 doubles. */
+st_status st_mlp_features(st_mlp* m, const double* d_z, int64_t n, const double* center,
+                          const double* inv_scale, double extra, float* d_x, void* stream);
+
+/* Training targets from tracked one-turn quaternions (d_q: device 4×n SoA
+ * doubles, as filled by st_track with st_bind_quaternions): t[j] = ±q_j
+ * with the sign that makes t·ref >= 0 (ref: host, 4 doubles), as floats. */
+st_status st_mlp_targets(st_mlp* m, const double* d_q, int64_t n, const double* ref, float* d_t,
+                         void* stream);
+
+/* Track the bound particles for `turns` turns with the surrogate for spin.
+ * Each turn a particle with d_fallback[j] == 0 gets the orbit push and a spin
+ * rotation by the network's quaternion for its turn-start coordinates
+ * (inputs as in st_mlp_features); a particle with d_fallback[j] != 0 gets the
+ * full double-precision turn.  Every audit_every-th turn (≥ 1) every particle
+ * gets the full double-precision turn and its network quaternion is compared
+ * with the tracked one: when the largest component difference (after
+ * aligning the sign) exceeds `threshold`, d_fallback[j] is set to the turn
+ * number (1-based) and the particle stays on the double-precision path.
+ * d_fallback: device int32 [n], initialised by the caller.  Polarization is
+ * recorded as in st_track.  Requires a lattice, particles and a network
+ * created on the same device. */
+st_status st_track_surrogate(st_ctx* ctx, st_mlp* m, int64_t turns, int32_t audit_every,
+                             double threshold, const double* center, const double* inv_scale,
+                             double extra, int32_t* d_fallback, void* stream);
 
 #ifdef __cplusplus
 }

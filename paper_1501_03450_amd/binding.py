@@ -20,16 +20,18 @@ LIB_PATH = os.environ.get("SPINTRACK_LIB", os.path.join(_HERE, "libspintrack.so"
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDEVICE, ST_ESTATE = 0, -1, -2, -3, -4
 ST_MARKER, ST_DRIFT, ST_SBEND, ST_QUAD, ST_THIN, ST_SNAKE = range(6)
 ST_ORB_EXACT, ST_ORB_DKD, ST_ORB_MK = range(3)
-ST_FP64, ST_MIXED = 0, 1
+ST_FP64, ST_MIXED, ST_MIXED_ALL = 0, 1, 2
 
 KIND_CODES = {"marker": ST_MARKER, "drift": ST_DRIFT, "sbend": ST_SBEND, "quad": ST_QUAD,
               "thin": ST_THIN, "snake": ST_SNAKE}
 ORBIT_CODES = {"exact": ST_ORB_EXACT, "dkd": ST_ORB_DKD, "mk": ST_ORB_MK}
-PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED}
+PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED, "mixed_all": ST_MIXED_ALL}
 
 EXPORTS = ("st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
            "st_bind_quaternions", "st_track", "st_polarization", "st_read_particles",
-           "st_last_error")
+           "st_last_error", "st_mlp_create", "st_mlp_destroy", "st_mlp_last_error",
+           "st_mlp_params", "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
+           "st_mlp_features", "st_mlp_targets", "st_track_surrogate")
 
 
 class st_element(ctypes.Structure):
@@ -68,8 +70,20 @@ def _load():
     lib.st_read_particles.argtypes = [vp, vp, vp, vp, vp]
     lib.st_last_error.argtypes = [vp]
     lib.st_last_error.restype = ctypes.c_char_p
+    f64, f32, u64 = ctypes.c_double, ctypes.c_float, ctypes.c_uint64
+    lib.st_mlp_create.argtypes = [P(vp), i32, ctypes.c_int32, ctypes.c_int32, u64]
+    lib.st_mlp_destroy.argtypes = [vp]
+    lib.st_mlp_last_error.argtypes = [vp]
+    lib.st_mlp_last_error.restype = ctypes.c_char_p
+    lib.st_mlp_params.argtypes = [vp, vp, vp, P(i64)]
+    lib.st_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp]
+    lib.st_mlp_gradient.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    lib.st_mlp_infer.argtypes = [vp, vp, vp, i64, vp]
+    lib.st_mlp_features.argtypes = [vp, vp, i64, P(f64), P(f64), f64, vp, vp]
+    lib.st_mlp_targets.argtypes = [vp, vp, i64, P(f64), vp, vp]
+    lib.st_track_surrogate.argtypes = [vp, vp, i64, ctypes.c_int32, f64, P(f64), P(f64), f64, vp, vp]
     for name in EXPORTS:
-        if name != "st_last_error":
+        if name not in ("st_last_error", "st_mlp_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -149,3 +163,62 @@ def st_polarization(ctx, d_out_ptr=None, capacity=0, stream=None) -> int:
 
 def st_read_particles(ctx, h_z_ptr, h_spin_ptr, h_alive_ptr, stream=None):
     _check(ctx, LIB.st_read_particles(ctx, h_z_ptr, h_spin_ptr, h_alive_ptr, stream))
+
+
+# ---------------------------------------------------------------- surrogate --
+
+def _check_mlp(m, status):
+    if status != ST_OK:
+        msg = LIB.st_mlp_last_error(m).decode() if m else "invalid argument"
+        raise SpinTrackError(status, msg)
+
+
+def _d6(v):
+    return (ctypes.c_double * 6)(*[float(x) for x in v])
+
+
+def st_mlp_create(device=0, n_in=6, width=256, seed=0):
+    h = ctypes.c_void_p()
+    st = LIB.st_mlp_create(ctypes.byref(h), int(device), int(n_in), int(width), int(seed))
+    if st != ST_OK:
+        raise SpinTrackError(st, f"cannot create a network (n_in={n_in}, width={width})")
+    return h
+
+
+def st_mlp_destroy(m):
+    LIB.st_mlp_destroy(m)
+
+
+def st_mlp_params(m, h_get_ptr=None, h_set_ptr=None) -> int:
+    n = ctypes.c_int64(0)
+    _check_mlp(m, LIB.st_mlp_params(m, h_get_ptr, h_set_ptr, ctypes.byref(n)))
+    return int(n.value)
+
+
+def st_mlp_train_step(m, x_ptr, t_ptr, batch, lr, loss_ptr=None, stream=None):
+    _check_mlp(m, LIB.st_mlp_train_step(m, x_ptr, t_ptr, int(batch), float(lr), loss_ptr, stream))
+
+
+def st_mlp_gradient(m, x_ptr, t_ptr, batch, grad_ptr, loss_ptr=None, stream=None):
+    _check_mlp(m, LIB.st_mlp_gradient(m, x_ptr, t_ptr, int(batch), grad_ptr, loss_ptr, stream))
+
+
+def st_mlp_infer(m, x_ptr, q_ptr, n, stream=None):
+    _check_mlp(m, LIB.st_mlp_infer(m, x_ptr, q_ptr, int(n), stream))
+
+
+def st_mlp_features(m, z_ptr, n, center, inv_scale, extra, x_ptr, stream=None):
+    _check_mlp(m, LIB.st_mlp_features(m, z_ptr, int(n), _d6(center), _d6(inv_scale), float(extra),
+                                      x_ptr, stream))
+
+
+def st_mlp_targets(m, q_ptr, n, ref, t_ptr, stream=None):
+    r = (ctypes.c_double * 4)(*[float(x) for x in ref])
+    _check_mlp(m, LIB.st_mlp_targets(m, q_ptr, int(n), r, t_ptr, stream))
+
+
+def st_track_surrogate(ctx, m, turns, audit_every, threshold, center, inv_scale, extra,
+                       fallback_ptr, stream=None):
+    _check(ctx, LIB.st_track_surrogate(ctx, m, int(turns), int(audit_every), float(threshold),
+                                       _d6(center), _d6(inv_scale), float(extra), fallback_ptr,
+                                       stream))

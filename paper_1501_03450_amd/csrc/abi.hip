@@ -12,6 +12,10 @@
 #include "spintrack.h"
 #include "track_kernels.h"
 
+// The network's device and input width, for argument checks.
+int st_mlp_device_of(const st_mlp* m);
+int st_mlp_inputs_of(const st_mlp* m);
+
 struct st_ctx {
   int device = 0;
   std::string err;
@@ -38,6 +42,11 @@ struct st_ctx {
   double* d_pol = nullptr;
   size_t pol_cap = 0;          // doubles
   int64_t n_reports = 0;
+  // surrogate tracking scratch
+  float* d_feat = nullptr;     // [n][8]
+  float* d_qnn = nullptr;      // [n][4]
+  double* d_q64 = nullptr;     // 4 × n
+  int64_t surr_cap = 0;
 };
 
 namespace {
@@ -112,13 +121,29 @@ std::string validate(const st_element& e, int64_t i) {
   return std::string();
 }
 
-st::DevElem derive(const st_element& e, double beta0) {
+// Finest-slice rotation angle of an element for a particle at amplitude r_ref
+// (the element's spin-step size: used to choose the series length and, in the
+// mixed mode, the precision of the spin arithmetic).
+double design_angle(const st_element& e, const st_beam& b, double r_ref);
+
+// Single precision keeps the spin error per element near ε32·Σ|q ⊗ Q - Q|,
+// which grows with the slice rotation; above this angle the element stays in
+// double precision in ST_MIXED.
+constexpr double kSpin32MaxAngle = 0.02;
+
+st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
   st::DevElem d;
   std::memset(&d, 0, sizeof(d));
   d.kind = e.kind;
   d.orbit = e.orbit;
   d.nsl = 1;
   d.K = 0;
+  // Only the sliced elements: a thin element costs one rotation, and its
+  // quaternion would need a double-precision renormalisation anyway.
+  const bool thick = e.kind == ST_SBEND || e.kind == ST_QUAD;
+  if (thick && (beam.precision == ST_MIXED_ALL ||
+                (beam.precision == ST_MIXED && design_angle(e, beam, 0.005) <= kSpin32MaxAngle)))
+    d.flags |= st::F_SPIN32;
   if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
     d.nsl = e.n_slices;
     const int re = std::min(e.romberg_rows, 1 + v2(e.n_slices));
@@ -131,13 +156,19 @@ st::DevElem derive(const st_element& e, double beta0) {
     b.eta = e.eta;
     b.eta_h = e.eta * b.h;
     b.inv_eta_h = 1.0 / (e.eta * b.h);
-    b.cs = std::cos(b.h * b.ds);
-    b.sn = std::sin(b.h * b.ds);
-    const double s2 = std::sin(0.5 * b.h * b.ds);
-    b.omc = 2.0 * s2 * s2;
     b.one_m_eta2 = (1.0 - e.eta) * (1.0 + e.eta);
-    b.ds_eta = b.ds / e.eta;
-    b.tconst = (1.0 - 1.0 / e.eta) * b.ds / beta0;
+    auto step = [&](double s) {
+      st::BendStep k;
+      k.cs = std::cos(b.h * s);
+      k.sn = std::sin(b.h * s);
+      const double s2 = std::sin(0.5 * b.h * s);
+      k.omc = 2.0 * s2 * s2;
+      k.s_eta = s / e.eta;
+      k.tconst = (1.0 - 1.0 / e.eta) * s / beta0;
+      return k;
+    };
+    b.slice = step(b.ds);
+    b.whole = step(e.L);
   } else if (e.kind == ST_QUAD) {
     st::QuadParams& q = d.q;
     q.ds = e.L / e.n_slices;
@@ -160,12 +191,11 @@ st::DevElem derive(const st_element& e, double beta0) {
   return d;
 }
 
-// Largest rotation angle a design-amplitude particle meets in one series
+// Largest rotation angle a particle at amplitude r_ref meets in one series
 // evaluation of this element: the finest Romberg level, w ds |Ω| with w = 1
 // at interior edges (coarser levels are obtained by squaring).
-double design_angle(const st_element& e, const st_beam& b) {
+double design_angle(const st_element& e, const st_beam& b, double r_ref) {
   const double a1 = 1.0 + b.G * b.gamma0;
-  const double r_ref = 0.02;
   if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
     const double ds = e.L / e.n_slices;
     const double f = e.n_slices > 1 ? ds : 0.5 * ds;
@@ -180,6 +210,46 @@ double design_angle(const st_element& e, const st_beam& b) {
   }
   if (e.kind == ST_THIN) return a1 * (std::fabs(e.k1l) * r_ref + 0.5 * std::fabs(e.k2l) * r_ref * r_ref);
   return 0.0;
+}
+
+st::TrackArgs track_args(const st_ctx* c) {
+  st::TrackArgs a{};
+  a.z = c->z;
+  a.spin = c->spin;
+  a.alive = c->alive;
+  a.n = c->n;
+  a.tab = c->d_tab;
+  a.seq = c->d_seq;
+  a.n_elems = c->n_elems;
+  a.n_blocks = (int32_t)((c->n + st::track_block_size() - 1) / st::track_block_size());
+  a.beta0 = c->beta0;
+  a.inv_beta0 = 1.0 / c->beta0;
+  a.gamma0 = c->beam.gamma0;
+  a.inv_gamma0_sq = 1.0 / (c->beam.gamma0 * c->beam.gamma0);
+  a.G = c->beam.G;
+  a.aperture = c->beam.aperture;
+  a.ymax = c->ymax;
+  return a;
+}
+
+// Grow the polarization buffers for n_rep reports of nb blocks each.
+st_status ensure_polarization(st_ctx* c, int64_t n_rep, int64_t nb) {
+  hipError_t e;
+  if (n_rep <= 0) return ST_OK;
+  const size_t need = (size_t)n_rep * (size_t)nb * 4;
+  if (need > c->partials_cap) {
+    if (c->d_partials) { (void)hipFree(c->d_partials); c->d_partials = nullptr; c->partials_cap = 0; }
+    if ((e = hipMalloc(&c->d_partials, need * sizeof(double))) != hipSuccess)
+      return fail(c, ST_ENOMEM, std::string("polarization partials: ") + hipGetErrorString(e));
+    c->partials_cap = need;
+  }
+  if ((size_t)n_rep * 4 > c->pol_cap) {
+    if (c->d_pol) { (void)hipFree(c->d_pol); c->d_pol = nullptr; c->pol_cap = 0; }
+    if ((e = hipMalloc(&c->d_pol, (size_t)n_rep * 4 * sizeof(double))) != hipSuccess)
+      return fail(c, ST_ENOMEM, std::string("polarization history: ") + hipGetErrorString(e));
+    c->pol_cap = (size_t)n_rep * 4;
+  }
+  return ST_OK;
 }
 
 }  // namespace
@@ -206,6 +276,9 @@ st_status st_destroy(st_ctx* c) {
     if (c->d_seq) (void)hipFree(c->d_seq);
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_pol) (void)hipFree(c->d_pol);
+    if (c->d_feat) (void)hipFree(c->d_feat);
+    if (c->d_qnn) (void)hipFree(c->d_qnn);
+    if (c->d_q64) (void)hipFree(c->d_q64);
   }
   delete c;
   return ST_OK;
@@ -224,7 +297,8 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   if (!std::isfinite(b->G) || !std::isfinite(b->gamma0) || !(b->gamma0 > 1.0))
     return fail(c, ST_EINVAL, "gamma0 must be finite and > 1, G finite");
   if (!(b->aperture > 0.0)) return fail(c, ST_EINVAL, "aperture must be > 0");
-  if (b->precision != ST_FP64 && b->precision != ST_MIXED) return fail(c, ST_EINVAL, "unknown precision");
+  if (b->precision != ST_FP64 && b->precision != ST_MIXED && b->precision != ST_MIXED_ALL)
+    return fail(c, ST_EINVAL, "unknown precision");
   if (b->report_every < 0) return fail(c, ST_EINVAL, "report_every must be >= 0");
   for (int64_t i = 0; i < n; ++i) {
     std::string m = validate(els[i], i);
@@ -246,10 +320,10 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
       k = (int)uniq.size() - 1;
     }
     seq[(size_t)i] = (uint32_t)k;
-    theta = std::max(theta, design_angle(els[i], *b));
+    theta = std::max(theta, design_angle(els[i], *b, 0.02));
   }
   std::vector<st::DevElem> tab(std::max<size_t>(uniq.size(), 1));
-  for (size_t u = 0; u < uniq.size(); ++u) tab[u] = derive(uniq[u], beta0);
+  for (size_t u = 0; u < uniq.size(); ++u) tab[u] = derive(uniq[u], *b, beta0);
 
   DeviceGuard g(c->device);
   if (c->d_tab) { (void)hipFree(c->d_tab); c->d_tab = nullptr; }
@@ -309,7 +383,6 @@ st_status st_track(st_ctx* c, int64_t turns, void* stream) {
   if (!c->have_particles) return fail(c, ST_ESTATE, "no particles bound");
   if (turns < 0 || turns > std::numeric_limits<int32_t>::max())
     return fail(c, ST_EINVAL, "turns must be in 0..2^31-1");
-  if (c->beam.precision != ST_FP64) return fail(c, ST_EINVAL, "mixed precision is not built yet");
   c->n_reports = 0;
   if (turns == 0 || c->n == 0) return ST_OK;
   DeviceGuard g(c->device);
@@ -319,42 +392,15 @@ st_status st_track(st_ctx* c, int64_t turns, void* stream) {
   const int rep_every = c->beam.report_every;
   const int64_t n_rep = rep_every > 0 ? turns / rep_every : 0;
   hipError_t e;
-  if (n_rep > 0) {
-    const size_t need = (size_t)n_rep * (size_t)nb * 4;
-    if (need > c->partials_cap) {
-      if (c->d_partials) { (void)hipFree(c->d_partials); c->d_partials = nullptr; c->partials_cap = 0; }
-      if ((e = hipMalloc(&c->d_partials, need * sizeof(double))) != hipSuccess)
-        return fail(c, ST_ENOMEM, std::string("polarization partials: ") + hipGetErrorString(e));
-      c->partials_cap = need;
-    }
-    if ((size_t)n_rep * 4 > c->pol_cap) {
-      if (c->d_pol) { (void)hipFree(c->d_pol); c->d_pol = nullptr; c->pol_cap = 0; }
-      if ((e = hipMalloc(&c->d_pol, (size_t)n_rep * 4 * sizeof(double))) != hipSuccess)
-        return fail(c, ST_ENOMEM, std::string("polarization history: ") + hipGetErrorString(e));
-      c->pol_cap = (size_t)n_rep * 4;
-    }
-  }
-  st::TrackArgs a;
-  a.z = c->z;
-  a.spin = c->spin;
-  a.alive = c->alive;
+  st_status pst = ensure_polarization(c, n_rep, nb);
+  if (pst != ST_OK) return pst;
+  st::TrackArgs a = track_args(c);
   a.qout = c->qout;
-  a.n = c->n;
-  a.tab = c->d_tab;
-  a.seq = c->d_seq;
-  a.n_elems = c->n_elems;
   a.turns = (int32_t)turns;
   a.report_every = rep_every;
-  a.n_blocks = (int32_t)nb;
   a.partials = c->d_partials;
-  a.beta0 = c->beta0;
-  a.inv_beta0 = 1.0 / c->beta0;
-  a.gamma0 = c->beam.gamma0;
-  a.inv_gamma0_sq = 1.0 / (c->beam.gamma0 * c->beam.gamma0);
-  a.G = c->beam.G;
-  a.aperture = c->beam.aperture;
-  a.ymax = c->ymax;
-  if ((e = st::launch_track_fp64(a, c->nt, s)) != hipSuccess) return hip_fail(c, e, "launch track");
+  if ((e = st::launch_track(a, c->nt, c->beam.precision != ST_FP64, s)) != hipSuccess)
+    return hip_fail(c, e, "launch track");
   if (n_rep > 0) {
     if ((e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol, s)) != hipSuccess)
       return hip_fail(c, e, "launch polarization reduction");
@@ -396,3 +442,70 @@ st_status st_read_particles(st_ctx* c, double* h_z, double* h_spin, int32_t* h_a
 }
 
 }  // extern "C"
+
+extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int32_t audit_every,
+                                        double threshold, const double* center,
+                                        const double* inv_scale, double extra,
+                                        int32_t* d_fallback, void* stream) {
+  if (!c) return ST_EINVAL;
+  if (!m) return fail(c, ST_EINVAL, "network is NULL");
+  if (!c->have_lattice) return fail(c, ST_ESTATE, "no lattice loaded");
+  if (!c->have_particles) return fail(c, ST_ESTATE, "no particles bound");
+  if (turns < 0 || turns > std::numeric_limits<int32_t>::max())
+    return fail(c, ST_EINVAL, "turns must be in 0..2^31-1");
+  if (audit_every < 1) return fail(c, ST_EINVAL, "audit_every must be >= 1");
+  if (!(threshold >= 0.0) || !std::isfinite(threshold)) return fail(c, ST_EINVAL, "bad threshold");
+  if (!center || !inv_scale) return fail(c, ST_EINVAL, "feature scaling is NULL");
+  if (c->n > 0 && !d_fallback) return fail(c, ST_EINVAL, "fallback array is NULL");
+  if (st_mlp_device_of(m) != c->device) return fail(c, ST_EINVAL, "network on another device");
+  c->n_reports = 0;
+  if (turns == 0 || c->n == 0) return ST_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  const int64_t n = c->n;
+  if (n > c->surr_cap) {
+    for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64}) if (p) (void)hipFree(p);
+    c->d_feat = nullptr; c->d_qnn = nullptr; c->d_q64 = nullptr; c->surr_cap = 0;
+    if ((e = hipMalloc(&c->d_feat, (size_t)n * 8 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&c->d_qnn, (size_t)n * 4 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&c->d_q64, (size_t)n * 4 * sizeof(double))) != hipSuccess)
+      return fail(c, ST_ENOMEM, std::string("surrogate scratch: ") + hipGetErrorString(e));
+    c->surr_cap = n;
+  }
+  const int bs = st::track_block_size();
+  const int64_t nb = (n + bs - 1) / bs;
+  const int rep_every = c->beam.report_every;
+  const int64_t n_rep = rep_every > 0 ? turns / rep_every : 0;
+  st_status pst = ensure_polarization(c, n_rep, nb);
+  if (pst != ST_OK) return pst;
+  for (int64_t t = 1; t <= turns; ++t) {
+    st_status ms = st_mlp_features(m, c->z, n, center, inv_scale, extra, c->d_feat, stream);
+    if (ms == ST_OK) ms = st_mlp_infer(m, c->d_feat, c->d_qnn, n, stream);
+    if (ms != ST_OK) return fail(c, ms, std::string("network: ") + st_mlp_last_error(m));
+    const bool audit = t % audit_every == 0;
+    st::TrackArgs a = track_args(c);
+    a.turns = 1;
+    if (audit) {
+      a.qout = c->d_q64;
+      if ((e = st::launch_track(a, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "audit turn");
+      if ((e = st::launch_audit(c->alive, d_fallback, c->d_qnn, c->d_q64, n, threshold, (int32_t)t, s)) != hipSuccess)
+        return hip_fail(c, e, "audit");
+    } else {
+      a.fallback = d_fallback;
+      if ((e = st::launch_track(a, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "surrogate turn");
+      if ((e = st::launch_surrogate_spin(c->spin, c->alive, d_fallback, c->d_qnn, n, s)) != hipSuccess)
+        return hip_fail(c, e, "surrogate spin");
+    }
+    if (n_rep > 0 && t % rep_every == 0) {
+      const int64_t rep = t / rep_every - 1;
+      if ((e = st::launch_polarization_partials(c->spin, c->alive, n, c->d_partials + rep * nb * 4, s)) != hipSuccess)
+        return hip_fail(c, e, "polarization");
+    }
+  }
+  if (n_rep > 0 && (e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol, s)) != hipSuccess)
+    return hip_fail(c, e, "polarization reduction");
+  c->n_reports = n_rep;
+  c->err.clear();
+  return ST_OK;
+}

@@ -138,20 +138,20 @@ __device__ __forceinline__ void omega_bend(const BendParams& e, double X, double
 // with W1 - W0 = (Px - Px(s))(Px + Px(s))/(W0 + W1), and
 // asin(Px/Pα) - asin(Px(s)/Pα) = asin((Px W1 - Px(s) W0)/Pα²): both
 // algebraically identical to the printed forms and free of cancellation.
-__device__ __forceinline__ void bend_step(const BendParams& e, double& X, double& Px, double Py,
-                                          double& Y, double& T, double& W0, double& r0,
-                                          double& wme, double Pa2, double invPa2,
-                                          const Particle& p) {
+__device__ __forceinline__ void bend_step(const BendParams& e, const BendStep& k, double& X,
+                                          double& Px, double Py, double& Y, double& T,
+                                          double& W0, double& r0, double& wme, double Pa2,
+                                          double invPa2, const Particle& p) {
   double A = fma(-e.eta_h, X, wme);
-  double px1 = fma(Px, e.cs, A * e.sn);
+  double px1 = fma(Px, k.cs, A * k.sn);
   double ps2n = fma(-px1, px1, Pa2);
   double r1 = rsqrt_nr(ps2n);
   double W1 = ps2n * r1;
   double dW = (Px - px1) * (Px + px1) * rcp_nr(W0 + W1);
-  double X1 = fma(X, e.cs, fma(wme, e.omc, fma(Px, e.sn, dW)) * e.inv_eta_h);
+  double X1 = fma(X, k.cs, fma(wme, k.omc, fma(Px, k.sn, dW)) * e.inv_eta_h);
   double D = asin_small(fma(Px, W1, -px1 * W0) * invPa2);
-  Y = fma(Py, e.ds_eta, fma(Py * D, e.inv_eta_h, Y));
-  T = T - p.Pt * e.ds_eta - p.ib() * D * e.inv_eta_h + e.tconst;
+  Y = fma(Py, k.s_eta, fma(Py * D, e.inv_eta_h, Y));
+  T = T - p.Pt * k.s_eta - p.ib() * D * e.inv_eta_h + k.tconst;
   wme += dW;
   X = X1;
   Px = px1;

@@ -19,13 +19,17 @@ enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2 };
 constexpr int kMaxRows = 4;   // Romberg tableau rows supported by the kernels
 
 // Per-kind parameters, precomputed on the host.
+struct BendStep {          // constants of one exact step of length s
+  double cs, sn, omc;      // cos(h s), sin(h s), 1 - cos(h s)
+  double s_eta;            // s / η
+  double tconst;           // (1 - 1/η) s / β0
+};
 struct BendParams {        // sector bend (§3.1)
   double ds;               // slice length L/N
   double h, eta, eta_h, inv_eta_h;
-  double cs, sn, omc;      // cos(h ds), sin(h ds), 1 - cos(h ds)
   double one_m_eta2;       // 1 - η²
-  double ds_eta;           // ds / η
-  double tconst;           // (1 - 1/η) ds / β0
+  BendStep slice;          // s = ds
+  BendStep whole;          // s = L (orbit-only passes)
 };
 struct QuadParams {        // quadrupole (§3.3, §3.4)
   double ds, hds;          // slice length and half of it
@@ -38,8 +42,11 @@ struct SnakeParams { double qw, qx, qy, qz; };      // fixed rotation quaternion
 
 constexpr int kElemWords = sizeof(BendParams) / sizeof(double);   // largest member
 
+enum : int32_t { F_SPIN32 = 1 };   // element flag: single-precision spin arithmetic
+
 struct DevElem {
   int32_t kind, orbit, nsl, K;   // K = R_e - 1: Romberg levels minus one
+  int32_t flags, pad_;
   union {
     BendParams b;
     QuadParams q;
@@ -65,6 +72,8 @@ struct TrackArgs {
   double* partials;   // [n_reports][n_blocks][4]
   double beta0, inv_beta0, gamma0, inv_gamma0_sq, G, aperture;
   double ymax;        // largest (θ/2)² the quaternion polynomial covers
+  // surrogate tracking: lanes with fallback[j] == 0 skip the spin arithmetic
+  const int32_t* fallback;
 };
 
 }  // namespace st

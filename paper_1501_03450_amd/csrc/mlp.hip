@@ -1,0 +1,479 @@
+// Spin surrogate network: MLP n_in -> 256 -> 256 -> 256 -> 4 with SiLU
+// activations and a normalised output q = y/|y|, trained on the mean squared
+// error against one-turn quaternions with Adam.
+//
+// The two 256×256 layers run on the matrix cores: bf16 operands, fp32
+// accumulation, v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i + 16(k/8),
+// element k%8; B[k][j] in lane j + 16(k/8); D[i][j] in lane j + 16(i/4),
+// element i%4).  The n_in -> 256 and 256 -> 4 layers are a few hundred
+// multiply-adds per sample and run on the vector ALU in fp32.
+//
+// Kernels (one batch, 64 samples per workgroup of four waves):
+//   forward        all four layers fused, activations kept in LDS; when
+//                  training it stores the pre-activations (fp32) and the
+//                  activations (bf16) feature-major for the backward pass and
+//                  fuses the loss and dL/dy of the normalised output
+//   backward_data  dL/dy -> dz3 -> dz2 -> dz1 through the transposed bf16
+//                  weights, with per-workgroup partial sums of the bias and
+//                  vector-layer weight gradients
+//   weight_grad    dW2, dW3 = dzᵀ hᵀ as split-K MFMA GEMMs over the batch
+//   reduce         fixed-order sum of the partials (deterministic)
+//   adam           fp32 master weights, then the bf16 copies W and Wᵀ
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "mlp_kernels.h"
+
+namespace st {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int W = kMlpWidth;       // 256
+constexpr int TM = 64;             // samples per workgroup
+constexpr int LDA = W + 8;         // padded LDS row (bf16 elements)
+constexpr int NT = 256;            // threads per workgroup
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// acc[mt][nt] += A[64 x 256] (LDS, row stride LDA) · B'[n_base + 16 nt + j][k]
+// (global, row-major [256][256]) for the wave's 64 output columns.
+__device__ __forceinline__ void gemm_64x64(const __bf16* A, const __bf16* Bg, int n_base,
+                                           f32x4 acc[4][4], int lane) {
+  const int r = lane & 15, kb = 8 * (lane >> 4);
+#pragma unroll 2
+  for (int k0 = 0; k0 < W; k0 += 32) {
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+      a[mt] = *reinterpret_cast<const bf16x8*>(A + (mt * 16 + r) * LDA + k0 + kb);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      b[nt] = *reinterpret_cast<const bf16x8*>(Bg + (size_t)(n_base + nt * 16 + r) * W + k0 + kb);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void zero_acc(f32x4 acc[4][4]) {
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Hidden-layer epilogue: z = acc + b, h = silu(z) into LDS (bf16, row-major)
+// and, when training, zT (fp32) and hT (bf16) feature-major in HBM.
+template <bool TRAIN>
+__device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const float* bias,
+                                                __bf16* out_lds, float* zT, __bf16* hT,
+                                                int64_t ld, int64_t b0, int rows, int n_base,
+                                                int lane) {
+  const int c = lane & 15, rq = 4 * (lane >> 4);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n = n_base + nt * 16 + c;
+    const float bn = bias[n];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int m0 = mt * 16 + rq;
+      float z[4], h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        z[i] = acc[mt][nt][i] + bn;
+        h[i] = silu(z[i]);
+        out_lds[(m0 + i) * LDA + n] = (__bf16)h[i];
+      }
+      if (TRAIN) {
+        // padded samples (beyond the batch) carry zero activations
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool ok = m0 + i < rows;
+          zT[(size_t)n * ld + b0 + m0 + i] = ok ? z[i] : 0.0f;
+          hT[(size_t)n * ld + b0 + m0 + i] = (__bf16)(ok ? h[i] : 0.0f);
+        }
+      }
+    }
+  }
+}
+
+template <bool TRAIN>
+__global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
+  __shared__ __align__(16) __bf16 bufA[TM * LDA];
+  __shared__ __align__(16) __bf16 bufB[TM * LDA];
+  __shared__ float xs[TM][kMlpMaxIn];
+  __shared__ float ys[TM][4];
+  __shared__ float red[NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t B = a.batch, b0 = (int64_t)blockIdx.x * TM;
+  const int rows = (int)min((int64_t)TM, B - b0);
+  const int nin = a.n_in;
+  const float* P = a.params;
+
+  for (int i = tid; i < TM * kMlpMaxIn; i += NT) {
+    const int m = i / kMlpMaxIn, k = i % kMlpMaxIn;
+    xs[m][k] = (m < rows && k < nin) ? a.x[(b0 + m) * nin + k] : 0.0f;
+  }
+  __syncthreads();
+
+  // layer 1 (vector): thread n computes feature n for all samples
+  {
+    const int n = tid;
+    float w[kMlpMaxIn];
+#pragma unroll
+    for (int k = 0; k < kMlpMaxIn; ++k) w[k] = k < nin ? P[a.off.W1 + n * nin + k] : 0.0f;
+    const float bn = P[a.off.b1 + n];
+    for (int m = 0; m < TM; ++m) {
+      float z = bn;
+#pragma unroll
+      for (int k = 0; k < kMlpMaxIn; ++k) z = fmaf(w[k], xs[m][k], z);
+      const float h = silu(z);
+      bufA[m * LDA + n] = (__bf16)h;
+      if (TRAIN) {
+        a.zT1[(size_t)n * a.ld + b0 + m] = m < rows ? z : 0.0f;
+        a.hT1[(size_t)n * a.ld + b0 + m] = (__bf16)(m < rows ? h : 0.0f);
+      }
+    }
+  }
+  __syncthreads();
+
+  f32x4 acc[4][4];
+  // layer 2 (MFMA)
+  zero_acc(acc);
+  gemm_64x64(bufA, a.W2b, wv * 64, acc, lane);
+  hidden_epilogue<TRAIN>(acc, P + a.off.b2, bufB, a.zT2, a.hT2, a.ld, b0, rows, wv * 64, lane);
+  __syncthreads();
+  // layer 3 (MFMA)
+  zero_acc(acc);
+  gemm_64x64(bufB, a.W3b, wv * 64, acc, lane);
+  hidden_epilogue<TRAIN>(acc, P + a.off.b3, bufA, a.zT3, a.hT3, a.ld, b0, rows, wv * 64, lane);
+  __syncthreads();
+
+  // layer 4 (vector): thread t -> sample t % 64, output t / 64
+  {
+    const int m = tid & 63, j = tid >> 6;
+    const float* w4 = P + a.off.W4 + j * W;
+    float y = P[a.off.b4 + j];
+    for (int k = 0; k < W; ++k) y = fmaf(w4[k], (float)bufA[m * LDA + k], y);
+    ys[m][j] = y;
+  }
+  __syncthreads();
+
+  float l = 0.0f;
+  if (tid < TM && tid < rows) {
+    const int m = tid;
+    const float y0 = ys[m][0], y1 = ys[m][1], y2 = ys[m][2], y3 = ys[m][3];
+    const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2 + y3 * y3);
+    const float inv = 1.0f / ny;
+    const float q[4] = {y0 * inv, y1 * inv, y2 * inv, y3 * inv};
+    if (!TRAIN) {
+      for (int j = 0; j < 4; ++j) a.q_out[(b0 + m) * 4 + j] = q[j];
+    } else {
+      const float* t = a.target + (b0 + m) * 4;
+      float dq[4], qd = 0.0f;
+      for (int j = 0; j < 4; ++j) {
+        const float d = q[j] - t[j];
+        l += d * d;
+        dq[j] = 2.0f * d * a.inv_loss_norm;
+        qd += q[j] * dq[j];
+      }
+      for (int j = 0; j < 4; ++j) a.dy[(b0 + m) * 4 + j] = (dq[j] - q[j] * qd) * inv;
+    }
+  }
+  if (TRAIN) {
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+    if (lane == 0) red[wv] = l;
+    __syncthreads();
+    if (tid == 0) a.loss_part[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * a.inv_loss_norm;
+  }
+}
+
+// Backward through the layers for one tile of samples.
+__global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) {
+  __shared__ __align__(16) __bf16 bufA[TM * LDA];
+  __shared__ __align__(16) __bf16 bufB[TM * LDA];
+  __shared__ float xs[TM][kMlpMaxIn];
+  __shared__ float dys[TM][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t B = a.batch, b0 = (int64_t)blockIdx.x * TM;
+  const int rows = (int)min((int64_t)TM, B - b0);
+  const int nin = a.n_in;
+  const float* P = a.params;
+  const int blk = blockIdx.x;
+
+  for (int i = tid; i < TM * kMlpMaxIn; i += NT) {
+    const int m = i / kMlpMaxIn, k = i % kMlpMaxIn;
+    xs[m][k] = (m < rows && k < nin) ? a.x[(b0 + m) * nin + k] : 0.0f;
+  }
+  for (int i = tid; i < TM * 4; i += NT) {
+    const int m = i / 4, j = i % 4;
+    dys[m][j] = m < rows ? a.dy[(b0 + m) * 4 + j] : 0.0f;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    float s = 0.0f;
+    for (int m = 0; m < rows; ++m) s += dys[m][tid];
+    a.gpart_b4[(size_t)blk * 4 + tid] = s;
+  }
+
+  // dz3 = (dy W4) ⊙ silu'(z3); dW4 and db3 partials
+  {
+    const int k = tid;
+    const float w0 = P[a.off.W4 + 0 * W + k], w1 = P[a.off.W4 + 1 * W + k];
+    const float w2 = P[a.off.W4 + 2 * W + k], w3 = P[a.off.W4 + 3 * W + k];
+    float gw[4] = {0.f, 0.f, 0.f, 0.f}, gb = 0.0f;
+    for (int m = 0; m < TM; ++m) {
+      float dz = 0.0f;
+      if (m < rows) {
+        const float z = a.zT3[(size_t)k * a.ld + b0 + m];
+        const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
+        dz = dh * dsilu(z);
+        const float h = silu(z);
+        gw[0] = fmaf(dys[m][0], h, gw[0]);
+        gw[1] = fmaf(dys[m][1], h, gw[1]);
+        gw[2] = fmaf(dys[m][2], h, gw[2]);
+        gw[3] = fmaf(dys[m][3], h, gw[3]);
+        gb += dz;
+      }
+      a.dzT3[(size_t)k * a.ld + b0 + m] = (__bf16)dz;
+      bufA[m * LDA + k] = (__bf16)dz;
+    }
+    for (int j = 0; j < 4; ++j) a.gpart_W4[((size_t)blk * 4 + j) * W + k] = gw[j];
+    a.gpart_b3[(size_t)blk * W + k] = gb;
+  }
+  __syncthreads();
+
+  f32x4 acc[4][4];
+  const int c = lane & 15, rq = 4 * (lane >> 4);
+  // dz2 = (dz3 W3) ⊙ silu'(z2)
+  zero_acc(acc);
+  gemm_64x64(bufA, a.W3Tb, wv * 64, acc, lane);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n = wv * 64 + nt * 16 + c;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int m0 = mt * 16 + rq;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float dz = 0.0f;
+        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zT2[(size_t)n * a.ld + b0 + m0 + i]);
+        a.dzT2[(size_t)n * a.ld + b0 + m0 + i] = (__bf16)dz;
+        bufB[(m0 + i) * LDA + n] = (__bf16)dz;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    float s = 0.0f;
+    for (int m = 0; m < rows; ++m) s += (float)bufB[m * LDA + tid];
+    a.gpart_b2[(size_t)blk * W + tid] = s;
+  }
+  // dz1 = (dz2 W2) ⊙ silu'(z1)
+  zero_acc(acc);
+  gemm_64x64(bufB, a.W2Tb, wv * 64, acc, lane);
+  __syncthreads();   // bufA is reused below
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n = wv * 64 + nt * 16 + c;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int m0 = mt * 16 + rq;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float dz = 0.0f;
+        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zT1[(size_t)n * a.ld + b0 + m0 + i]);
+        bufA[(m0 + i) * LDA + n] = (__bf16)dz;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int n = tid;
+    float gw[kMlpMaxIn], gb = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMlpMaxIn; ++k) gw[k] = 0.0f;
+    for (int m = 0; m < rows; ++m) {
+      const float dz = (float)bufA[m * LDA + n];
+      gb += dz;
+#pragma unroll
+      for (int k = 0; k < kMlpMaxIn; ++k) gw[k] = fmaf(dz, xs[m][k], gw[k]);
+    }
+    for (int k = 0; k < nin; ++k) a.gpart_W1[((size_t)blk * W + n) * nin + k] = gw[k];
+    a.gpart_b1[(size_t)blk * W + n] = gb;
+  }
+}
+
+// dW[n][k] = Σ_b dzT[n][b] hT[k][b] for a 64×64 tile and one batch chunk.
+// blockIdx.x: tile (16 per matrix), blockIdx.y: matrix (0: W2, 1: W3),
+// blockIdx.z: batch split.
+__global__ void __launch_bounds__(NT) mlp_weight_grad_kernel(const MlpArgs a) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tile = blockIdx.x, which = blockIdx.y, split = blockIdx.z;
+  const __bf16* dzT = which == 0 ? a.dzT2 : a.dzT3;
+  const __bf16* hT = which == 0 ? a.hT1 : a.hT2;
+  float* out = (which == 0 ? a.gpart_W2 : a.gpart_W3) + (size_t)split * W * W;
+  const int n0 = (tile / 4) * 64 + (wv >> 1) * 32, k0 = (tile % 4) * 64 + (wv & 1) * 32;
+  const int64_t ld = a.ld;
+  const int64_t chunk = a.split_chunk;
+  const int64_t bs = (int64_t)split * chunk, be = min(ld, bs + chunk);
+  const int r = lane & 15, kb = 8 * (lane >> 4);
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t b = bs; b < be; b += 32) {
+    bf16x8 av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      av[i] = *reinterpret_cast<const bf16x8*>(dzT + (size_t)(n0 + i * 16 + r) * ld + b + kb);
+      bv[i] = *reinterpret_cast<const bf16x8*>(hT + (size_t)(k0 + i * 16 + r) * ld + b + kb);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+  const int c = lane & 15, rq = 4 * (lane >> 4);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        out[(size_t)(n0 + i * 16 + rq + e) * W + k0 + j * 16 + c] = acc[i][j][e];
+}
+
+// out[i] = Σ_r part[r][i] in a fixed order.
+__global__ void __launch_bounds__(256) sum_partials_kernel(const float* part, int64_t len, int parts,
+                                                           float* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= len) return;
+  float s = 0.0f;
+  for (int r = 0; r < parts; ++r) s += part[(size_t)r * len + i];
+  out[i] = s;
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(const MlpArgs a, float lr, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n_params) return;
+  const float g = a.grad[i];
+  const float m = fmaf(kAdamBeta1, a.adam_m[i] - g, g);      // β1 m + (1 - β1) g
+  const float v = fmaf(kAdamBeta2, a.adam_v[i] - g * g, g * g);
+  a.adam_m[i] = m;
+  a.adam_v[i] = v;
+  const float p = a.params_rw[i] - lr * (m * c1) / (sqrtf(v * c2) + kAdamEps);
+  a.params_rw[i] = p;
+  if (i >= a.off.W2 && i < a.off.W2 + W * W) {
+    const int64_t e = i - a.off.W2, n = e / W, k = e % W;
+    a.W2b_rw[n * W + k] = (__bf16)p;
+    a.W2Tb_rw[k * W + n] = (__bf16)p;
+  } else if (i >= a.off.W3 && i < a.off.W3 + W * W) {
+    const int64_t e = i - a.off.W3, n = e / W, k = e % W;
+    a.W3b_rw[n * W + k] = (__bf16)p;
+    a.W3Tb_rw[k * W + n] = (__bf16)p;
+  }
+}
+
+// Rewrite the bf16 copies from the master weights (after a parameter upload).
+__global__ void __launch_bounds__(256) refresh_bf16_kernel(const MlpArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= W * W) return;
+  const int64_t n = e / W, k = e % W;
+  const float p2 = a.params[a.off.W2 + e], p3 = a.params[a.off.W3 + e];
+  a.W2b_rw[n * W + k] = (__bf16)p2;
+  a.W2Tb_rw[k * W + n] = (__bf16)p2;
+  a.W3b_rw[n * W + k] = (__bf16)p3;
+  a.W3Tb_rw[k * W + n] = (__bf16)p3;
+}
+
+}  // namespace
+
+int mlp_tile() { return TM; }
+
+hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s) {
+  const dim3 grid((unsigned)((a.batch + TM - 1) / TM)), block(NT);
+  if (train) hipLaunchKernelGGL(mlp_forward_kernel<true>, grid, block, 0, s, a);
+  else       hipLaunchKernelGGL(mlp_forward_kernel<false>, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.batch + TM - 1) / TM);
+  hipLaunchKernelGGL(mlp_backward_data_kernel, dim3(nb), dim3(NT), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(16, 2, (unsigned)a.n_splits), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, part,
+                     len, parts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.n_params + 255) / 256)), dim3(256), 0, s, a, lr,
+                     c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_bf16(const MlpArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(refresh_bf16_kernel, dim3((W * W + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace st
+
+namespace st {
+namespace {
+
+__global__ void __launch_bounds__(256) features_kernel(const double* z, int64_t n, FeatureMap f,
+                                                       int n_in, float* x) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  for (int i = 0; i < 6 && i < n_in; ++i)
+    x[j * n_in + i] = (float)((z[(size_t)i * n + j] - f.center[i]) * f.inv_scale[i]);
+  if (n_in == 7) x[j * n_in + 6] = (float)f.extra;
+}
+
+__global__ void __launch_bounds__(256) targets_kernel(const double* q, int64_t n, double r0, double r1,
+                                                      double r2, double r3, float* t) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const double w = q[j], x = q[n + j], y = q[2 * n + j], z = q[3 * n + j];
+  const double s = (w * r0 + x * r1 + y * r2 + z * r3) < 0.0 ? -1.0 : 1.0;
+  t[j * 4 + 0] = (float)(s * w);
+  t[j * 4 + 1] = (float)(s * x);
+  t[j * 4 + 2] = (float)(s * y);
+  t[j * 4 + 3] = (float)(s * z);
+}
+
+}  // namespace
+
+hipError_t launch_features(const double* z, int64_t n, const FeatureMap& f, int n_in, float* x,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, n, f,
+                     n_in, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const double* q, int64_t n, const double* ref, float* t, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q, n, ref[0],
+                     ref[1], ref[2], ref[3], t);
+  return hipGetLastError();
+}
+
+}  // namespace st

@@ -1,0 +1,337 @@
+// C ABI of the spin surrogate network (see include/spintrack.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mlp_kernels.h"
+#include "spintrack.h"
+
+struct st_mlp {
+  int device = 0;
+  int n_in = 0;
+  std::string err;
+  st::MlpOffsets off{};
+  int64_t n_params = 0;
+  int64_t step = 0;                 // Adam steps taken
+  float* params = nullptr;          // fp32 master weights
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* grad = nullptr;
+  __bf16* wb = nullptr;             // W2, W3, W2ᵀ, W3ᵀ in bf16 (4 × 256²)
+  // training scratch, sized for the largest batch seen
+  int64_t cap_ld = 0;
+  std::vector<void*> scratch;
+  float *zT[3] = {nullptr, nullptr, nullptr};
+  __bf16 *hT[3] = {nullptr, nullptr, nullptr};
+  __bf16 *dzT[2] = {nullptr, nullptr};
+  float *dy = nullptr, *loss_part = nullptr;
+  float *gW1 = nullptr, *gb1 = nullptr, *gb2 = nullptr, *gb3 = nullptr, *gW4 = nullptr, *gb4 = nullptr;
+  float *gW2 = nullptr, *gW3 = nullptr;
+};
+
+namespace {
+
+constexpr int kSplits = 64;
+
+struct DeviceGuard {
+  int old = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+  }
+};
+
+st_status fail(st_mlp* m, st_status s, const std::string& msg) {
+  if (m) m->err = msg;
+  return s;
+}
+
+st_status hip_fail(st_mlp* m, hipError_t e, const char* what) {
+  return fail(m, ST_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): a counter-based 64-bit generator.
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+void free_scratch(st_mlp* m) {
+  for (void* p : m->scratch) (void)hipFree(p);
+  m->scratch.clear();
+  m->cap_ld = 0;
+}
+
+template <class T>
+hipError_t alloc(st_mlp* m, T** p, size_t count) {
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) m->scratch.push_back(*p);
+  return e;
+}
+
+st_status ensure_scratch(st_mlp* m, int64_t ld) {
+  if (ld <= m->cap_ld) return ST_OK;
+  free_scratch(m);
+  const int64_t W = st::kMlpWidth;
+  const int64_t nb = ld / st::mlp_tile();
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = alloc(m, &m->zT[l], (size_t)(W * ld));
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = alloc(m, &m->hT[l], (size_t)(W * ld));
+  for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->dzT[l], (size_t)(W * ld));
+  if (e == hipSuccess) e = alloc(m, &m->dy, (size_t)(ld * 4));
+  if (e == hipSuccess) e = alloc(m, &m->loss_part, (size_t)nb);
+  if (e == hipSuccess) e = alloc(m, &m->gW1, (size_t)(nb * W * m->n_in));
+  if (e == hipSuccess) e = alloc(m, &m->gb1, (size_t)(nb * W));
+  if (e == hipSuccess) e = alloc(m, &m->gb2, (size_t)(nb * W));
+  if (e == hipSuccess) e = alloc(m, &m->gb3, (size_t)(nb * W));
+  if (e == hipSuccess) e = alloc(m, &m->gW4, (size_t)(nb * 4 * W));
+  if (e == hipSuccess) e = alloc(m, &m->gb4, (size_t)(nb * 4));
+  if (e == hipSuccess) e = alloc(m, &m->gW2, (size_t)(kSplits * W * W));
+  if (e == hipSuccess) e = alloc(m, &m->gW3, (size_t)(kSplits * W * W));
+  if (e != hipSuccess) {
+    free_scratch(m);
+    return fail(m, ST_ENOMEM, std::string("training scratch: ") + hipGetErrorString(e));
+  }
+  m->cap_ld = ld;
+  return ST_OK;
+}
+
+st::MlpArgs base_args(st_mlp* m) {
+  st::MlpArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const int64_t W2 = (int64_t)st::kMlpWidth * st::kMlpWidth;
+  a.n_in = m->n_in;
+  a.off = m->off;
+  a.n_params = m->n_params;
+  a.params = m->params;
+  a.params_rw = m->params;
+  a.W2b = m->wb;
+  a.W3b = m->wb + W2;
+  a.W2Tb = m->wb + 2 * W2;
+  a.W3Tb = m->wb + 3 * W2;
+  a.W2b_rw = m->wb;
+  a.W3b_rw = m->wb + W2;
+  a.W2Tb_rw = m->wb + 2 * W2;
+  a.W3Tb_rw = m->wb + 3 * W2;
+  a.grad = m->grad;
+  a.adam_m = m->adam_m;
+  a.adam_v = m->adam_v;
+  return a;
+}
+
+// Forward, backward and the gradient reduction for one batch into m->grad.
+st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t batch, float* d_loss,
+                           hipStream_t s) {
+  const int64_t tile = st::mlp_tile();
+  const int64_t ld = (batch + tile - 1) / tile * tile;
+  st_status st = ensure_scratch(m, ld);
+  if (st != ST_OK) return st;
+  st::MlpArgs a = base_args(m);
+  a.batch = batch;
+  a.ld = ld;
+  a.x = x;
+  a.target = t;
+  a.inv_loss_norm = 1.0f / (float)batch;
+  a.loss_part = m->loss_part;
+  a.dy = m->dy;
+  a.zT1 = m->zT[0]; a.zT2 = m->zT[1]; a.zT3 = m->zT[2];
+  a.hT1 = m->hT[0]; a.hT2 = m->hT[1]; a.hT3 = m->hT[2];
+  a.dzT2 = m->dzT[0]; a.dzT3 = m->dzT[1];
+  a.gpart_W1 = m->gW1; a.gpart_b1 = m->gb1; a.gpart_b2 = m->gb2; a.gpart_b3 = m->gb3;
+  a.gpart_W4 = m->gW4; a.gpart_b4 = m->gb4; a.gpart_W2 = m->gW2; a.gpart_W3 = m->gW3;
+  a.n_splits = kSplits;
+  a.split_chunk = ((ld + kSplits - 1) / kSplits + 31) / 32 * 32;
+  const int nb = (int)(ld / tile);
+  const int64_t W = st::kMlpWidth;
+  hipError_t e;
+  if ((e = st::launch_mlp_forward(a, true, s)) != hipSuccess) return hip_fail(m, e, "forward");
+  if ((e = st::launch_mlp_backward(a, s)) != hipSuccess) return hip_fail(m, e, "backward");
+  const st::MlpOffsets& o = m->off;
+  struct { const float* part; int64_t len; int parts; int64_t off; } red[] = {
+      {m->gW1, W * m->n_in, nb, o.W1}, {m->gb1, W, nb, o.b1}, {m->gW2, W * W, kSplits, o.W2},
+      {m->gb2, W, nb, o.b2}, {m->gW3, W * W, kSplits, o.W3}, {m->gb3, W, nb, o.b3},
+      {m->gW4, 4 * W, nb, o.W4}, {m->gb4, 4, nb, o.b4}};
+  for (auto& r : red)
+    if ((e = st::launch_sum_partials(r.part, r.len, r.parts, m->grad + r.off, s)) != hipSuccess)
+      return hip_fail(m, e, "gradient reduction");
+  if (d_loss && (e = st::launch_sum_partials(m->loss_part, 1, nb, d_loss, s)) != hipSuccess)
+    return hip_fail(m, e, "loss reduction");
+  return ST_OK;
+}
+
+st_status check_batch(st_mlp* m, const void* x, const void* t, int64_t batch) {
+  if (!m) return ST_EINVAL;
+  if (batch <= 0 || batch > (int64_t)1 << 26) return fail(m, ST_EINVAL, "batch must be in 1..2^26");
+  if (!x || !t) return fail(m, ST_EINVAL, "inputs or targets are NULL");
+  return ST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+st_status st_mlp_create(st_mlp** out, int device, int32_t n_in, int32_t width, uint64_t seed) {
+  if (!out) return ST_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return ST_EINVAL;
+  if (n_in < 1 || n_in > st::kMlpMaxIn || width != st::kMlpWidth) return ST_EINVAL;
+  st_mlp* m = new (std::nothrow) st_mlp();
+  if (!m) return ST_ENOMEM;
+  m->device = device;
+  m->n_in = n_in;
+  m->off = st::mlp_offsets(n_in);
+  m->n_params = m->off.total;
+  std::vector<float> p((size_t)m->n_params, 0.0f);
+  uint64_t ctr = seed * 0x100000001B3ull;
+  auto fill = [&](int64_t off, int64_t count, int fan_in) {
+    const double lim = 1.0 / std::sqrt((double)fan_in);
+    for (int64_t i = 0; i < count; ++i) {
+      const double u = (double)(splitmix64(ctr++) >> 11) * 0x1.0p-53;   // [0, 1)
+      p[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * lim);
+    }
+  };
+  const int64_t W = st::kMlpWidth;
+  fill(m->off.W1, W * n_in, n_in);
+  fill(m->off.W2, W * W, (int)W);
+  fill(m->off.W3, W * W, (int)W);
+  fill(m->off.W4, 4 * W, (int)W);
+  DeviceGuard g(device);
+  hipError_t e = hipSuccess;
+  const size_t nbytes = (size_t)m->n_params * sizeof(float);
+  if (e == hipSuccess) e = hipMalloc(&m->params, nbytes);
+  if (e == hipSuccess) e = hipMalloc(&m->adam_m, nbytes);
+  if (e == hipSuccess) e = hipMalloc(&m->adam_v, nbytes);
+  if (e == hipSuccess) e = hipMalloc(&m->grad, nbytes);
+  if (e == hipSuccess) e = hipMalloc(&m->wb, (size_t)4 * W * W * sizeof(__bf16));
+  if (e == hipSuccess) e = hipMemcpy(m->params, p.data(), nbytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->adam_m, 0, nbytes);
+  if (e == hipSuccess) e = hipMemset(m->adam_v, 0, nbytes);
+  if (e == hipSuccess) e = st::launch_refresh_bf16(base_args(m), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    st_mlp_destroy(m);
+    return ST_ENOMEM;
+  }
+  *out = m;
+  return ST_OK;
+}
+
+st_status st_mlp_destroy(st_mlp* m) {
+  if (!m) return ST_OK;
+  {
+    DeviceGuard g(m->device);
+    free_scratch(m);
+    for (void* p : {(void*)m->params, (void*)m->adam_m, (void*)m->adam_v, (void*)m->grad, (void*)m->wb})
+      if (p) (void)hipFree(p);
+  }
+  delete m;
+  return ST_OK;
+}
+
+const char* st_mlp_last_error(const st_mlp* m) { return m ? m->err.c_str() : "null network"; }
+
+}  // extern "C"
+
+int st_mlp_device_of(const st_mlp* m) { return m->device; }
+int st_mlp_inputs_of(const st_mlp* m) { return m->n_in; }
+
+extern "C" {
+
+st_status st_mlp_params(st_mlp* m, float* h_get, const float* h_set, int64_t* n_params) {
+  if (!m) return ST_EINVAL;
+  if (n_params) *n_params = m->n_params;
+  DeviceGuard g(m->device);
+  const size_t nbytes = (size_t)m->n_params * sizeof(float);
+  hipError_t e;
+  if (h_get && (e = hipMemcpy(h_get, m->params, nbytes, hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(m, e, "read parameters");
+  if (h_set) {
+    if ((e = hipMemcpy(m->params, h_set, nbytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(m, e, "write parameters");
+    if ((e = st::launch_refresh_bf16(base_args(m), nullptr)) != hipSuccess)
+      return hip_fail(m, e, "refresh bf16 weights");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(m, e, "synchronise");
+  }
+  return ST_OK;
+}
+
+st_status st_mlp_gradient(st_mlp* m, const float* d_x, const float* d_t, int64_t batch,
+                          float* d_grad, float* d_loss, void* stream) {
+  st_status st = check_batch(m, d_x, d_t, batch);
+  if (st != ST_OK) return st;
+  if (!d_grad) return fail(m, ST_EINVAL, "gradient output is NULL");
+  DeviceGuard g(m->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = compute_gradient(m, d_x, d_t, batch, d_loss, s)) != ST_OK) return st;
+  hipError_t e = hipMemcpyAsync(d_grad, m->grad, (size_t)m->n_params * sizeof(float),
+                                hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(m, e, "copy gradient");
+  return ST_OK;
+}
+
+st_status st_mlp_train_step(st_mlp* m, const float* d_x, const float* d_t, int64_t batch, float lr,
+                            float* d_loss, void* stream) {
+  st_status st = check_batch(m, d_x, d_t, batch);
+  if (st != ST_OK) return st;
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(m, ST_EINVAL, "learning rate must be > 0");
+  DeviceGuard g(m->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = compute_gradient(m, d_x, d_t, batch, d_loss, s)) != ST_OK) return st;
+  m->step += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)st::kAdamBeta1, (double)m->step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)st::kAdamBeta2, (double)m->step)));
+  hipError_t e = st::launch_adam(base_args(m), lr, c1, c2, s);
+  if (e != hipSuccess) return hip_fail(m, e, "adam");
+  return ST_OK;
+}
+
+st_status st_mlp_infer(st_mlp* m, const float* d_x, float* d_q, int64_t n, void* stream) {
+  if (!m) return ST_EINVAL;
+  if (n < 0) return fail(m, ST_EINVAL, "negative count");
+  if (n == 0) return ST_OK;
+  if (!d_x || !d_q) return fail(m, ST_EINVAL, "inputs or outputs are NULL");
+  DeviceGuard g(m->device);
+  st::MlpArgs a = base_args(m);
+  a.batch = n;
+  a.x = d_x;
+  a.q_out = d_q;
+  hipError_t e = st::launch_mlp_forward(a, false, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(m, e, "inference");
+  return ST_OK;
+}
+
+st_status st_mlp_features(st_mlp* m, const double* d_z, int64_t n, const double* center,
+                          const double* inv_scale, double extra, float* d_x, void* stream) {
+  if (!m) return ST_EINVAL;
+  if (n < 0 || (n > 0 && (!d_z || !d_x)) || !center || !inv_scale)
+    return fail(m, ST_EINVAL, "bad feature arguments");
+  st::FeatureMap f;
+  for (int i = 0; i < 6; ++i) { f.center[i] = center[i]; f.inv_scale[i] = inv_scale[i]; }
+  f.extra = extra;
+  DeviceGuard g(m->device);
+  hipError_t e = st::launch_features(d_z, n, f, m->n_in, d_x, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(m, e, "features");
+  return ST_OK;
+}
+
+st_status st_mlp_targets(st_mlp* m, const double* d_q, int64_t n, const double* ref, float* d_t,
+                         void* stream) {
+  if (!m) return ST_EINVAL;
+  if (n < 0 || (n > 0 && (!d_q || !d_t)) || !ref) return fail(m, ST_EINVAL, "bad target arguments");
+  DeviceGuard g(m->device);
+  hipError_t e = st::launch_targets(d_q, n, ref, d_t, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(m, e, "targets");
+  return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Spin surrogate network: shared constants, kernel arguments and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace st {
+
+constexpr int kMlpWidth = 256;
+constexpr int kMlpMaxIn = 8;
+constexpr float kAdamBeta1 = 0.9f, kAdamBeta2 = 0.999f, kAdamEps = 1e-8f;
+
+// Offsets of the tensors in the flat parameter (and gradient) vector:
+// W1 [256][n_in], b1 [256], W2 [256][256], b2, W3 [256][256], b3, W4 [4][256], b4 [4].
+struct MlpOffsets {
+  int64_t W1, b1, W2, b2, W3, b3, W4, b4, total;
+};
+
+inline MlpOffsets mlp_offsets(int n_in) {
+  MlpOffsets o;
+  const int64_t w = kMlpWidth;
+  o.W1 = 0;
+  o.b1 = o.W1 + w * n_in;
+  o.W2 = o.b1 + w;
+  o.b2 = o.W2 + w * w;
+  o.W3 = o.b2 + w;
+  o.b3 = o.W3 + w * w;
+  o.W4 = o.b3 + w;
+  o.b4 = o.W4 + 4 * w;
+  o.total = o.b4 + 4;
+  return o;
+}
+
+struct MlpArgs {
+  int64_t batch;          // samples
+  int64_t ld;             // padded batch: leading dimension of the feature-major arrays
+  int n_in;
+  MlpOffsets off;
+  int64_t n_params;
+  const float* params;    // fp32 master weights (flat)
+  float* params_rw;
+  const __bf16* W2b;      // bf16 [256][256] copies of W2, W3 and their transposes
+  const __bf16* W3b;
+  const __bf16* W2Tb;
+  const __bf16* W3Tb;
+  __bf16* W2b_rw;
+  __bf16* W3b_rw;
+  __bf16* W2Tb_rw;
+  __bf16* W3Tb_rw;
+  const float* x;         // [batch][n_in]
+  const float* target;    // [batch][4]
+  float* q_out;           // [batch][4]
+  float* dy;              // [batch][4]
+  float inv_loss_norm;    // 1/batch
+  float* loss_part;       // [blocks]
+  float* zT1;             // [256][ld] pre-activations
+  float* zT2;
+  float* zT3;
+  __bf16* hT1;            // [256][ld] activations
+  __bf16* hT2;
+  __bf16* hT3;
+  __bf16* dzT2;           // [256][ld] gradients at the pre-activations
+  __bf16* dzT3;
+  float* gpart_W1;        // per-block partial gradients
+  float* gpart_b1;
+  float* gpart_b2;
+  float* gpart_b3;
+  float* gpart_W4;
+  float* gpart_b4;
+  float* gpart_W2;        // [splits][256][256]
+  float* gpart_W3;
+  int n_splits;
+  int64_t split_chunk;    // samples per split (multiple of 32)
+  float* grad;            // flat gradient, same layout as params
+  float* adam_m;
+  float* adam_v;
+};
+
+// Network inputs from coordinates: (z_i - center_i) * inv_scale_i, then extra.
+struct FeatureMap {
+  double center[6], inv_scale[6], extra;
+};
+
+int mlp_tile();
+hipError_t launch_features(const double* z, int64_t n, const FeatureMap& f, int n_in, float* x,
+                           hipStream_t s);
+hipError_t launch_targets(const double* q, int64_t n, const double* ref, float* t, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s);
+hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s);
+hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, hipStream_t s);
+hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s);
+hipError_t launch_refresh_bf16(const MlpArgs& a, hipStream_t s);
+
+}  // namespace st

@@ -1,4 +1,4 @@
-// Persistent FP64 tracking kernel: one lane per particle, all turns and all
+// Persistent tracking kernel: one lane per particle, all turns and all
 // elements of the ring in one launch, state in registers.
 //
 // Per element (wave-uniform walk of the lattice index sequence):
@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fp64_maps.h"
+#include "mixed_spin.h"
 #include "track_kernels.h"
 
 namespace st {
@@ -34,6 +35,7 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
   d.orbit = p->orbit;
   d.nsl = p->nsl;
   d.K = p->K;
+  d.flags = p->flags;
 #pragma unroll
   for (int i = 0; i < kElemWords; ++i) d.v[i] = p->v[i];
   return d;
@@ -45,9 +47,11 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
 
 // Romberg spin integration through one thick element, fused with its orbit
 // slices (KIND: 0 sector bend, 1 MK quadrupole focusing in x, 3 MK
-// quadrupole focusing in y, 2 DKD quadrupole).  Returns the normalised
+// quadrupole focusing in y, 2 DKD quadrupole).  In the MIXED kernel,
+// elements flagged F_SPIN32 use single-precision edge quaternions and
+// compensated single-precision level products.  Returns the normalised
 // element quaternion.
-template <int NT, int KIND>
+template <int NT, int KIND, bool MIXED>
 __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, double& Px, double& Y,
                                               double& Py, double& T, const Particle& p,
                                               const TrackArgs& a) {
@@ -55,8 +59,10 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   const int N = el.nsl;
   const int K = el.K;
   const double ds = KIND == 0 ? el.b.ds : el.q.ds;
+  const bool spin32 = MIXED && (el.flags & F_SPIN32);
   // running products of the Romberg levels: level m keeps every 2^m-th edge
   Quat Q0 = qident(), Q1 = qident(), Q2 = qident(), Q3 = qident();
+  QuatC C0 = qc_ident(), C1 = qc_ident(), C2 = qc_ident(), C3 = qc_ident();
 
   // bend invariants of this particle: Py and Pt do not change in a bend
   double Pa2 = p.P2() - Py * Py;
@@ -77,7 +83,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   for (int j = 0; j <= N; ++j) {
     if (j > 0) {
       if (KIND == 0) {
-        bend_step(el.b, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
+        bend_step(el.b, el.b.slice, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
       } else {
         if (KIND == 1) {
           mk_linear(mc, X, Px, Y, Py, T, p);
@@ -105,23 +111,48 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
     // rotation about Ω by 2^m times the finest angle, i.e. the finest
     // quaternion squared m times.
     const double f = ((j == 0 || j == N) ? 0.5 : 1.0) * ds;
-    double c, sfac;
-    rot_half_angle<NT>(0.25 * f * f * om2, a.ymax, c, sfac);
-    const double g = sfac * f;
-    Quat qb = {c, g * ox, g * oy, g * oz};
-    Q0 = qmul(qb, Q0);
-    if (K >= 1 && (j & 1) == 0) {
-      qb = qsquare(qb);
-      Q1 = qmul(qb, Q1);
-      if (K >= 2 && (j & 3) == 0) {
+    if (spin32) {
+      float d, sf;
+      rot_deviation_f32(0.25 * f * f * om2, d, sf);
+      float vx = sf * (float)(f * ox), vy = sf * (float)(f * oy), vz = sf * (float)(f * oz);
+      qc_update(C0, d, vx, vy, vz);
+      if (K >= 1 && (j & 1) == 0) {
+        dev_square(d, vx, vy, vz);
+        qc_update(C1, d, vx, vy, vz);
+        if (K >= 2 && (j & 3) == 0) {
+          dev_square(d, vx, vy, vz);
+          qc_update(C2, d, vx, vy, vz);
+          if (K >= 3 && (j & 7) == 0) {
+            dev_square(d, vx, vy, vz);
+            qc_update(C3, d, vx, vy, vz);
+          }
+        }
+      }
+    } else {
+      double c, sfac;
+      rot_half_angle<NT>(0.25 * f * f * om2, a.ymax, c, sfac);
+      const double g = sfac * f;
+      Quat qb = {c, g * ox, g * oy, g * oz};
+      Q0 = qmul(qb, Q0);
+      if (K >= 1 && (j & 1) == 0) {
         qb = qsquare(qb);
-        Q2 = qmul(qb, Q2);
-        if (K >= 3 && (j & 7) == 0) {
+        Q1 = qmul(qb, Q1);
+        if (K >= 2 && (j & 3) == 0) {
           qb = qsquare(qb);
-          Q3 = qmul(qb, Q3);
+          Q2 = qmul(qb, Q2);
+          if (K >= 3 && (j & 7) == 0) {
+            qb = qsquare(qb);
+            Q3 = qmul(qb, Q3);
+          }
         }
       }
     }
+  }
+  if (spin32) {
+    Q0 = qc_to_double(C0);
+    if (K >= 1) Q1 = qc_to_double(C1);
+    if (K >= 2) Q2 = qc_to_double(C2);
+    if (K >= 3) Q3 = qc_to_double(C3);
   }
 
   // Romberg tableau (§4.3 eq. romberg) with levels indexed by stride 2^m:
@@ -142,6 +173,42 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   return {Q0.w * inv, Q0.x * inv, Q0.y * inv, Q0.z * inv};
 }
 
+// Orbit only through a thick element (surrogate tracking, no spin): the
+// sector bend is an exact flow and is crossed in one step; quadrupoles keep
+// their slices.
+template <int KIND>
+__device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double& Px, double& Y,
+                                            double& Py, double& T, const Particle& p,
+                                            const TrackArgs& a) {
+  if (KIND == 0) {
+    const double Pa2 = p.P2() - Py * Py;
+    const double ps2 = fma(-Px, Px, Pa2);
+    double r = rsqrt_nr(ps2);
+    double W = ps2 * r;
+    double wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
+    bend_step(el.b, el.b.whole, X, Px, Py, Y, T, W, r, wme, Pa2, rcp_nr(Pa2), p);
+    return;
+  }
+  MKConst mc;
+  if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+  for (int j = 0; j < el.nsl; ++j) {
+    if (KIND == 1) {
+      mk_linear(mc, X, Px, Y, Py, T, p);
+      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
+      mk_linear(mc, X, Px, Y, Py, T, p);
+    } else if (KIND == 3) {
+      mk_linear(mc, Y, Py, X, Px, T, p);
+      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
+      mk_linear(mc, Y, Py, X, Px, T, p);
+    } else {
+      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+      Px = fma(-el.q.k1ds, X, Px);
+      Py = fma(el.q.k1ds, Y, Py);
+      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+    }
+  }
+}
+
 template <int NT>
 __device__ __forceinline__ Quat thin_element(const DevElem& e, double X, double& Px, double Y,
                                              double& Py, const Particle& p, const TrackArgs& a) {
@@ -154,10 +221,11 @@ __device__ __forceinline__ Quat thin_element(const DevElem& e, double X, double&
   double by = fma(e.t.k1l, X, 0.5 * e.t.k2l * (X * X - Y * Y));
   double ox, oy, oz;
   omega_straight(bx, by, Px, Py, r, p, ox, oy, oz);
-  double c, sfac;
-  rot_half_angle<NT>(0.25 * fma(ox, ox, fma(oy, oy, oz * oz)), a.ymax, c, sfac);
+  const double y = 0.25 * fma(ox, ox, fma(oy, oy, oz * oz));
   Px -= fma(hk1, X, 0.5 * hk2 * (X * X - Y * Y));
   Py += fma(hk1, Y, hk2 * X * Y);
+  double c, sfac;
+  rot_half_angle<NT>(y, a.ymax, c, sfac);
   return {c, sfac * ox, sfac * oy, sfac * oz};
 }
 
@@ -167,9 +235,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int NT>
+// SURR: surrogate tracking; lanes with fallback[j] == 0 leave the spin to the
+// network (the caller rotates it), and waves without a fallback lane skip the
+// spin arithmetic altogether.
+template <int NT, bool MIXED, bool SURR>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ST_WAVES_PER_EU)))
-track_fp64_kernel(const TrackArgs a) {
+track_kernel(const TrackArgs a) {
   __shared__ double red[kBlock / 64][4];
   // Cold per-lane data in LDS: the spin (touched once per turn) and the
   // orbit at the current element's entrance (read back only on a loss).
@@ -190,6 +261,7 @@ track_fp64_kernel(const TrackArgs a) {
   }
   const Particle p = make_particle(Pt, a);
   Quat qturn = qident();
+  const bool spin_lane = !SURR || (valid && a.fallback[j] != 0);
   // The lattice is read-only for the whole launch: reading it through the
   // constant address space lets the uniform loads go through the scalar cache.
   const ConstElem* tab = (const ConstElem*)(a.tab);
@@ -214,14 +286,29 @@ track_fp64_kernel(const TrackArgs a) {
       cold[3][tid] = X; cold[4][tid] = Px; cold[5][tid] = Y; cold[6][tid] = Py; cold[7][tid] = T;
       Quat q;
       bool spin = true;
-      switch (e.kind) {
+      if (SURR && !__any(spin_lane)) {   // no lane of this wave needs the spin
+        spin = false;
+        if (e.kind == K_SBEND) {
+          thick_orbit<0>(e, X, Px, Y, Py, T, p, a);
+        } else if (e.kind == K_QUAD) {
+          if (e.orbit != M_MK)    thick_orbit<2>(e, X, Px, Y, Py, T, p, a);
+          else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a);
+          else                    thick_orbit<3>(e, X, Px, Y, Py, T, p, a);
+        } else if (e.kind == K_THIN) {
+          const double hk1 = 0.5 * e.t.k1l, hk2 = 0.5 * e.t.k2l;
+          for (int h = 0; h < 2; ++h) {
+            Px -= fma(hk1, X, 0.5 * hk2 * (X * X - Y * Y));
+            Py += fma(hk1, Y, hk2 * X * Y);
+          }
+        }
+      } else switch (e.kind) {
         case K_SBEND:
-          q = thick_element<NT, 0>(e, X, Px, Y, Py, T, p, a);
+          q = thick_element<NT, 0, MIXED>(e, X, Px, Y, Py, T, p, a);
           break;
         case K_QUAD:
-          if (e.orbit != M_MK)   q = thick_element<NT, 2>(e, X, Px, Y, Py, T, p, a);
-          else if (e.q.k1 >= 0.0) q = thick_element<NT, 1>(e, X, Px, Y, Py, T, p, a);
-          else                   q = thick_element<NT, 3>(e, X, Px, Y, Py, T, p, a);
+          if (e.orbit != M_MK)   q = thick_element<NT, 2, MIXED>(e, X, Px, Y, Py, T, p, a);
+          else if (e.q.k1 >= 0.0) q = thick_element<NT, 1, MIXED>(e, X, Px, Y, Py, T, p, a);
+          else                   q = thick_element<NT, 3, MIXED>(e, X, Px, Y, Py, T, p, a);
           break;
         case K_THIN:
           q = thin_element<NT>(e, X, Px, Y, Py, p, a);
@@ -246,7 +333,7 @@ track_fp64_kernel(const TrackArgs a) {
     // A particle lost during this turn still receives the rotation of the
     // elements it completed before the loss.
     double sx = cold[0][tid], sy = cold[1][tid], sz = cold[2][tid];
-    if (was_live) {
+    if (was_live && spin_lane) {
       qrotate(qturn, sx, sy, sz);
       cold[0][tid] = sx; cold[1][tid] = sy; cold[2][tid] = sz;
     }
@@ -308,14 +395,99 @@ __global__ void __launch_bounds__(256) reduce_polarization_kernel(const double* 
 
 int track_block_size() { return kBlock; }
 
-hipError_t launch_track_fp64(const TrackArgs& a, int nt, hipStream_t stream) {
+template <bool MIXED, bool SURR>
+hipError_t launch_nt(const TrackArgs& a, int nt, hipStream_t stream) {
   const dim3 grid((unsigned)a.n_blocks), block(kBlock);
   switch (nt) {
-    case 6:  hipLaunchKernelGGL(track_fp64_kernel<6>, grid, block, 0, stream, a); break;
-    case 8:  hipLaunchKernelGGL(track_fp64_kernel<8>, grid, block, 0, stream, a); break;
-    case 12: hipLaunchKernelGGL(track_fp64_kernel<12>, grid, block, 0, stream, a); break;
-    default: hipLaunchKernelGGL(track_fp64_kernel<16>, grid, block, 0, stream, a); break;
+    case 6:  hipLaunchKernelGGL((track_kernel<6, MIXED, SURR>), grid, block, 0, stream, a); break;
+    case 8:  hipLaunchKernelGGL((track_kernel<8, MIXED, SURR>), grid, block, 0, stream, a); break;
+    case 12: hipLaunchKernelGGL((track_kernel<12, MIXED, SURR>), grid, block, 0, stream, a); break;
+    default: hipLaunchKernelGGL((track_kernel<16, MIXED, SURR>), grid, block, 0, stream, a); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, hipStream_t stream) {
+  if (a.fallback) return launch_nt<false, true>(a, nt, stream);
+  return mixed ? launch_nt<true, false>(a, nt, stream) : launch_nt<false, false>(a, nt, stream);
+}
+
+namespace {
+
+// S <- q S q* with the network's quaternion (float [n][4], normalised again in
+// double) for alive particles that are not on the fallback path.
+__global__ void __launch_bounds__(256) surrogate_spin_kernel(double* spin, const int32_t* alive,
+                                                             const int32_t* fallback,
+                                                             const float* qnn, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n || alive[j] != 1 || fallback[j] != 0) return;
+  Quat q = {qnn[4 * j], qnn[4 * j + 1], qnn[4 * j + 2], qnn[4 * j + 3]};
+  const double inv = rsqrt_nr(fma(q.w, q.w, fma(q.x, q.x, fma(q.y, q.y, q.z * q.z))));
+  q.w *= inv; q.x *= inv; q.y *= inv; q.z *= inv;
+  double sx = spin[j], sy = spin[n + j], sz = spin[2 * n + j];
+  qrotate(q, sx, sy, sz);
+  spin[j] = sx; spin[n + j] = sy; spin[2 * n + j] = sz;
+}
+
+// Audit: largest component difference between the network's quaternion and
+// the tracked one (sign aligned); above the threshold the particle falls back.
+__global__ void __launch_bounds__(256) audit_kernel(const int32_t* alive, int32_t* fallback,
+                                                    const float* qnn, const double* q64, int64_t n,
+                                                    double threshold, int32_t turn) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n || alive[j] != 1 || fallback[j] != 0) return;
+  const double a[4] = {qnn[4 * j], qnn[4 * j + 1], qnn[4 * j + 2], qnn[4 * j + 3]};
+  const double na = rsqrt_nr(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+  const double b[4] = {q64[j], q64[n + j], q64[2 * n + j], q64[3 * n + j]};
+  const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+  const double s = dot < 0.0 ? -1.0 : 1.0;
+  double d = 0.0;
+  for (int c = 0; c < 4; ++c) d = fmax(d, fabs(a[c] * na - s * b[c]));
+  if (!(d <= threshold)) fallback[j] = turn;
+}
+
+// Per-block sums (Sx, Sy, Sz, N) over alive particles for one report.
+__global__ void __launch_bounds__(256) polarization_partials_kernel(const double* spin,
+                                                                    const int32_t* alive, int64_t n,
+                                                                    double* partials) {
+  __shared__ double red[4][4];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = j < n && alive[j] == 1;
+  double v[4] = {live ? spin[j] : 0.0, live ? spin[n + j] : 0.0, live ? spin[2 * n + j] : 0.0,
+                 live ? 1.0 : 0.0};
+  for (int c = 0; c < 4; ++c)
+    for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 4; ++c) red[threadIdx.x >> 6][c] = v[c];
+  __syncthreads();
+  if (threadIdx.x < 4)
+    partials[(int64_t)blockIdx.x * 4 + threadIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+}  // namespace
+
+hipError_t launch_surrogate_spin(double* spin, const int32_t* alive, const int32_t* fallback,
+                                 const float* qnn, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(surrogate_spin_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spin,
+                     alive, fallback, qnn, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_audit(const int32_t* alive, int32_t* fallback, const float* qnn, const double* q64,
+                        int64_t n, double threshold, int32_t turn, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(audit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, alive, fallback,
+                     qnn, q64, n, threshold, turn);
+  return hipGetLastError();
+}
+
+hipError_t launch_polarization_partials(const double* spin, const int32_t* alive, int64_t n,
+                                        double* partials, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(polarization_partials_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     spin, alive, n, partials);
   return hipGetLastError();
 }
 

@@ -9,8 +9,19 @@ namespace st {
 
 int track_block_size();
 
-// nt: number of series terms of the quaternion half-angle polynomial (6, 8, 12, 16).
-hipError_t launch_track_fp64(const TrackArgs& a, int nt, hipStream_t stream);
+// nt: number of series terms of the double-precision quaternion half-angle
+// series (6, 8, 12, 16); mixed: the kernel with single-precision spin
+// arithmetic in the elements flagged for it.
+hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, hipStream_t stream);
+
+// a.fallback non-null selects the surrogate-tracking kernel.
+
+hipError_t launch_surrogate_spin(double* spin, const int32_t* alive, const int32_t* fallback,
+                                 const float* qnn, int64_t n, hipStream_t s);
+hipError_t launch_audit(const int32_t* alive, int32_t* fallback, const float* qnn, const double* q64,
+                        int64_t n, double threshold, int32_t turn, hipStream_t s);
+hipError_t launch_polarization_partials(const double* spin, const int32_t* alive, int64_t n,
+                                        double* partials, hipStream_t s);
 
 hipError_t launch_reduce_polarization(const double* partials, int n_blocks, int n_reports,
                                       double* out, hipStream_t stream);

@@ -1,0 +1,63 @@
+"""Pins of the CPU reference network used to check the GPU surrogate kernels:
+central finite differences of the loss for every parameter tensor, the
+normalised output, the textbook Adam update and the bf16 rounding rule."""
+
+import numpy as np
+
+from oracle import mlp_ref as M
+
+
+def _setup(n_in=7, batch=8, seed=0):
+    rng = np.random.default_rng(seed)
+    params = []
+    for s in M.shapes(n_in):
+        fan_in = s[1] if len(s) == 2 else 256
+        params.append(rng.normal(0, 1.0 / np.sqrt(fan_in), size=s))
+    x = rng.normal(size=(batch, n_in))
+    t = rng.normal(size=(batch, 4))
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    return params, x, t
+
+
+def test_output_is_a_unit_quaternion():
+    params, x, _ = _setup()
+    q, _ = M.forward(params, x)
+    np.testing.assert_allclose(np.linalg.norm(q, axis=1), 1.0, atol=1e-15)
+
+
+def test_backward_matches_central_differences_for_every_tensor():
+    params, x, t = _setup()
+    grads = M.backward(params, x, t)
+    rng = np.random.default_rng(1)
+    h = 1e-6
+    for k, (p, g) in enumerate(zip(params, grads)):
+        flat = p.ravel()
+        for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = M.loss(params, x, t)
+            flat[idx] = old - h
+            lm = M.loss(params, x, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            gk = g.ravel()[idx]
+            assert abs(fd - gk) <= 1e-6 * max(1e-3, abs(fd)), (k, idx, fd, gk)
+
+
+def test_adam_first_step_is_lr_times_sign():
+    # With m0 = v0 = 0 the bias-corrected first step is -lr·g/(|g| + eps).
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -1e-3, 2.0])
+    m, v = np.zeros(3), np.zeros(3)
+    out = M.adam_step(theta.copy(), m, v, g, 1, lr=0.01)
+    np.testing.assert_allclose(out, theta - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, 1.0 + 2 ** -9, -3.14159265])
+    r = M.bf16_round(vals)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                                      # exactly half way to 1 + 2^-7: ties to even
+    assert r[2] == 1.0 + 2 ** -7                            # above half way: rounds up
+    assert r[3] == 1.0                                      # below half way: rounds down
+    assert abs(r[4] + 3.140625) < 1e-12

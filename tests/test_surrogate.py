@@ -1,0 +1,212 @@
+"""The spin surrogate: network kernels against the CPU float64 reference
+network (same bf16-rounded weights and inputs), Adam against the textbook
+update, training on tracked one-turn quaternions, and surrogate tracking
+with audits and fallback through the C ABI.
+
+There is no paper pin for the surrogate (it is not part of the method); the
+plain double-precision tracker is the judge of its spin error."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+from workloads import Beam, gaussian_bunch, rhic_like_ring, small_ring
+
+pytestmark = pytest.mark.gpu
+
+BEAM = Beam()
+SIG = np.array([1e-3, 1e-4, 1e-3, 1e-4, 1e-2, 1e-3 * BEAM.beta0])
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def _params(m):
+    from paper_1501_03450_amd import binding as B
+    n = B.st_mlp_params(m)
+    out = np.zeros(n, dtype=np.float32)
+    B.st_mlp_params(m, out.ctypes.data)
+    return out
+
+
+def _cpu_params(theta, n_in):
+    """Master weights as the GPU uses them: W2, W3 rounded to bf16."""
+    p = M.unflatten(theta.astype(np.float64), n_in)
+    p[2] = M.bf16_round(p[2])
+    p[4] = M.bf16_round(p[4])
+    return p
+
+
+def _data(n, n_in, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, n_in)).astype(np.float32)
+    t = rng.normal(size=(n, 4))
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    return x, t.astype(np.float32)
+
+
+def _rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("n_in", [6, 7])
+def test_forward_matches_the_cpu_reference(n_in):
+    import torch
+    from paper_1501_03450_amd import binding as B
+    m = B.st_mlp_create(0, n_in, 256, seed=11)
+    x, _ = _data(1000, n_in, 1)
+    dx = _dev(x, np.float32)
+    dq = torch.zeros((1000, 4), dtype=torch.float32, device="cuda")
+    B.st_mlp_infer(m, dx.data_ptr(), dq.data_ptr(), 1000)
+    torch.cuda.synchronize()
+    # same rounding points as the kernels: bf16 W2, W3 and hidden activations,
+    # everything else float32 with float32 accumulation
+    q_cpu, _ = M.forward(_cpu_params(_params(m), n_in), x.astype(np.float64),
+                         round_act=M.bf16_round)
+    err = np.abs(dq.cpu().numpy() - q_cpu).max()
+    print(f"n_in {n_in}: forward max abs err {err:.3e}")
+    assert err < 2e-3
+    B.st_mlp_destroy(m)
+
+
+def test_gradient_matches_the_cpu_reference_tensor_by_tensor():
+    import torch
+    from paper_1501_03450_amd import binding as B
+    n_in = 6
+    m = B.st_mlp_create(0, n_in, 256, seed=12)
+    x, t = _data(1000, n_in, 2)            # 1000: several tiles and a ragged tail
+    dx, dt = _dev(x, np.float32), _dev(t, np.float32)
+    n = B.st_mlp_params(m)
+    g = torch.zeros(n, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), 1000, g.data_ptr(), loss.data_ptr())
+    torch.cuda.synchronize()
+    p = _cpu_params(_params(m), n_in)
+    g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64))
+    g_gpu = M.unflatten(g.cpu().numpy(), n_in)
+    for k, (a, b) in enumerate(zip(g_gpu, g_cpu)):
+        assert _rel_fro(a, b) <= 1e-2, (k, _rel_fro(a, b))
+    assert abs(loss.item() - M.loss(p, x.astype(np.float64), t.astype(np.float64))) < 1e-3
+    B.st_mlp_destroy(m)
+
+
+def test_adam_step_is_the_textbook_update():
+    import torch
+    from paper_1501_03450_amd import binding as B
+    n_in = 6
+    m = B.st_mlp_create(0, n_in, 256, seed=13)
+    x, t = _data(512, n_in, 3)
+    dx, dt = _dev(x, np.float32), _dev(t, np.float32)
+    n = B.st_mlp_params(m)
+    p0 = _params(m).astype(np.float64)
+    g = torch.zeros(n, dtype=torch.float32, device="cuda")
+    B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), 512, g.data_ptr())
+    B.st_mlp_train_step(m, dx.data_ptr(), dt.data_ptr(), 512, 1e-3)
+    torch.cuda.synchronize()
+    p1 = _params(m).astype(np.float64)
+    ref = M.adam_step(p0.copy(), np.zeros(n), np.zeros(n), g.cpu().numpy().astype(np.float64), 1, 1e-3)
+    np.testing.assert_allclose(p1, ref, rtol=0, atol=1e-6)
+    B.st_mlp_destroy(m)
+
+
+def _tracked_quaternions(ring, n, seed, widen=1.0):
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    z, s, a = gaussian_bunch(n, seed, BEAM, scale=widen)
+    tr = SpinTracker(ring, BEAM)
+    tr.set_particles(z, s, a)
+    q = tr.enable_quaternions()
+    tr.track(1)
+    torch.cuda.synchronize()
+    zt = torch.as_tensor(z).cuda().contiguous()
+    return tr, zt, q
+
+
+def test_training_on_tracked_one_turn_quaternions_reduces_the_loss():
+    import torch
+    from paper_1501_03450_amd import binding as B
+    n = 1 << 14
+    tr, z0, q = _tracked_quaternions(rhic_like_ring(), n, 101)
+    m = B.st_mlp_create(0, 6, 256, seed=5)
+    x = torch.zeros((n, 6), dtype=torch.float32, device="cuda")
+    t = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    B.st_mlp_features(m, z0.data_ptr(), n, np.zeros(6), 1.0 / SIG, 0.0, x.data_ptr())
+    B.st_mlp_targets(m, q.data_ptr(), n, (0.0, 0.0, 1.0, 0.0), t.data_ptr())
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    for step in range(400):
+        lo = (step * 4096) % n
+        B.st_mlp_train_step(m, x[lo:lo + 4096].data_ptr(), t[lo:lo + 4096].data_ptr(), 4096,
+                            1e-3, loss.data_ptr())
+        losses.append(loss.item())
+    print(f"loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.05 * losses[0]
+    # the network's spin prediction is closer to the tracker than "no rotation
+    # information" (the mean quaternion of the bunch)
+    dq = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    B.st_mlp_infer(m, x.data_ptr(), dq.data_ptr(), n)
+    tt = t.cpu().numpy()
+    err_net = np.abs(dq.cpu().numpy() - tt).max(axis=1)
+    mean = tt.mean(0) / np.linalg.norm(tt.mean(0))
+    err_mean = np.abs(tt - mean).max(axis=1)
+    assert np.median(err_net) < 0.3 * np.median(err_mean)
+    B.st_mlp_destroy(m)
+    tr.close()
+
+
+def _surrogate_run(ring, z, s, a, turns, audit_every, threshold, seed=7):
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from paper_1501_03450_amd import binding as B
+    m = B.st_mlp_create(0, 6, 256, seed=seed)
+    tr = SpinTracker(ring, BEAM)
+    tr.set_particles(z, s, a)
+    fb = torch.zeros(z.shape[1], dtype=torch.int32, device="cuda")
+    B.st_track_surrogate(tr.ctx, m, turns, audit_every, threshold, np.zeros(6), 1.0 / SIG, 0.0,
+                         fb.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    out = tr.read()
+    tr.close()
+    B.st_mlp_destroy(m)
+    return out, fb.cpu().numpy()
+
+
+def _fp64_run(ring, z, s, a, turns):
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    tr = SpinTracker(ring, BEAM)
+    tr.set_particles(z, s, a)
+    tr.track(turns)
+    torch.cuda.synchronize()
+    out = tr.read()
+    tr.close()
+    return out
+
+
+def test_auditing_every_turn_is_exactly_the_double_precision_tracker():
+    z, s, a = gaussian_bunch(700, 201, BEAM)
+    (zs, ss, as_), fb = _surrogate_run(small_ring(), z, s, a, 4, 1, 1e9)
+    z64, s64, a64 = _fp64_run(small_ring(), z, s, a, 4)
+    np.testing.assert_array_equal(zs, z64)
+    np.testing.assert_array_equal(ss, s64)
+    assert (fb == 0).all()
+
+
+def test_threshold_zero_sends_every_particle_to_the_fallback_at_the_first_audit():
+    z, s, a = gaussian_bunch(700, 202, BEAM)
+    (zs, ss, as_), fb = _surrogate_run(rhic_like_ring(), z, s, a, 5, 3, 0.0)
+    assert (fb[as_ == 1] == 3).all()
+
+
+def test_without_fallback_the_orbit_is_the_double_precision_orbit():
+    z, s, a = gaussian_bunch(700, 203, BEAM)
+    turns = 3
+    (zs, ss, as_), fb = _surrogate_run(rhic_like_ring(), z, s, a, turns, 1000, 1e9)
+    z64, _, _ = _fp64_run(rhic_like_ring(), z, s, a, turns)
+    assert (fb == 0).all()
+    sig = z64.std(axis=1)
+    rel = np.abs(zs - z64) / np.maximum(np.abs(z64), sig[:, None])
+    assert rel.max() < 1e-12 * turns * 10      # bends crossed in one exact step
+    np.testing.assert_allclose(np.linalg.norm(ss, axis=0), 1.0, atol=1e-6)
