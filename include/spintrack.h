@@ -185,6 +185,15 @@ const char* st_mlp_last_error(const st_mlp* m);
  * (host, may be NULL) receives the count.  Synchronous. */
 st_status st_mlp_params(st_mlp* m, float* h_get, const float* h_set, int64_t* n_params);
 
+/* Output frame of the network: with the last layer's output y, the
+ * prediction is q = u/|u| for u = ref + scale ⊙ y (ref, scale: host, 4
+ * doubles each, finite, scale > 0; stored as floats).  A reference
+ * quaternion close to the targets and a scale of their spread around it let
+ * the network learn only the deviation, so that its bf16 rounding error is
+ * scaled down with it.  Default ref = 0, scale = 1.  Applies to training,
+ * gradients, inference and surrogate tracking alike. */
+st_status st_mlp_set_frame(st_mlp* m, const double* ref, const double* scale);
+
 /* One Adam step (learning rate lr > 0) on `batch` samples: inputs d_x, unit
  * quaternion targets d_t (device).  d_loss (device, 1 float, may be NULL)
  * receives the batch's mean loss before the step.  Queued on `stream`. */

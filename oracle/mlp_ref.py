@@ -51,8 +51,9 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(params, x, round_act=None):
-    """q = y/|y| for a batch x [B][n_in].  round_act, when given, is applied
+def forward(params, x, round_act=None, ref=None, scale=None):
+    """q = u/|u| with u = ref + scale ⊙ y for a batch x [B][n_in] (the output
+    frame; ref = 0, scale = 1 by default).  round_act, when given, is applied
     to each hidden activation before it enters the next layer (the GPU
     kernels hold them in bf16)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = params
@@ -64,23 +65,31 @@ def forward(params, x, round_act=None):
     z3 = h2 @ W3.T + b3
     h3 = r(silu(z3))
     y = h3 @ W4.T + b4
-    q = y / np.linalg.norm(y, axis=1, keepdims=True)
-    return q, (x, z1, h1, z2, h2, z3, h3, y)
+    u = _frame(y, ref, scale)
+    q = u / np.linalg.norm(u, axis=1, keepdims=True)
+    return q, (x, z1, h1, z2, h2, z3, h3, u)
 
 
-def loss(params, x, t):
-    q, _ = forward(params, x)
+def _frame(y, ref, scale):
+    ref = np.zeros(N_OUT) if ref is None else np.asarray(ref, dtype=np.float64)
+    scale = np.ones(N_OUT) if scale is None else np.asarray(scale, dtype=np.float64)
+    return ref + scale * y
+
+
+def loss(params, x, t, ref=None, scale=None):
+    q, _ = forward(params, x, ref=ref, scale=scale)
     return float(np.mean(np.sum((q - t) ** 2, axis=1)))
 
 
-def backward(params, x, t):
+def backward(params, x, t, ref=None, scale=None):
     """Gradients of L with respect to every parameter (same order)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = params
-    q, (x, z1, h1, z2, h2, z3, h3, y) = forward(params, x)
+    q, (x, z1, h1, z2, h2, z3, h3, u) = forward(params, x, ref=ref, scale=scale)
     B = x.shape[0]
     dq = 2.0 * (q - t) / B
-    ny = np.linalg.norm(y, axis=1, keepdims=True)
-    dy = (dq - q * np.sum(q * dq, axis=1, keepdims=True)) / ny
+    nu = np.linalg.norm(u, axis=1, keepdims=True)
+    du = (dq - q * np.sum(q * dq, axis=1, keepdims=True)) / nu
+    dy = du * (np.ones(N_OUT) if scale is None else np.asarray(scale, dtype=np.float64))
     gW4 = dy.T @ h3
     gb4 = dy.sum(0)
     dz3 = (dy @ W4) * dsilu(z3)

@@ -30,7 +30,7 @@ PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED, "mixed_all": ST_MIXED_ALL
 EXPORTS = ("st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
            "st_bind_quaternions", "st_track", "st_polarization", "st_read_particles",
            "st_last_error", "st_mlp_create", "st_mlp_destroy", "st_mlp_last_error",
-           "st_mlp_params", "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
+           "st_mlp_params", "st_mlp_set_frame", "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
            "st_mlp_features", "st_mlp_targets", "st_track_surrogate")
 
 
@@ -76,6 +76,7 @@ def _load():
     lib.st_mlp_last_error.argtypes = [vp]
     lib.st_mlp_last_error.restype = ctypes.c_char_p
     lib.st_mlp_params.argtypes = [vp, vp, vp, P(i64)]
+    lib.st_mlp_set_frame.argtypes = [vp, P(f64), P(f64)]
     lib.st_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp]
     lib.st_mlp_gradient.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.st_mlp_infer.argtypes = [vp, vp, vp, i64, vp]
@@ -193,6 +194,12 @@ def st_mlp_params(m, h_get_ptr=None, h_set_ptr=None) -> int:
     n = ctypes.c_int64(0)
     _check_mlp(m, LIB.st_mlp_params(m, h_get_ptr, h_set_ptr, ctypes.byref(n)))
     return int(n.value)
+
+
+def st_mlp_set_frame(m, ref, scale):
+    r = (ctypes.c_double * 4)(*[float(x) for x in ref])
+    c = (ctypes.c_double * 4)(*[float(x) for x in scale])
+    _check_mlp(m, LIB.st_mlp_set_frame(m, r, c))
 
 
 def st_mlp_train_step(m, x_ptr, t_ptr, batch, lr, loss_ptr=None, stream=None):

@@ -170,7 +170,10 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
   float l = 0.0f;
   if (tid < TM && tid < rows) {
     const int m = tid;
-    const float y0 = ys[m][0], y1 = ys[m][1], y2 = ys[m][2], y3 = ys[m][3];
+    const float y0 = fmaf(a.out_scale[0], ys[m][0], a.out_ref[0]);
+    const float y1 = fmaf(a.out_scale[1], ys[m][1], a.out_ref[1]);
+    const float y2 = fmaf(a.out_scale[2], ys[m][2], a.out_ref[2]);
+    const float y3 = fmaf(a.out_scale[3], ys[m][3], a.out_ref[3]);
     const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2 + y3 * y3);
     const float inv = 1.0f / ny;
     const float q[4] = {y0 * inv, y1 * inv, y2 * inv, y3 * inv};
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
         dq[j] = 2.0f * d * a.inv_loss_norm;
         qd += q[j] * dq[j];
       }
-      for (int j = 0; j < 4; ++j) a.dy[(b0 + m) * 4 + j] = (dq[j] - q[j] * qd) * inv;
+      for (int j = 0; j < 4; ++j) a.dy[(b0 + m) * 4 + j] = a.out_scale[j] * ((dq[j] - q[j] * qd) * inv);
     }
   }
   if (TRAIN) {

@@ -16,6 +16,8 @@ struct st_mlp {
   st::MlpOffsets off{};
   int64_t n_params = 0;
   int64_t step = 0;                 // Adam steps taken
+  float frame_ref[4] = {0.0f, 0.0f, 0.0f, 0.0f};    // output frame (st_mlp_set_frame)
+  float frame_scale[4] = {1.0f, 1.0f, 1.0f, 1.0f};
   float* params = nullptr;          // fp32 master weights
   float* adam_m = nullptr;
   float* adam_v = nullptr;
@@ -125,6 +127,7 @@ st::MlpArgs base_args(st_mlp* m) {
   a.grad = m->grad;
   a.adam_m = m->adam_m;
   a.adam_v = m->adam_v;
+  for (int j = 0; j < 4; ++j) { a.out_ref[j] = m->frame_ref[j]; a.out_scale[j] = m->frame_scale[j]; }
   return a;
 }
 
@@ -262,6 +265,16 @@ st_status st_mlp_params(st_mlp* m, float* h_get, const float* h_set, int64_t* n_
       return hip_fail(m, e, "refresh bf16 weights");
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(m, e, "synchronise");
   }
+  return ST_OK;
+}
+
+st_status st_mlp_set_frame(st_mlp* m, const double* ref, const double* scale) {
+  if (!m) return ST_EINVAL;
+  if (!ref || !scale) return fail(m, ST_EINVAL, "frame is NULL");
+  for (int j = 0; j < 4; ++j)
+    if (!std::isfinite(ref[j]) || !std::isfinite(scale[j]) || !(scale[j] > 0.0))
+      return fail(m, ST_EINVAL, "frame values must be finite with scale > 0");
+  for (int j = 0; j < 4; ++j) { m->frame_ref[j] = (float)ref[j]; m->frame_scale[j] = (float)scale[j]; }
   return ST_OK;
 }
 

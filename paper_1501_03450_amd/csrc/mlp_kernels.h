@@ -51,6 +51,8 @@ struct MlpArgs {
   const float* target;    // [batch][4]
   float* q_out;           // [batch][4]
   float* dy;              // [batch][4]
+  float out_ref[4];       // output frame: u = out_ref + out_scale ⊙ y, q = u/|u|
+  float out_scale[4];
   float inv_loss_norm;    // 1/batch
   float* loss_part;       // [blocks]
   float* zT1;             // [256][ld] pre-activations

@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
     assert names == sorted(["st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
                             "st_bind_quaternions", "st_track", "st_polarization",
                             "st_read_particles", "st_last_error", "st_mlp_create",
-                            "st_mlp_destroy", "st_mlp_last_error", "st_mlp_params",
+                            "st_mlp_destroy", "st_mlp_last_error", "st_mlp_params", "st_mlp_set_frame",
                             "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
                             "st_mlp_features", "st_mlp_targets", "st_track_surrogate"])
 
@@ -60,6 +60,7 @@ def test_null_context_and_bad_device_are_rejected_without_device_work():
     assert B.st_last_error(None) == "null context"
     assert lib.st_mlp_train_step(None, None, None, 1, 1e-3, None, None) == B.ST_EINVAL
     assert lib.st_mlp_destroy(None) == B.ST_OK
+    assert lib.st_mlp_set_frame(None, None, None) == B.ST_EINVAL
     assert lib.st_track_surrogate(None, None, 1, 1, 0.0, None, None, 0.0, None, None) == B.ST_EINVAL
     with pytest.raises(B.SpinTrackError):
         B.st_create(-1)

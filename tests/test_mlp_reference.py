@@ -3,6 +3,7 @@ central finite differences of the loss for every parameter tensor, the
 normalised output, the textbook Adam update and the bf16 rounding rule."""
 
 import numpy as np
+import pytest
 
 from oracle import mlp_ref as M
 
@@ -25,9 +26,11 @@ def test_output_is_a_unit_quaternion():
     np.testing.assert_allclose(np.linalg.norm(q, axis=1), 1.0, atol=1e-15)
 
 
-def test_backward_matches_central_differences_for_every_tensor():
+@pytest.mark.parametrize("frame", [None, ((0.1, -0.3, 0.9, 0.2), (0.05, 0.02, 0.1, 0.03))])
+def test_backward_matches_central_differences_for_every_tensor(frame):
     params, x, t = _setup()
-    grads = M.backward(params, x, t)
+    ref, scale = frame if frame else (None, None)
+    grads = M.backward(params, x, t, ref=ref, scale=scale)
     rng = np.random.default_rng(1)
     h = 1e-6
     for k, (p, g) in enumerate(zip(params, grads)):
@@ -35,13 +38,21 @@ def test_backward_matches_central_differences_for_every_tensor():
         for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
             old = flat[idx]
             flat[idx] = old + h
-            lp = M.loss(params, x, t)
+            lp = M.loss(params, x, t, ref, scale)
             flat[idx] = old - h
-            lm = M.loss(params, x, t)
+            lm = M.loss(params, x, t, ref, scale)
             flat[idx] = old
             fd = (lp - lm) / (2 * h)
             gk = g.ravel()[idx]
             assert abs(fd - gk) <= 1e-6 * max(1e-3, abs(fd)), (k, idx, fd, gk)
+
+
+def test_output_frame_with_zero_weights_returns_the_reference_direction():
+    params, x, _ = _setup()
+    params = [np.zeros_like(p) for p in params]
+    ref = np.array([0.0, 0.6, 0.0, -0.8])
+    q, _ = M.forward(params, x, ref=ref, scale=(0.01, 0.01, 0.01, 0.01))
+    np.testing.assert_allclose(q, np.broadcast_to(ref, q.shape), atol=1e-15)
 
 
 def test_adam_first_step_is_lr_times_sign():
