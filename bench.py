@@ -50,15 +50,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRACK_SOURCES = ("track.hip", "track_kernels.h", "fp64_maps.h", "device_math.h",
+                 "lattice_table.h", "mixed_spin.h")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the library sources: a recorded traffic figure is only valid
-    for the kernel it was measured on."""
-    import glob
+    """Hash of the tracking kernel's sources: a recorded traffic figure is
+    only valid for the kernel it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1501_03450_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
+    for name in TRACK_SOURCES:
+        with open(os.path.join(ROOT, "paper_1501_03450_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -90,23 +93,49 @@ def parse():
     ap.add_argument("--mixed-particles", type=int, default=4 << 20)
     ap.add_argument("--mixed-turns", type=int, default=20)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--band-energies", type=int, default=16,
+                    help="energies of the default surrogate leg (the first band of the scan)")
+    ap.add_argument("--scan-particles", type=int, default=65536)
+    ap.add_argument("--scan-turns", type=int, default=100)
+    ap.add_argument("--audit-every", type=int, default=50)
+    ap.add_argument("--threshold", type=float, default=1e-6)
+    ap.add_argument("--band-train-per-energy", type=int, default=65536)
+    ap.add_argument("--band-epochs", type=int, default=60)
+    ap.add_argument("--c3", action="store_true",
+                    help="full surrogate training run: 2^24 widened samples labelled by one "
+                         "double-precision turn, batch 65536")
+    ap.add_argument("--c3-samples", type=int, default=1 << 24)
+    ap.add_argument("--c3-epochs", type=int, default=20)
+    ap.add_argument("--c4", action="store_true",
+                    help="full energy scan: 256 energies x 65536 particles, 16 bands")
+    ap.add_argument("--c4-energies", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one device copy of 1 GiB and one tracking launch "
                          "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print the source hash")
     return ap.parse_args()
 
 
-def cpu_baseline(ring, beam, z, s, a, n_sample, turns):
+def cpu_baseline(ring, beam, z, s, a, n_sample, turns, n_1core, turns_1core):
+    """The double-precision oracle on the host cores: all cores (up to 16) on
+    n_sample particles, and one core on a smaller sample."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
-    zs, ss, as_ = z[:, :n_sample].copy(), s[:, :n_sample].copy(), a[:n_sample].copy()
     t0 = time.perf_counter()
-    oracle.track(ring, beam, zs, ss, as_, turns=turns, extended=True, threads=threads)
+    oracle.track(ring, beam, z[:, :n_sample], s[:, :n_sample], a[:n_sample], turns=turns,
+                 extended=False, threads=threads)
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.track(ring, beam, z[:, :n_1core], s[:, :n_1core], a[:n_1core], turns=turns_1core,
+                 extended=False, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": n_sample * turns / dt, "unit": "particle-turns/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_sample} particles x {turns} turns of the same ring and bunch, "
-                      f"extended-precision oracle, {threads} threads, {dt:.1f} s"}
+                      f"double-precision oracle, {threads} threads, {dt:.1f} s",
+            "value_1core": n_1core * turns_1core / dt1,
+            "sample_1core": f"{n_1core} particles x {turns_1core} turns, 1 thread, {dt1:.1f} s"}
 
 
 def timed_tracking(tracker, turns, steps, stream):
@@ -158,6 +187,108 @@ def mixed_leg(ring, beam, n, turns, stream):
             "polarization_err": float(np.abs(m["pol"][-1, :3] - f["pol"][-1, :3]).max()),
         }
     return out
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def quantiles(e):
+    q = np.quantile(e, [0.5, 0.9, 0.99])
+    return {"median": float(q[0]), "p90": float(q[1]), "p99": float(q[2]), "max": float(e.max()),
+            "frac_le_1e-6": float(np.mean(e <= 1e-6)), "frac_le_1e-4": float(np.mean(e <= 1e-4))}
+
+
+def c3_leg(ring, beam, n_samples, epochs, batch, lr):
+    """Surrogate training: labels from one double-precision turn of a
+    widened bunch, Adam on the library's kernels, held-out errors."""
+    import torch
+    from paper_1501_03450_amd import surrogate as S
+    from workloads import gaussian_bunch
+    from workloads.bunch import SEED_BASE
+    widen = 3.0
+    ref = S.design_quaternion(ring, beam)
+    c, inv = S.feature_map(beam, widen)
+    sur = S.new_surrogate(6, 1, c, inv, ref)
+    z, _, _ = gaussian_bunch(n_samples, SEED_BASE + 3, beam, scale=widen)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, t = S.label_bunch(sur, ring, beam, z)
+    t_label = time.perf_counter() - t0
+    del z
+    S.set_scale(sur, S.frame_from_targets(t[:65536].cpu().numpy(), ref))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.train(sur, x, t, epochs, batch, lr, log=lambda m: log(f"[bench] c3 {m}"))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    steps = epochs * (x.shape[0] // batch)
+    sps = steps * batch / t_train
+    tflops = sps * S.flops_per_sample(6, True) / 1e12
+    zv, _, _ = gaussian_bunch(65536, SEED_BASE + 33, beam)
+    xv, tv = S.label_bunch(sur, ring, beam, zv)
+    out = {
+        "workload": f"{n_samples} samples (bunch sigma x{widen:g}), one double-precision turn of "
+                    f"rhic_like_ring each; MLP 6-256-256-256-4 SiLU, bf16 MFMA, batch {batch}, "
+                    f"{epochs} epochs, Adam lr {lr:g} cosine to {lr * 1e-2:g}",
+        "labels_per_s": n_samples / t_label,
+        "train_samples_per_s": sps,
+        "train_tflops": tflops,
+        "train_mfma_frac_of_bf16_peak": tflops / MFMA_BF16_PEAK_TFLOPS,
+        "train_seconds": t_train,
+        "final_loss": sur.losses[-1],
+        "output_frame_scale": [float(v) for v in sur.scale],
+        "err_train_sample": quantiles(S.component_errors(sur, x[:65536], t[:65536])),
+        "err_heldout_base_bunch": quantiles(S.component_errors(sur, xv, tv)),
+    }
+    sur.close()
+    return out
+
+
+def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_energy, epochs,
+             lr, n_bands):
+    """Energy scan with surrogate + fallback against plain double precision on
+    the same bunches, plus the fallback fraction at looser thresholds."""
+    from paper_1501_03450_amd import surrogate as S
+    from workloads import energy_scan_bunches, energy_scan_gammas
+    from workloads.bunch import SEED_BASE
+    gam_all = energy_scan_gammas(256)
+    gam = gam_all[:n_energies]
+    bunches = energy_scan_bunches(gam, n_per, SEED_BASE + 4)
+    beams = [b[0] for b in bunches]
+    t0 = time.perf_counter()
+    nets, per = [], []
+    for b, rng_ in enumerate(S.band_slices(n_energies, n_bands)):
+        sur = S.train_band(ring, [beams[i] for i in rng_], train_per_energy,
+                           SEED_BASE + 3 + 1000 * (b + 1), epochs, 65536, lr, net_seed=b + 1)
+        log(f"[bench] band {b + 1}/{n_bands}: final loss {sur.losses[-1]:.3e}")
+        nets.append(sur)
+        per += [sur] * len(rng_)
+    t_train = time.perf_counter() - t0
+    f = S.energy_scan(ring, bunches, turns, None, log=lambda m: log(f"[bench] fp64 scan {m}"))
+    res = {}
+    for thr in sorted({threshold, 1e-4, 1e-2}):
+        r = S.energy_scan(ring, bunches, turns, per, audit_every, thr,
+                          log=lambda m: log(f"[bench] surrogate scan (threshold {thr:g}) {m}"))
+        dp = np.abs(r["polarization"][:, :3] - f["polarization"][:, :3]).max()
+        res[f"{thr:g}"] = {"value": r["rate"], "speedup_vs_fp64": r["rate"] / f["rate"],
+                           "fallback_fraction_mean": float(r["fallback_fraction"].mean()),
+                           "fallback_fraction_max": float(r["fallback_fraction"].max()),
+                           "polarization_err_max": float(dp)}
+    for sur in nets:
+        sur.close()
+    pol = f["polarization"]
+    return {
+        "workload": f"{n_energies} energies (G*gamma0 from {gam[0] * beams[0].G:.4f} to "
+                    f"{gam[-1] * beams[0].G:.4f}) x {n_per} particles x {turns} turns on "
+                    f"rhic_like_ring; {n_bands} band networks (7 inputs), audit every {audit_every}",
+        "unit": "particle-turns/s",
+        "fp64_value": f["rate"],
+        "surrogate_by_threshold": res,
+        "band_training_seconds": t_train,
+        "polarization_fp64": {"Py_min": float(pol[:, 1].min()), "Py_max": float(pol[:, 1].max()),
+                              "per_energy_Py": [round(float(v), 6) for v in pol[:, 1]]},
+        "survival_min": float(f["survival"].min()),
+    }
 
 
 def main():
@@ -261,10 +392,20 @@ def main():
     }
     if not args.no_mixed:
         out["mixed"] = mixed_leg(ring, beam, args.mixed_particles, args.mixed_turns, stream)
+    if not args.no_surrogate:
+        out["surrogate"] = scan_leg(ring, args.band_energies, args.scan_particles, args.scan_turns,
+                                    args.audit_every, args.threshold, args.band_train_per_energy,
+                                    args.band_epochs, args.lr, 1)
+    if args.c3:
+        out["c3_training"] = c3_leg(ring, beam, args.c3_samples, args.c3_epochs, 65536, args.lr)
+    if args.c4:
+        out["c4_scan"] = scan_leg(ring, args.c4_energies, args.scan_particles, args.scan_turns,
+                                  args.audit_every, args.threshold, args.band_train_per_energy,
+                                  args.band_epochs, args.lr, max(1, args.c4_energies // 16))
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(ring, beam, z, s, a, args.cpu_sample_particles,
-                                           args.cpu_sample_turns)
+                                           args.cpu_sample_turns, 256, 4)
     print(json.dumps(out), flush=True)
 
 

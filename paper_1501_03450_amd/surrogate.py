@@ -191,3 +191,108 @@ def track(sur: Surrogate, tracker: SpinTracker, turns: int, audit_every: int, th
     B.st_track_surrogate(tracker.ctx, sur.net, turns, audit_every, threshold, sur.center,
                          sur.inv_scale, sur.extra(tracker.beam.gamma0), fallback.data_ptr(),
                          stream.cuda_stream if stream is not None else None)
+
+
+# ---------------------------------------------------------------------------
+# Energy scans: one bunch per reference energy, networks per energy band
+# ---------------------------------------------------------------------------
+
+def band_slices(n_energies: int, n_bands: int):
+    """Contiguous bands of energies (index ranges)."""
+    edges = np.linspace(0, n_energies, n_bands + 1).round().astype(int)
+    return [range(edges[b], edges[b + 1]) for b in range(n_bands)]
+
+
+def train_band(ring, beams, n_per_energy: int, seed: int, epochs: int, batch: int, lr: float,
+               widen: float = 3.0, net_seed: int = 1, device: int = 0, log=None) -> Surrogate:
+    """A 7-input network for a band of reference energies: inputs are the six
+    coordinates and the energy offset within the band; labels are tracked one
+    turn at each energy of the band (widened bunch)."""
+    import torch
+    from workloads import gaussian_bunch
+    g = np.array([b.gamma0 for b in beams])
+    centre = 0.5 * (g.min() + g.max())
+    half = max(0.5 * (g.max() - g.min()), 1e-12)
+    mid = beams[int(np.argmin(np.abs(g - centre)))]
+    ref = design_quaternion(ring, mid, device=device)
+    c, inv = feature_map(mid, widen)
+    sur = new_surrogate(7, net_seed, c, inv, ref, device=device, gamma_center=centre,
+                        gamma_half_width=half)
+    xs, ts = [], []
+    for k, beam in enumerate(beams):
+        z, _, _ = gaussian_bunch(n_per_energy, seed + k, beam, scale=widen)
+        x, t = label_bunch(sur, ring, beam, z, device=device)
+        xs.append(x)
+        ts.append(t)
+    # interleave the energies so that every batch sees the whole band
+    n = min(x.shape[0] for x in xs)
+    x = torch.stack([v[:n] for v in xs], dim=1).reshape(-1, 7).contiguous()
+    t = torch.stack([v[:n] for v in ts], dim=1).reshape(-1, 4).contiguous()
+    set_scale(sur, frame_from_targets(t[:65536].cpu().numpy(), ref))
+    train(sur, x, t, epochs, min(batch, x.shape[0]), lr, log=log)
+    return sur
+
+
+def energy_scan(ring, bunches, turns: int, nets=None, audit_every: int = 50,
+                threshold: float = 1e-6, n_streams: int = 4, device: int = 0, log=None):
+    """Track one bunch per reference energy, spread over n_streams streams.
+
+    bunches: list of (beam, z, spin, alive); nets: None for the plain
+    double-precision tracker, else one Surrogate per bunch (shared objects
+    allowed).  Returns wall-clock seconds of the tracking (from the first
+    launch to the last completion, inputs resident), and per bunch the final
+    polarization (Px, Py, Pz, N_alive), the survival and the fallback
+    fraction."""
+    import time
+    import torch
+    dev = torch.device("cuda", device)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    trackers, falls = [], []
+    for (beam, z, s, a) in bunches:
+        tr = SpinTracker(ring, beam, device=device, report_every=turns)
+        tr.set_particles(z, s, a)
+        trackers.append(tr)
+        falls.append(torch.zeros(z.shape[1], dtype=torch.int32, device=dev) if nets else None)
+    torch.cuda.synchronize(dev)
+
+    # One host thread per stream: surrogate tracking queues a few launches per
+    # turn, and a full queue blocks only the thread that feeds it.
+    errors = []
+
+    def feed(k):
+        try:
+            for i in range(k, len(trackers), n_streams):
+                st = streams[k]
+                if nets is None:
+                    trackers[i].track(turns, stream=st)
+                else:
+                    track(nets[i], trackers[i], turns, audit_every, threshold, falls[i], stream=st)
+        except Exception as e:          # reported after the join
+            errors.append(e)
+
+    import threading
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=feed, args=(k,)) for k in range(n_streams)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
+    if log:
+        log(f"tracked {len(trackers)} bunches x {turns} turns in {wall:.2f} s")
+    pol, surv, fb = [], [], []
+    for i, tr in enumerate(trackers):
+        p = tr.polarization().cpu().numpy()
+        pol.append(p[-1] if len(p) else np.full(4, np.nan))
+        alive = tr.alive
+        surv.append(float((alive == 1).float().mean().item()))
+        if falls[i] is not None:
+            fb.append(float((falls[i] != 0).float().mean().item()))
+        tr.close()
+    n_pt = sum(b[1].shape[1] for b in bunches) * turns
+    return {"seconds": wall, "particle_turns": n_pt, "rate": n_pt / wall,
+            "polarization": np.array(pol), "survival": np.array(surv),
+            "fallback_fraction": np.array(fb) if fb else None}

@@ -11,4 +11,6 @@ from .lattice import (  # noqa: F401
     KINDS, METHODS, Element, small_ring, rhic_like_ring, uniform_bend_ring,
     lattice_summary, element_table,
 )
-from .bunch import Beam, gaussian_bunch, widened_bunch, energy_scan_gammas  # noqa: F401
+from .bunch import (  # noqa: F401
+    Beam, gaussian_bunch, widened_bunch, energy_scan_gammas, energy_scan_bunches,
+)

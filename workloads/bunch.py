@@ -38,10 +38,9 @@ class Beam:
 SIGMAS = {"X": 1e-3, "Px": 1e-4, "Y": 1e-3, "Py": 1e-4, "T": 1e-2, "delta": 1e-3}
 
 
-def _draw(n: int, seed: int, scale: float, beam: Beam):
-    rng = np.random.Generator(np.random.Philox(key=seed))
-    g = rng.standard_normal((6, n))
-    z = np.empty((6, n), dtype=np.float64)
+def _coords(g: np.ndarray, scale: float, beam: Beam) -> np.ndarray:
+    """Coordinates from standard normals g[6][n] (rows X, Px, Y, Py, T, δ)."""
+    z = np.empty(g.shape, dtype=np.float64)
     z[0] = SIGMAS["X"] * scale * g[0]
     z[1] = SIGMAS["Px"] * scale * g[1]
     z[2] = SIGMAS["Y"] * scale * g[2]
@@ -51,6 +50,11 @@ def _draw(n: int, seed: int, scale: float, beam: Beam):
     b0g0 = beam.beta0 * beam.gamma0
     z[5] = np.sqrt((1.0 + delta) ** 2 + 1.0 / (b0g0 * b0g0)) - 1.0 / beam.beta0
     return z
+
+
+def _draw(n: int, seed: int, scale: float, beam: Beam):
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    return _coords(rng.standard_normal((6, n)), scale, beam)
 
 
 def gaussian_bunch(n: int, seed: int, beam: Beam = Beam(), scale: float = 1.0):
@@ -73,6 +77,23 @@ def energy_scan_gammas(n_energies: int = 256, G: float = PROTON_G,
     i = np.arange(n_energies, dtype=np.float64)
     ggamma = ggamma_lo + (ggamma_hi - ggamma_lo) * (i + 0.5) / n_energies
     return ggamma / G
+
+
+def energy_scan_bunches(gammas, n_per: int, seed: int, G: float = PROTON_G, scale: float = 1.0):
+    """One bunch per reference energy from a single seeded draw: bunch i uses
+    the normals of columns [i·n_per, (i+1)·n_per) of one (6, len·n_per) draw,
+    converted to Pt with its own β0.  Returns a list of (beam, z, spin, alive)."""
+    gammas = np.asarray(gammas, dtype=np.float64)
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    g_all = rng.standard_normal((6, len(gammas) * n_per))
+    out = []
+    for i, g0 in enumerate(gammas):
+        beam = Beam(G=G, gamma0=float(g0))
+        z = _coords(g_all[:, i * n_per:(i + 1) * n_per], scale, beam)
+        spin = np.zeros((3, n_per))
+        spin[1] = 1.0
+        out.append((beam, np.ascontiguousarray(z), spin, np.ones(n_per, dtype=np.int32)))
+    return out
 
 
 def random_spins(n: int, seed: int, opening_angle: float) -> np.ndarray:
