@@ -10,9 +10,10 @@
 //
 // Kernels (one batch, 64 samples per workgroup of four waves):
 //   forward        all four layers fused, activations kept in LDS; when
-//                  training it stores the pre-activations (fp32) and the
-//                  activations (bf16) feature-major for the backward pass and
-//                  fuses the loss and dL/dy of the normalised output
+//                  training it stores the pre-activations (fp32,
+//                  sample-major) and the activations (bf16, feature-major,
+//                  copied out of LDS in 128-byte rows) for the backward pass
+//                  and fuses the loss and dL/dy of the normalised output
 //   backward_data  dL/dy -> dz3 -> dz2 -> dz1 through the transposed bf16
 //                  weights, with per-workgroup partial sums of the bias and
 //                  vector-layer weight gradients
@@ -35,31 +36,48 @@ constexpr int TM = 64;             // samples per workgroup
 constexpr int LDA = W + 8;         // padded LDS row (bf16 elements)
 constexpr int NT = 256;            // threads per workgroup
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// σ(z) = 1/(1 + e^-z) with the hardware exponential and reciprocal
+// (about 1 ulp each): the activations are rounded to bf16 right after.
+__device__ __forceinline__ float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float dsilu(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
 // acc[mt][nt] += A[64 x 256] (LDS, row stride LDA) · B'[n_base + 16 nt + j][k]
-// (global, row-major [256][256]) for the wave's 64 output columns.
+// (global, row-major [256][256]) for the wave's 64 output columns.  The B
+// fragments of the next 32-wide k step are loaded before the current step's
+// sixteen MFMAs, so the L2 latency overlaps the matrix work.
 __device__ __forceinline__ void gemm_64x64(const __bf16* A, const __bf16* Bg, int n_base,
                                            f32x4 acc[4][4], int lane) {
   const int r = lane & 15, kb = 8 * (lane >> 4);
-#pragma unroll 2
+  const __bf16* brow = Bg + (size_t)(n_base + r) * W + kb;
+  bf16x8 b[4], bn[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) b[nt] = *reinterpret_cast<const bf16x8*>(brow + nt * 16 * W);
+#pragma unroll
   for (int k0 = 0; k0 < W; k0 += 32) {
-    bf16x8 a[4], b[4];
+    if (k0 + 32 < W) {
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        bn[nt] = *reinterpret_cast<const bf16x8*>(brow + nt * 16 * W + k0 + 32);
+    }
+    bf16x8 a[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
       a[mt] = *reinterpret_cast<const bf16x8*>(A + (mt * 16 + r) * LDA + k0 + kb);
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
-      b[nt] = *reinterpret_cast<const bf16x8*>(Bg + (size_t)(n_base + nt * 16 + r) * W + k0 + kb);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
         acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+    if (k0 + 32 < W) {
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) b[nt] = bn[nt];
+    }
   }
 }
 
@@ -71,12 +89,12 @@ __device__ __forceinline__ void zero_acc(f32x4 acc[4][4]) {
 }
 
 // Hidden-layer epilogue: z = acc + b, h = silu(z) into LDS (bf16, row-major)
-// and, when training, zT (fp32) and hT (bf16) feature-major in HBM.
+// and, when training, z (fp32) sample-major [ld][256] in HBM (16 lanes write
+// 64 contiguous bytes of one sample).
 template <bool TRAIN>
 __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const float* bias,
-                                                __bf16* out_lds, float* zT, __bf16* hT,
-                                                int64_t ld, int64_t b0, int rows, int n_base,
-                                                int lane) {
+                                                __bf16* out_lds, float* zS, int64_t b0, int rows,
+                                                int n_base, int lane) {
   const int c = lane & 15, rq = 4 * (lane >> 4);
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -85,23 +103,29 @@ __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const flo
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
       const int m0 = mt * 16 + rq;
-      float z[4], h[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        z[i] = acc[mt][nt][i] + bn;
-        h[i] = silu(z[i]);
-        out_lds[(m0 + i) * LDA + n] = (__bf16)h[i];
-      }
-      if (TRAIN) {
+        const float z = acc[mt][nt][i] + bn;
         // padded samples (beyond the batch) carry zero activations
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const bool ok = m0 + i < rows;
-          zT[(size_t)n * ld + b0 + m0 + i] = ok ? z[i] : 0.0f;
-          hT[(size_t)n * ld + b0 + m0 + i] = (__bf16)(ok ? h[i] : 0.0f);
-        }
+        const bool ok = m0 + i < rows;
+        out_lds[(m0 + i) * LDA + n] = (__bf16)(ok ? silu(z) : 0.0f);
+        if (TRAIN) zS[(size_t)(b0 + m0 + i) * W + n] = ok ? z : 0.0f;
       }
     }
+  }
+}
+
+// Copy a 64-sample × 256-feature bf16 tile from LDS (sample-major, pitch
+// LDA) to HBM feature-major [256][ld] at column b0: eight lanes write the 128
+// contiguous bytes of one feature.
+__device__ __forceinline__ void store_feature_major(const __bf16* lds, __bf16* outT, int64_t ld,
+                                                    int64_t b0, int tid) {
+  for (int it = tid; it < W * (TM / 8); it += NT) {
+    const int n = it >> 3, ch = it & 7;
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = lds[(ch * 8 + e) * LDA + n];
+    *reinterpret_cast<bf16x8*>(outT + (size_t)n * ld + b0 + ch * 8) = v;
   }
 }
 
@@ -135,26 +159,24 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
       float z = bn;
 #pragma unroll
       for (int k = 0; k < kMlpMaxIn; ++k) z = fmaf(w[k], xs[m][k], z);
-      const float h = silu(z);
-      bufA[m * LDA + n] = (__bf16)h;
-      if (TRAIN) {
-        a.zT1[(size_t)n * a.ld + b0 + m] = m < rows ? z : 0.0f;
-        a.hT1[(size_t)n * a.ld + b0 + m] = (__bf16)(m < rows ? h : 0.0f);
-      }
+      bufA[m * LDA + n] = (__bf16)(m < rows ? silu(z) : 0.0f);
+      if (TRAIN) a.zS1[(size_t)(b0 + m) * W + n] = m < rows ? z : 0.0f;
     }
   }
   __syncthreads();
+  if (TRAIN) store_feature_major(bufA, a.hT1, a.ld, b0, tid);
 
   f32x4 acc[4][4];
   // layer 2 (MFMA)
   zero_acc(acc);
   gemm_64x64(bufA, a.W2b, wv * 64, acc, lane);
-  hidden_epilogue<TRAIN>(acc, P + a.off.b2, bufB, a.zT2, a.hT2, a.ld, b0, rows, wv * 64, lane);
+  hidden_epilogue<TRAIN>(acc, P + a.off.b2, bufB, a.zS2, b0, rows, wv * 64, lane);
   __syncthreads();
+  if (TRAIN) store_feature_major(bufB, a.hT2, a.ld, b0, tid);
   // layer 3 (MFMA)
   zero_acc(acc);
   gemm_64x64(bufB, a.W3b, wv * 64, acc, lane);
-  hidden_epilogue<TRAIN>(acc, P + a.off.b3, bufA, a.zT3, a.hT3, a.ld, b0, rows, wv * 64, lane);
+  hidden_epilogue<TRAIN>(acc, P + a.off.b3, bufA, a.zS3, b0, rows, wv * 64, lane);
   __syncthreads();
 
   // layer 4 (vector): thread t -> sample t % 64, output t / 64
@@ -162,7 +184,11 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
     const int m = tid & 63, j = tid >> 6;
     const float* w4 = P + a.off.W4 + j * W;
     float y = P[a.off.b4 + j];
-    for (int k = 0; k < W; ++k) y = fmaf(w4[k], (float)bufA[m * LDA + k], y);
+    for (int k = 0; k < W; k += 8) {
+      const bf16x8 h = *reinterpret_cast<const bf16x8*>(bufA + m * LDA + k);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) y = fmaf(w4[k + e], (float)h[e], y);
+    }
     ys[m][j] = y;
   }
   __syncthreads();
@@ -236,7 +262,7 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
     for (int m = 0; m < TM; ++m) {
       float dz = 0.0f;
       if (m < rows) {
-        const float z = a.zT3[(size_t)k * a.ld + b0 + m];
+        const float z = a.zS3[(size_t)(b0 + m) * W + k];
         const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
         dz = dh * dsilu(z);
         const float h = silu(z);
@@ -246,13 +272,13 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
         gw[3] = fmaf(dys[m][3], h, gw[3]);
         gb += dz;
       }
-      a.dzT3[(size_t)k * a.ld + b0 + m] = (__bf16)dz;
       bufA[m * LDA + k] = (__bf16)dz;
     }
     for (int j = 0; j < 4; ++j) a.gpart_W4[((size_t)blk * 4 + j) * W + k] = gw[j];
     a.gpart_b3[(size_t)blk * W + k] = gb;
   }
   __syncthreads();
+  store_feature_major(bufA, a.dzT3, a.ld, b0, tid);
 
   f32x4 acc[4][4];
   const int c = lane & 15, rq = 4 * (lane >> 4);
@@ -268,13 +294,13 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float dz = 0.0f;
-        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zT2[(size_t)n * a.ld + b0 + m0 + i]);
-        a.dzT2[(size_t)n * a.ld + b0 + m0 + i] = (__bf16)dz;
+        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zS2[(size_t)(b0 + m0 + i) * W + n]);
         bufB[(m0 + i) * LDA + n] = (__bf16)dz;
       }
     }
   }
   __syncthreads();
+  store_feature_major(bufB, a.dzT2, a.ld, b0, tid);
   {
     float s = 0.0f;
     for (int m = 0; m < rows; ++m) s += (float)bufB[m * LDA + tid];
@@ -293,7 +319,7 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float dz = 0.0f;
-        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zT1[(size_t)n * a.ld + b0 + m0 + i]);
+        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zS1[(size_t)(b0 + m0 + i) * W + n]);
         bufA[(m0 + i) * LDA + n] = (__bf16)dz;
       }
     }
@@ -355,14 +381,28 @@ __global__ void __launch_bounds__(NT) mlp_weight_grad_kernel(const MlpArgs a) {
         out[(size_t)(n0 + i * 16 + rq + e) * W + k0 + j * 16 + c] = acc[i][j][e];
 }
 
-// out[i] = Σ_r part[r][i] in a fixed order.
+// Partial sums part[r][i] (r < parts, i < len) reduced over r in a fixed
+// order, 64 parts per workgroup row: out[blockIdx.y][i] = Σ_{r in chunk} part[r][i].
+// A workgroup covers C columns (C = 64, or fewer for short rows) with 256/C
+// threads per column; every thread sums a strided subset of the chunk and
+// the subsets are combined in LDS in thread order.
 __global__ void __launch_bounds__(256) sum_partials_kernel(const float* part, int64_t len, int parts,
-                                                           float* out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= len) return;
+                                                           int C, float* out) {
+  __shared__ float acc[256];
+  const int t = threadIdx.x, c = t % C, g = t / C, G = 256 / C;
+  const int64_t i = (int64_t)blockIdx.x * C + c;
+  const int r0 = blockIdx.y * 64, r1 = min(parts, r0 + 64);
   float s = 0.0f;
-  for (int r = 0; r < parts; ++r) s += part[(size_t)r * len + i];
-  out[i] = s;
+  if (i < len)
+#pragma unroll 4
+    for (int r = r0 + g; r < r1; r += G) s += part[(size_t)r * len + i];
+  acc[t] = s;
+  __syncthreads();
+  if (g == 0 && i < len) {
+    float v = 0.0f;
+    for (int k = 0; k < G; ++k) v += acc[k * C + c];
+    out[(size_t)blockIdx.y * len + i] = v;
+  }
 }
 
 __global__ void __launch_bounds__(256) adam_kernel(const MlpArgs a, float lr, float c1, float c2) {
@@ -418,10 +458,31 @@ hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, hipStream_t s) {
+// Reduce in passes of 64 parts per row until at most 64 rows are left, then
+// once more into out.  tmp: 2 · len · ceil(parts/64) floats (two halves used
+// alternately), needed only when parts > 64.
+hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, float* tmp,
+                               hipStream_t s) {
   if (len <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, part,
-                     len, parts, out);
+  int C = 64;
+  while (C > 1 && C / 2 >= len) C /= 2;
+  const dim3 block(256);
+  const unsigned gx = (unsigned)((len + C - 1) / C);
+  const size_t half = (size_t)len * (size_t)((parts + 63) / 64);
+  const float* src = part;
+  int rows = parts, k = 0;
+  while (rows > 64) {
+    float* dst = tmp + (k & 1) * half;
+    const int next = (rows + 63) / 64;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(gx, (unsigned)next), block, 0, s, src, len, rows, C,
+                       dst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = dst;
+    rows = next;
+    ++k;
+  }
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(gx, 1u), block, 0, s, src, len, rows, C, out);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // C ABI of the spin surrogate network (see include/spintrack.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -26,10 +27,10 @@ struct st_mlp {
   // training scratch, sized for the largest batch seen
   int64_t cap_ld = 0;
   std::vector<void*> scratch;
-  float *zT[3] = {nullptr, nullptr, nullptr};
-  __bf16 *hT[3] = {nullptr, nullptr, nullptr};
+  float *zS[3] = {nullptr, nullptr, nullptr};
+  __bf16 *hT[2] = {nullptr, nullptr};
   __bf16 *dzT[2] = {nullptr, nullptr};
-  float *dy = nullptr, *loss_part = nullptr;
+  float *dy = nullptr, *loss_part = nullptr, *red_tmp = nullptr;
   float *gW1 = nullptr, *gb1 = nullptr, *gb2 = nullptr, *gb3 = nullptr, *gW4 = nullptr, *gb4 = nullptr;
   float *gW2 = nullptr, *gW3 = nullptr;
 };
@@ -86,11 +87,14 @@ st_status ensure_scratch(st_mlp* m, int64_t ld) {
   const int64_t W = st::kMlpWidth;
   const int64_t nb = ld / st::mlp_tile();
   hipError_t e = hipSuccess;
-  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = alloc(m, &m->zT[l], (size_t)(W * ld));
-  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = alloc(m, &m->hT[l], (size_t)(W * ld));
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = alloc(m, &m->zS[l], (size_t)(W * ld));
+  for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->hT[l], (size_t)(W * ld));
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->dzT[l], (size_t)(W * ld));
   if (e == hipSuccess) e = alloc(m, &m->dy, (size_t)(ld * 4));
   if (e == hipSuccess) e = alloc(m, &m->loss_part, (size_t)nb);
+  // two-pass reduction buffer for the per-workgroup partials (largest row: W1)
+  if (e == hipSuccess)
+    e = alloc(m, &m->red_tmp, (size_t)(2 * W * std::max(m->n_in, 4) * ((nb + 63) / 64)));
   if (e == hipSuccess) e = alloc(m, &m->gW1, (size_t)(nb * W * m->n_in));
   if (e == hipSuccess) e = alloc(m, &m->gb1, (size_t)(nb * W));
   if (e == hipSuccess) e = alloc(m, &m->gb2, (size_t)(nb * W));
@@ -146,8 +150,8 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
   a.inv_loss_norm = 1.0f / (float)batch;
   a.loss_part = m->loss_part;
   a.dy = m->dy;
-  a.zT1 = m->zT[0]; a.zT2 = m->zT[1]; a.zT3 = m->zT[2];
-  a.hT1 = m->hT[0]; a.hT2 = m->hT[1]; a.hT3 = m->hT[2];
+  a.zS1 = m->zS[0]; a.zS2 = m->zS[1]; a.zS3 = m->zS[2];
+  a.hT1 = m->hT[0]; a.hT2 = m->hT[1];
   a.dzT2 = m->dzT[0]; a.dzT3 = m->dzT[1];
   a.gpart_W1 = m->gW1; a.gpart_b1 = m->gb1; a.gpart_b2 = m->gb2; a.gpart_b3 = m->gb3;
   a.gpart_W4 = m->gW4; a.gpart_b4 = m->gb4; a.gpart_W2 = m->gW2; a.gpart_W3 = m->gW3;
@@ -164,9 +168,10 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
       {m->gb2, W, nb, o.b2}, {m->gW3, W * W, kSplits, o.W3}, {m->gb3, W, nb, o.b3},
       {m->gW4, 4 * W, nb, o.W4}, {m->gb4, 4, nb, o.b4}};
   for (auto& r : red)
-    if ((e = st::launch_sum_partials(r.part, r.len, r.parts, m->grad + r.off, s)) != hipSuccess)
+    if ((e = st::launch_sum_partials(r.part, r.len, r.parts, m->grad + r.off, m->red_tmp, s)) !=
+        hipSuccess)
       return hip_fail(m, e, "gradient reduction");
-  if (d_loss && (e = st::launch_sum_partials(m->loss_part, 1, nb, d_loss, s)) != hipSuccess)
+  if (d_loss && (e = st::launch_sum_partials(m->loss_part, 1, nb, d_loss, m->red_tmp, s)) != hipSuccess)
     return hip_fail(m, e, "loss reduction");
   return ST_OK;
 }

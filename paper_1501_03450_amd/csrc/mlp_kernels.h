@@ -55,12 +55,11 @@ struct MlpArgs {
   float out_scale[4];
   float inv_loss_norm;    // 1/batch
   float* loss_part;       // [blocks]
-  float* zT1;             // [256][ld] pre-activations
-  float* zT2;
-  float* zT3;
-  __bf16* hT1;            // [256][ld] activations
+  float* zS1;             // [ld][256] pre-activations, sample-major
+  float* zS2;
+  float* zS3;
+  __bf16* hT1;            // [256][ld] activations, feature-major
   __bf16* hT2;
-  __bf16* hT3;
   __bf16* dzT2;           // [256][ld] gradients at the pre-activations
   __bf16* dzT3;
   float* gpart_W1;        // per-block partial gradients
@@ -89,7 +88,8 @@ hipError_t launch_features(const double* z, int64_t n, const FeatureMap& f, int 
 hipError_t launch_targets(const double* q, int64_t n, const double* ref, float* t, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s);
 hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s);
-hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, hipStream_t s);
+hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, float* tmp,
+                               hipStream_t s);
 hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s);
 hipError_t launch_refresh_bf16(const MlpArgs& a, hipStream_t s);
 

@@ -47,6 +47,17 @@ def _data(n, n_in, seed):
     return x, t.astype(np.float32)
 
 
+def _coherent_data(n, n_in, seed):
+    """Inputs with a non-zero mean and targets clustered about one direction,
+    so that the mean-loss gradient is a coherent sum rather than a cancelling
+    one (which would magnify the kernels' bf16 rounding)."""
+    rng = np.random.default_rng(seed)
+    x = (1.0 + 0.3 * rng.normal(size=(n, n_in))).astype(np.float32)
+    t = np.array([1.0, 2.0, 3.0, 4.0]) + 0.2 * rng.normal(size=(n, 4))
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    return x, t.astype(np.float32)
+
+
 def _rel_fro(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
@@ -103,6 +114,52 @@ def test_gradient_matches_the_cpu_reference_tensor_by_tensor(frame):
         assert _rel_fro(a, b) <= 1e-2, (k, _rel_fro(a, b))
     l_cpu = M.loss(p, x.astype(np.float64), t.astype(np.float64), ref, scale)
     assert abs(loss.item() - l_cpu) <= 1e-3 * max(1.0, l_cpu)
+    B.st_mlp_destroy(m)
+
+
+def test_gradient_of_a_large_ragged_batch_matches_the_cpu_reference():
+    # 70001 samples: 1094 tiles of 64, so the per-tile partials are reduced
+    # in two passes
+    import torch
+    from paper_1501_03450_amd import binding as B
+    n_in, n = 6, 70001
+    m = B.st_mlp_create(0, n_in, 256, seed=14)
+    B.st_mlp_set_frame(m, *FRAME)
+    x, t = _coherent_data(n, n_in, 4)
+    dx, dt = _dev(x, np.float32), _dev(t, np.float32)   # keep both alive during the call
+    g = torch.zeros(B.st_mlp_params(m), dtype=torch.float32, device="cuda")
+    B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), n, g.data_ptr())
+    torch.cuda.synchronize()
+    p = _cpu_params(_params(m), n_in)
+    g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64), *FRAME)
+    errs = [_rel_fro(a, b) for a, b in zip(M.unflatten(g.cpu().numpy(), n_in), g_cpu)]
+    print("per-tensor relative errors", [f"{e:.1e}" for e in errs])
+    assert max(errs) <= 1e-2, errs
+    B.st_mlp_destroy(m)
+
+
+def test_gradient_of_a_batch_is_the_weighted_mean_of_its_parts():
+    # 300000 samples (4688 tiles: three reduction passes) against the two
+    # halves computed separately: the mean-loss gradient is linear in the
+    # per-sample terms
+    import torch
+    from paper_1501_03450_amd import binding as B
+    n_in, n, h = 6, 300000, 131072
+    m = B.st_mlp_create(0, n_in, 256, seed=15)
+    x, t = _coherent_data(n, n_in, 5)
+    dx, dt = _dev(x, np.float32), _dev(t, np.float32)
+    npar = B.st_mlp_params(m)
+    g = [torch.zeros(npar, dtype=torch.float32, device="cuda") for _ in range(3)]
+    B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), n, g[0].data_ptr())
+    B.st_mlp_gradient(m, dx[:h].data_ptr(), dt[:h].data_ptr(), h, g[1].data_ptr())
+    B.st_mlp_gradient(m, dx[h:].data_ptr(), dt[h:].data_ptr(), n - h, g[2].data_ptr())
+    torch.cuda.synchronize()
+    whole = g[0].cpu().numpy().astype(np.float64)
+    parts = (h * g[1].cpu().numpy().astype(np.float64) +
+             (n - h) * g[2].cpu().numpy().astype(np.float64)) / n
+    errs = [_rel_fro(a, b) for a, b in zip(M.unflatten(whole, n_in), M.unflatten(parts, n_in))]
+    print("per-tensor relative differences", [f"{e:.1e}" for e in errs])
+    assert max(errs) <= 1e-4, errs
     B.st_mlp_destroy(m)
 
 
