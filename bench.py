@@ -88,7 +88,7 @@ def parse():
     ap.add_argument("--turns-per-step", type=int, default=100)
     ap.add_argument("--particles", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-particles", type=int, default=4096)
+    ap.add_argument("--cpu-sample-particles", type=int, default=32768)
     ap.add_argument("--cpu-sample-turns", type=int, default=10)
     ap.add_argument("--mixed-particles", type=int, default=4 << 20)
     ap.add_argument("--mixed-turns", type=int, default=20)
@@ -405,7 +405,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(ring, beam, z, s, a, args.cpu_sample_particles,
-                                           args.cpu_sample_turns, 256, 4)
+                                           args.cpu_sample_turns, 1024, 10)
     print(json.dumps(out), flush=True)
 
 
