@@ -224,14 +224,19 @@ st_status st_mlp_targets(st_mlp* m, const double* d_q, int64_t n, const double* 
  * Each turn a particle with d_fallback[j] == 0 gets the orbit push and a spin
  * rotation by the network's quaternion for its turn-start coordinates
  * (inputs as in st_mlp_features); a particle with d_fallback[j] != 0 gets the
- * full double-precision turn.  Every audit_every-th turn (≥ 1) every particle
+ * full double-precision turn.  Every audit_every-th turn (>= 1) every particle
  * gets the full double-precision turn and its network quaternion is compared
- * with the tracked one: when the largest component difference (after
- * aligning the sign) exceeds `threshold`, d_fallback[j] is set to the turn
- * number (1-based) and the particle stays on the double-precision path.
- * d_fallback: device int32 [n], initialised by the caller.  Polarization is
- * recorded as in st_track.  Requires a lattice, particles and a network
- * created on the same device. */
+ * with the tracked one.  When the largest component difference (after
+ * aligning the sign) exceeds `threshold`, the particle falls back: d_fallback[j]
+ * is set to the turn number (1-based), its state is rolled back to the
+ * previous audit (or the start) and the turns since then are replayed in
+ * double precision, so its spin carries no network error; it stays on the
+ * double-precision path afterwards.  The orbit is the double-precision orbit
+ * throughout.  d_fallback: device int32 [n], initialised by the caller (0 =
+ * start on the network).  Polarization is recorded as in st_track; the
+ * beam's report_every must then be a multiple of audit_every, so that every
+ * report follows an audit.  Requires a lattice, particles and a network
+ * created on the same device.  Library scratch: 112 bytes per particle. */
 st_status st_track_surrogate(st_ctx* ctx, st_mlp* m, int64_t turns, int32_t audit_every,
                              double threshold, const double* center, const double* inv_scale,
                              double extra, int32_t* d_fallback, void* stream);

@@ -46,6 +46,9 @@ struct st_ctx {
   float* d_feat = nullptr;     // [n][8]
   float* d_qnn = nullptr;      // [n][4]
   double* d_q64 = nullptr;     // 4 × n
+  double* d_ck = nullptr;      // checkpoint of the last audit: z (6 × n) then spin (3 × n)
+  int32_t* d_ck_alive = nullptr;
+  int32_t* d_ralive = nullptr; // live set of a replay
   int64_t surr_cap = 0;
 };
 
@@ -276,9 +279,9 @@ st_status st_destroy(st_ctx* c) {
     if (c->d_seq) (void)hipFree(c->d_seq);
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_pol) (void)hipFree(c->d_pol);
-    if (c->d_feat) (void)hipFree(c->d_feat);
-    if (c->d_qnn) (void)hipFree(c->d_qnn);
-    if (c->d_q64) (void)hipFree(c->d_q64);
+    for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
+                    (void*)c->d_ck_alive, (void*)c->d_ralive})
+      if (p) (void)hipFree(p);
   }
   delete c;
   return ST_OK;
@@ -458,6 +461,8 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   if (!center || !inv_scale) return fail(c, ST_EINVAL, "feature scaling is NULL");
   if (c->n > 0 && !d_fallback) return fail(c, ST_EINVAL, "fallback array is NULL");
   if (st_mlp_device_of(m) != c->device) return fail(c, ST_EINVAL, "network on another device");
+  if (c->beam.report_every > 0 && c->beam.report_every % audit_every != 0)
+    return fail(c, ST_EINVAL, "report_every must be a multiple of audit_every");
   c->n_reports = 0;
   if (turns == 0 || c->n == 0) return ST_OK;
   DeviceGuard g(c->device);
@@ -465,11 +470,17 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   hipError_t e;
   const int64_t n = c->n;
   if (n > c->surr_cap) {
-    for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64}) if (p) (void)hipFree(p);
-    c->d_feat = nullptr; c->d_qnn = nullptr; c->d_q64 = nullptr; c->surr_cap = 0;
+    for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
+                    (void*)c->d_ck_alive, (void*)c->d_ralive})
+      if (p) (void)hipFree(p);
+    c->d_feat = nullptr; c->d_qnn = nullptr; c->d_q64 = nullptr; c->d_ck = nullptr;
+    c->d_ck_alive = nullptr; c->d_ralive = nullptr; c->surr_cap = 0;
     if ((e = hipMalloc(&c->d_feat, (size_t)n * 8 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&c->d_qnn, (size_t)n * 4 * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&c->d_q64, (size_t)n * 4 * sizeof(double))) != hipSuccess)
+        (e = hipMalloc(&c->d_q64, (size_t)n * 4 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->d_ck, (size_t)n * 9 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->d_ck_alive, (size_t)n * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_ralive, (size_t)n * sizeof(int32_t))) != hipSuccess)
       return fail(c, ST_ENOMEM, std::string("surrogate scratch: ") + hipGetErrorString(e));
     c->surr_cap = n;
   }
@@ -479,6 +490,21 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   const int64_t n_rep = rep_every > 0 ? turns / rep_every : 0;
   st_status pst = ensure_polarization(c, n_rep, nb);
   if (pst != ST_OK) return pst;
+  // Checkpoint of the state at the start and after every audit: a particle
+  // that fails an audit is rolled back to it and replayed in double precision.
+  auto checkpoint = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(c->d_ck, c->z, (size_t)n * 6 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(c->d_ck + 6 * n, c->spin, (size_t)n * 3 * sizeof(double),
+                         hipMemcpyDeviceToDevice, s);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(c->d_ck_alive, c->alive, (size_t)n * sizeof(int32_t),
+                         hipMemcpyDeviceToDevice, s);
+    return r;
+  };
+  if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");
+  int64_t last_audit = 0;
   for (int64_t t = 1; t <= turns; ++t) {
     st_status ms = st_mlp_features(m, c->z, n, center, inv_scale, extra, c->d_feat, stream);
     if (ms == ST_OK) ms = st_mlp_infer(m, c->d_feat, c->d_qnn, n, stream);
@@ -489,8 +515,27 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
     if (audit) {
       a.qout = c->d_q64;
       if ((e = st::launch_track(a, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "audit turn");
-      if ((e = st::launch_audit(c->alive, d_fallback, c->d_qnn, c->d_q64, n, threshold, (int32_t)t, s)) != hipSuccess)
+      if ((e = st::launch_audit(c->alive, d_fallback, c->d_qnn, c->d_q64, n, threshold, (int32_t)t,
+                                s)) != hipSuccess)
         return hip_fail(c, e, "audit");
+      // Roll the particles that failed back to the last checkpoint and replay
+      // the turns since then in double precision; the orbit is the same as on
+      // the surrogate path, so only their spins change.
+      if ((e = st::launch_replay_prepare(d_fallback, (int32_t)t, c->z, c->spin, c->d_ck,
+                                         c->d_ck + 6 * n, c->d_ck_alive, c->d_ralive, n, s)) !=
+          hipSuccess)
+        return hip_fail(c, e, "rollback");
+      st::TrackArgs r = track_args(c);
+      r.alive = c->d_ralive;
+      r.turns = (int)(t - last_audit);
+      r.report_every = 0;
+      r.partials = nullptr;
+      if ((e = st::launch_track(r, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "replay");
+      if ((e = st::launch_replay_finish(d_fallback, (int32_t)t, c->d_ralive, c->alive, n, s)) !=
+          hipSuccess)
+        return hip_fail(c, e, "replay status");
+      if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");
+      last_audit = t;
     } else {
       a.fallback = d_fallback;
       if ((e = st::launch_track(a, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "surrogate turn");
@@ -499,11 +544,13 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
     }
     if (n_rep > 0 && t % rep_every == 0) {
       const int64_t rep = t / rep_every - 1;
-      if ((e = st::launch_polarization_partials(c->spin, c->alive, n, c->d_partials + rep * nb * 4, s)) != hipSuccess)
+      if ((e = st::launch_polarization_partials(c->spin, c->alive, n, c->d_partials + rep * nb * 4,
+                                                s)) != hipSuccess)
         return hip_fail(c, e, "polarization");
     }
   }
-  if (n_rep > 0 && (e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol, s)) != hipSuccess)
+  if (n_rep > 0 && (e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol,
+                                                       s)) != hipSuccess)
     return hip_fail(c, e, "polarization reduction");
   c->n_reports = n_rep;
   c->err.clear();

@@ -259,6 +259,9 @@ track_kernel(const TrackArgs a) {
     T = a.z[4 * n + j]; Pt = a.z[5 * n + j];
     cold[0][tid] = a.spin[j]; cold[1][tid] = a.spin[n + j]; cold[2][tid] = a.spin[2 * n + j];
   }
+  // Without reports the kernel has no barrier, so a wave with no live lane
+  // (a replay of a few particles) may leave at once.
+  if (a.report_every == 0 && !__any(live)) return;
   const Particle p = make_particle(Pt, a);
   Quat qturn = qident();
   const bool spin_lane = !SURR || (valid && a.fallback[j] != 0);
@@ -446,6 +449,34 @@ __global__ void __launch_bounds__(256) audit_kernel(const int32_t* alive, int32_
   if (!(d <= threshold)) fallback[j] = turn;
 }
 
+// Rollback of the particles that failed the audit of turn `turn`: their
+// orbit, spin and status go back to the checkpoint of the previous audit, and
+// ralive marks exactly them as the live set of the replay launch.
+__global__ void __launch_bounds__(256) replay_prepare_kernel(const int32_t* fallback, int32_t turn,
+                                                             double* z, double* spin,
+                                                             const double* ck_z,
+                                                             const double* ck_spin,
+                                                             const int32_t* ck_alive,
+                                                             int32_t* ralive, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  if (fallback[j] != turn) {
+    ralive[j] = 0;
+    return;
+  }
+  for (int c = 0; c < 6; ++c) z[c * n + j] = ck_z[c * n + j];
+  for (int c = 0; c < 3; ++c) spin[c * n + j] = ck_spin[c * n + j];
+  ralive[j] = ck_alive[j];
+}
+
+// After the replay: the replayed particles take their status from it.
+__global__ void __launch_bounds__(256) replay_finish_kernel(const int32_t* fallback, int32_t turn,
+                                                            const int32_t* ralive, int32_t* alive,
+                                                            int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < n && fallback[j] == turn) alive[j] = ralive[j];
+}
+
 // Per-block sums (Sx, Sy, Sz, N) over alive particles for one report.
 __global__ void __launch_bounds__(256) polarization_partials_kernel(const double* spin,
                                                                     const int32_t* alive, int64_t n,
@@ -480,6 +511,23 @@ hipError_t launch_audit(const int32_t* alive, int32_t* fallback, const float* qn
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(audit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, alive, fallback,
                      qnn, q64, n, threshold, turn);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_prepare(const int32_t* fallback, int32_t turn, double* z, double* spin,
+                                 const double* ck_z, const double* ck_spin, const int32_t* ck_alive,
+                                 int32_t* ralive, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(replay_prepare_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     fallback, turn, z, spin, ck_z, ck_spin, ck_alive, ralive, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_finish(const int32_t* fallback, int32_t turn, const int32_t* ralive,
+                                int32_t* alive, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(replay_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     fallback, turn, ralive, alive, n);
   return hipGetLastError();
 }
 

@@ -20,6 +20,11 @@ hipError_t launch_surrogate_spin(double* spin, const int32_t* alive, const int32
                                  const float* qnn, int64_t n, hipStream_t s);
 hipError_t launch_audit(const int32_t* alive, int32_t* fallback, const float* qnn, const double* q64,
                         int64_t n, double threshold, int32_t turn, hipStream_t s);
+hipError_t launch_replay_prepare(const int32_t* fallback, int32_t turn, double* z, double* spin,
+                                 const double* ck_z, const double* ck_spin, const int32_t* ck_alive,
+                                 int32_t* ralive, int64_t n, hipStream_t s);
+hipError_t launch_replay_finish(const int32_t* fallback, int32_t turn, const int32_t* ralive,
+                                int32_t* alive, int64_t n, hipStream_t s);
 hipError_t launch_polarization_partials(const double* spin, const int32_t* alive, int64_t n,
                                         double* partials, hipStream_t s);
 

@@ -259,6 +259,8 @@ def energy_scan(ring, bunches, turns: int, nets=None, audit_every: int = 50,
     # turn, and a full queue blocks only the thread that feeds it.
     errors = []
 
+    done = [torch.cuda.Event() for _ in trackers]
+
     def feed(k):
         try:
             for i in range(k, len(trackers), n_streams):
@@ -267,6 +269,7 @@ def energy_scan(ring, bunches, turns: int, nets=None, audit_every: int = 50,
                     trackers[i].track(turns, stream=st)
                 else:
                     track(nets[i], trackers[i], turns, audit_every, threshold, falls[i], stream=st)
+                done[i].record(st)
         except Exception as e:          # reported after the join
             errors.append(e)
 
@@ -275,6 +278,14 @@ def energy_scan(ring, bunches, turns: int, nets=None, audit_every: int = 50,
     threads = [threading.Thread(target=feed, args=(k,)) for k in range(n_streams)]
     for th in threads:
         th.start()
+    # progress while the threads feed and the streams drain
+    last = time.perf_counter()
+    while any(th.is_alive() for th in threads) or not all(ev.query() for ev in done):
+        time.sleep(0.05)
+        if log and time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            log(f"{sum(ev.query() for ev in done)}/{len(trackers)} bunches done after "
+                f"{last - t0:.1f} s")
     for th in threads:
         th.join()
     torch.cuda.synchronize(dev)

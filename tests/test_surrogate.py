@@ -271,6 +271,32 @@ def test_threshold_zero_sends_every_particle_to_the_fallback_at_the_first_audit(
     assert (fb[as_ == 1] == 3).all()
 
 
+def test_a_particle_that_fails_its_audit_is_replayed_in_double_precision():
+    # threshold 0 and one audit at the last turn: every particle is rolled back
+    # to the start and replayed in one double-precision launch, so the result
+    # is the plain tracker's bit for bit
+    z, s, a = gaussian_bunch(700, 204, BEAM)
+    (zs, ss, as_), fb = _surrogate_run(small_ring(), z, s, a, 4, 4, 0.0)
+    z64, s64, a64 = _fp64_run(small_ring(), z, s, a, 4)
+    assert (fb == 4).all()
+    np.testing.assert_array_equal(zs, z64)
+    np.testing.assert_array_equal(ss, s64)
+    np.testing.assert_array_equal(as_, a64)
+
+
+def test_after_a_rollback_the_spin_stays_the_double_precision_spin():
+    # threshold 0, audits at turns 3 and 6 of 7: rollback and replay at turn
+    # 3, full double-precision turns afterwards
+    z, s, a = gaussian_bunch(700, 205, BEAM)
+    (zs, ss, as_), fb = _surrogate_run(rhic_like_ring(), z, s, a, 7, 3, 0.0)
+    z64, s64, a64 = _fp64_run(rhic_like_ring(), z, s, a, 7)
+    np.testing.assert_array_equal(as_, a64)
+    sig = z64.std(axis=1)
+    rel = np.abs(zs - z64) / np.maximum(np.abs(z64), sig[:, None])
+    assert rel.max() <= 1e-12 * 7
+    assert np.abs(ss - s64).max() <= 1e-12
+
+
 def test_without_fallback_the_orbit_is_the_double_precision_orbit():
     z, s, a = gaussian_bunch(700, 203, BEAM)
     turns = 3
