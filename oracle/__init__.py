@@ -31,12 +31,14 @@ _lock = threading.Lock()
 _lib = None
 
 KIND_CODES = {"marker": 0, "drift": 1, "sbend": 2, "quad": 3, "thin": 4, "snake": 5}
-METHOD_CODES = {"exact": 0, "dkd": 1, "mk": 2}
+METHOD_CODES = {"exact": 0, "dkd": 1, "mk": 2, "teapot": 3}
+SPIN_CODES = {"edges": 0, "kick": 1, "midpoint": 2}
 
 
 class _Elem(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("nsl", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("spin", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("L", ctypes.c_double), ("angle", ctypes.c_double), ("eta", ctypes.c_double),
                 ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
                 ("phi", ctypes.c_double), ("mu", ctypes.c_double)]
@@ -84,13 +86,19 @@ def _elems(elements):
         a.kind = KIND_CODES[e.kind]
         a.method = METHOD_CODES[e.method]
         a.nsl, a.rows = int(e.n_slices), int(e.rows)
+        a.spin = SPIN_CODES[getattr(e, "spin", "edges")]
         a.L, a.angle, a.eta = e.L, e.angle, e.eta
         a.k1, a.k1l, a.k2l = e.k1, e.k1l, e.k2l
         a.phi, a.mu = e.snake_phi, e.snake_mu
-        if e.kind == "sbend" and e.method != "exact":
-            raise ValueError("sector bends use the exact map")
+        if e.kind == "sbend" and e.method not in ("exact", "teapot"):
+            raise ValueError("sector bends use the exact map or teapot drift-kick slices")
         if e.kind == "quad" and e.method not in ("dkd", "mk"):
             raise ValueError("quadrupoles use dkd or mk slices")
+        if e.kind in ("sbend", "quad"):
+            if a.spin == SPIN_CODES["kick"] and e.method not in ("dkd", "teapot"):
+                raise ValueError("the kick spin placement needs drift-kick slices")
+            if a.spin != SPIN_CODES["edges"] and e.rows != 1:
+                raise ValueError("piece-wise constant spin placements take rows = 1")
         if e.kind in ("sbend", "quad") and (e.n_slices < 1 or e.rows < 1 or e.L <= 0):
             raise ValueError("thick elements need L > 0, n_slices >= 1, rows >= 1")
     return arr

@@ -116,10 +116,17 @@ inline long double value_(long double a) { return a; }
 // ---------------------------------------------------------------------------
 
 enum Kind : int32_t { MARKER = 0, DRIFT = 1, SBEND = 2, QUAD = 3, THIN = 4, SNAKE = 5 };
-enum Method : int32_t { EXACT = 0, DKD = 1, MK = 2 };
+enum Method : int32_t { EXACT = 0, DKD = 1, MK = 2, TEAPOT = 3 };
+// Where the spin is integrated inside a thick element:
+//   EDGES     Ω at the N + 1 slice edges, trapezoid products and Romberg (§4.3)
+//   KICK      drift-kick slices only: the rotation by Δs Ω sits between the two
+//             half kicks of each slice (the DKS placement of §5.2)
+//   MIDPOINT  piece-wise constant rotation by Δs Ω at the middle of each slice,
+//             between two half slices (§4.1 eq. pwcSpin; DKDS in §5.2)
+enum SpinPlace : int32_t { EDGES = 0, KICK = 1, MIDPOINT = 2 };
 
 struct Elem {             // the oracle's own element record
-  int32_t kind, method, nsl, rows;
+  int32_t kind, method, nsl, rows, spin, pad;
   double L, angle, eta, k1, k1l, k2l, phi, mu;
 };
 
@@ -225,6 +232,32 @@ template <class T> void sbend_step(T z[6], T s, T h, T eta, const Ref<T>& r) {
   z[Y] = z[Y] + (T(1) / eta) * Py * s + (T(1) / (eta * h)) * Py * D;
   z[TT] = z[TT] - (T(1) / eta) * Pt * s - (T(1) / (eta * h)) * (T(1) / r.beta0 + Pt) * D
           + (T(1) - T(1) / eta) * s / r.beta0;
+}
+
+// TEAPOT drift in a sector bend over a length s (§3.6 eq. teapotD): the flow
+// of H_D = -(1 + hX) Ps, a straight line seen from the rotating frame.  The
+// Pt/β0 term of eq. generalH (the reference particle's flight time) is
+// added to T here, as in the straight drift.
+template <class T> void teapot_drift(T z[6], T s, T h, const Ref<T>& r) {
+  using std::cos; using std::sin;
+  T ps = ps_of(z, r);
+  T Xi = z[X], Pxi = z[PX];
+  T c = cos(h * s), sn = sin(h * s);
+  T tn = sn / c;
+  T R = T(1) / h + Xi;
+  T den = T(1) - (Pxi / ps) * tn;
+  T path = R * tn / den;
+  z[X] = R * (T(1) / c) / den - T(1) / h;
+  z[PX] = Pxi * c + ps * sn;
+  z[Y] = z[Y] + (z[PY] / ps) * path;
+  z[TT] = z[TT] - (T(1) / r.beta0 + z[PT]) / ps * path + s / r.beta0;
+}
+
+// Kick of the sector-bend dipole over a length s (§3.6 eq. teapotHK): with
+// the field b_y = η h on the reference arc the vector-potential term is
+// H_K = η h (X + h X²/2), so Px -= η h (1 + hX) s.
+template <class T> void bend_kick(T z[6], T s, T h, T eta) {
+  z[PX] = z[PX] - eta * h * (T(1) + h * z[X]) * s;
 }
 
 // Matrix-kick quadrupole, linear part over a length s (§3.3 eq. quadL).  The
@@ -345,9 +378,26 @@ Quat<T> romberg_spin(const std::vector<T>& om, int N, T ds, int R) {
 // One element: orbit map and spin quaternion
 // ---------------------------------------------------------------------------
 
+// The drift and kick halves of a drift-kick slice (TEAPOT bend or DKD quad).
+template <class T>
+void dk_drift(const Elem& e, T z[6], T s, const Ref<T>& r) {
+  if (e.kind == SBEND) teapot_drift(z, s, T(e.angle) / T(e.L), r);
+  else                 drift(z, s, r);
+}
+
+template <class T>
+void dk_kick(const Elem& e, T z[6], T s) {
+  if (e.kind == SBEND) bend_kick(z, s, T(e.angle) / T(e.L), T(e.eta));
+  else                 kick(z, T(e.k1) * s, T(0));
+}
+
 template <class T>
 void slice(const Elem& e, T z[6], T ds, const Ref<T>& r) {
-  if (e.kind == SBEND) {
+  if (e.kind == SBEND && e.method == TEAPOT) {   // drift-kick-drift (§3.6)
+    dk_drift(e, z, ds / T(2), r);
+    dk_kick(e, z, ds);
+    dk_drift(e, z, ds / T(2), r);
+  } else if (e.kind == SBEND) {
     sbend_step(z, ds, T(e.angle) / T(e.L), T(e.eta), r);
   } else if (e.method == DKD) {           // drift-kick-drift (§3.4 applied to m = 2)
     drift(z, ds / T(2), r);
@@ -371,8 +421,32 @@ Quat<T> element(const Elem& e, T z[6], const Ref<T>& r) {
       int N = e.nsl;
       T ds = T(e.L) / T(N);
       T h = e.kind == SBEND ? T(e.angle) / T(e.L) : T(0);
-      std::vector<T> om(3 * (N + 1));
       T b[3];
+      if (e.spin != EDGES) {
+        // piece-wise constant rotations ω = Δs Ω (eq. pwcSpin), one per slice,
+        // Ω taken at the slice's middle state; later slices on the left
+        Quat<T> Q = qident<T>();
+        for (int j = 0; j < N; ++j) {
+          if (e.spin == KICK) {
+            dk_drift(e, z, ds / T(2), r);
+            dk_kick(e, z, ds / T(2));
+          } else {
+            slice(e, z, ds / T(2), r);
+          }
+          T w[3];
+          field(e, z, b);
+          omega(z, h, b, r, w);
+          Q = qmul(qrot(ds * w[0], ds * w[1], ds * w[2]), Q);
+          if (e.spin == KICK) {
+            dk_kick(e, z, ds / T(2));
+            dk_drift(e, z, ds / T(2), r);
+          } else {
+            slice(e, z, ds / T(2), r);
+          }
+        }
+        return qnormalise(Q);
+      }
+      std::vector<T> om(3 * (N + 1));
       field(e, z, b);
       omega(z, h, b, r, &om[0]);
       for (int j = 1; j <= N; ++j) {

@@ -34,7 +34,8 @@ from typing import List, Sequence
 import numpy as np
 
 KINDS = ("marker", "drift", "sbend", "quad", "thin", "snake")
-METHODS = ("exact", "dkd", "mk")
+METHODS = ("exact", "dkd", "mk", "teapot")
+SPIN_PLACES = ("edges", "kick", "midpoint")
 
 
 @dataclasses.dataclass(frozen=True)
@@ -52,24 +53,30 @@ class Element:
     n_slices: int = 1
     rows: int = 1
     name: str = ""
+    spin: str = "edges"
 
     def __post_init__(self):
         if self.kind not in KINDS:
             raise ValueError(f"unknown element kind {self.kind!r}")
         if self.method not in METHODS:
             raise ValueError(f"unknown integration method {self.method!r}")
+        if self.spin not in SPIN_PLACES:
+            raise ValueError(f"unknown spin placement {self.spin!r}")
 
 
 def drift(L: float, name: str = "D") -> Element:
     return Element("drift", L=L, name=name)
 
 
-def sbend(L: float, angle: float, n: int, rows: int, eta: float = 1.0, name: str = "SB") -> Element:
-    return Element("sbend", L=L, angle=angle, eta=eta, n_slices=n, rows=rows, name=name)
+def sbend(L: float, angle: float, n: int, rows: int, eta: float = 1.0, name: str = "SB",
+          method: str = "exact", spin: str = "edges") -> Element:
+    return Element("sbend", L=L, angle=angle, eta=eta, n_slices=n, rows=rows, name=name,
+                   method=method, spin=spin)
 
 
-def quad(L: float, k1: float, method: str, n: int, rows: int, name: str = "Q") -> Element:
-    return Element("quad", L=L, k1=k1, method=method, n_slices=n, rows=rows, name=name)
+def quad(L: float, k1: float, method: str, n: int, rows: int, name: str = "Q",
+         spin: str = "edges") -> Element:
+    return Element("quad", L=L, k1=k1, method=method, n_slices=n, rows=rows, name=name, spin=spin)
 
 
 def thin(k1l: float = 0.0, k2l: float = 0.0, name: str = "M") -> Element:
