@@ -111,6 +111,9 @@ def parse():
                     help="full energy scan: 256 energies x 65536 particles, 16 bands")
     ap.add_argument("--c4-energies", type=int, default=256)
     ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--compare-integrators", action="store_true",
+                    help="one-turn errors and throughput of drift-kick vs bend-kick/matrix-kick "
+                         "orbits with PWC and Romberg spin on the small ring")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one device copy of 1 GiB and one tracking launch "
                          "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), print the source hash")
@@ -291,6 +294,82 @@ def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_e
     }
 
 
+def integrator_leg(beam, n=4096, slices=(1, 2, 4, 8, 16, 32, 64)):
+    """The paper's integrator comparison (§5.2) on the small ring: one-turn
+    orbit and spin errors of drift-kick (TEAPOT bends and DKD quadrupoles,
+    DKS and DKDS spin placements) against bend-kick/matrix-kick orbits
+    (midpoint PWC spin, and Romberg over the slice edges), against a
+    reference of bend-kick/matrix-kick with 256 slices and 3 Romberg rows;
+    plus each method's throughput on the same ring."""
+    import math as m
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from workloads import gaussian_bunch
+    from workloads.bunch import SEED_BASE, random_spins
+    from workloads.lattice import drift, quad, sbend, snake
+    th = 2 * m.pi / 32
+
+    def ring(style, N):
+        if style in ("dk_kick", "dk_midpoint"):
+            place = "kick" if style == "dk_kick" else "midpoint"
+            qf = quad(1.0, 0.05, "dkd", N, 1, "QF", spin=place)
+            qd = quad(1.0, -0.05, "dkd", N, 1, "QD", spin=place)
+            sb = sbend(10.0, th, N, 1, method="teapot", spin=place)
+        elif style == "bkmk_midpoint":
+            qf = quad(1.0, 0.05, "mk", N, 1, "QF", spin="midpoint")
+            qd = quad(1.0, -0.05, "mk", N, 1, "QD", spin="midpoint")
+            sb = sbend(10.0, th, N, 1, spin="midpoint")
+        else:                                   # bkmk_romberg{R}
+            R = int(style[-1])
+            qf = quad(1.0, 0.05, "mk", N, R, "QF")
+            qd = quad(1.0, -0.05, "mk", N, R, "QD")
+            sb = sbend(10.0, th, N, R)
+        cell = [qf, drift(2.0), sb, drift(2.0), qd, drift(2.0), sb, drift(2.0)]
+        return cell * 16 + [snake(m.pi, 0.0)]
+
+    z, _, a = gaussian_bunch(n, SEED_BASE, beam)
+    s = random_spins(n, SEED_BASE + 7, m.pi)
+    n_time = 1 << 18                       # enough workgroups to fill the chip
+    zt, st_, at = gaussian_bunch(n_time, SEED_BASE, beam)
+
+    def one_turn(elems, turns=1, timing=False):
+        tr = SpinTracker(elems, beam)
+        if timing:
+            tr.set_particles(zt, st_, at)
+        else:
+            tr.set_particles(z, s, a)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        tr.track(turns)
+        ev1.record()
+        ev1.synchronize()
+        out = tr.read()
+        tr.close()
+        return out, ev0.elapsed_time(ev1) / 1e3
+
+    (zr, sr, ar), _ = one_turn(ring("bkmk_romberg3", 256))
+    live = ar == 1
+    sig = zr[:, live].std(axis=1)
+    table = {}
+    for style in ("dk_kick", "dk_midpoint", "bkmk_midpoint", "bkmk_romberg2", "bkmk_romberg3"):
+        rows = []
+        for N in slices:
+            if style.startswith("bkmk_romberg") and N < 2 ** (int(style[-1]) - 1):
+                continue
+            (zz, ss, aa), _ = one_turn(ring(style, N))
+            ok = live & (aa == 1)
+            orb = float((np.abs(zz[:, ok] - zr[:, ok]) / sig[:, None]).max())
+            spin = float(np.abs(ss[:, ok] - sr[:, ok]).max())
+            (_, _, _), secs = one_turn(ring(style, N), turns=5, timing=True)
+            rows.append({"slices": N, "orbit_err_over_sigma": orb, "spin_err": spin,
+                         "particle_turns_per_s": n_time * 5 / secs})
+            log(f"[bench] integrators {style} N={N}: orbit {orb:.2e} spin {spin:.2e}")
+        table[style] = rows
+    return {"workload": f"small ring (129 elements), {n} protons, all spin directions; "
+                        "reference: bend-kick/matrix-kick, 256 slices, 3 Romberg rows",
+            "one_turn": table}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -402,6 +481,8 @@ def main():
         out["c4_scan"] = scan_leg(ring, args.c4_energies, args.scan_particles, args.scan_turns,
                                   args.audit_every, args.threshold, args.band_train_per_energy,
                                   args.band_epochs, args.lr, max(1, args.c4_energies // 16))
+    if args.compare_integrators:
+        out["integrators"] = integrator_leg(beam)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(ring, beam, z, s, a, args.cpu_sample_particles,

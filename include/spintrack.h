@@ -62,8 +62,21 @@ typedef enum {
 typedef enum {
   ST_ORB_EXACT = 0, /* exact flow: drifts and sector bends                     */
   ST_ORB_DKD = 1,   /* drift-kick-drift slices (quadrupoles)                   */
-  ST_ORB_MK = 2     /* matrix-kick-matrix slices (§3.3 eq. quadConcat)         */
+  ST_ORB_MK = 2,    /* matrix-kick-matrix slices (§3.3 eq. quadConcat)         */
+  ST_ORB_TEAPOT = 3 /* sector bend in drift-kick-drift slices: the drift of the
+                       curved frame (§3.6 eq. teapotD) and the dipole kick
+                       Px -= eta h (1 + hX) ds (from eq. teapotHK)             */
 } st_orbit;
+
+typedef enum {
+  ST_SPIN_EDGES = 0,   /* Ω at the N + 1 slice edges, trapezoid level products
+                          and the Romberg tableau (§4.3)                       */
+  ST_SPIN_KICK = 1,    /* drift-kick slices only: one rotation by ds·Ω per
+                          slice between its two half kicks (§5.2, "DKS")      */
+  ST_SPIN_MIDPOINT = 2 /* one rotation by ds·Ω per slice, Ω at the slice's
+                          middle between two half slices (§4.1 eq. pwcSpin;
+                          "DKDS" for drift-kick slices)                        */
+} st_spin_place;
 
 typedef enum {
   ST_FP64 = 0,      /* every step in double precision                          */
@@ -85,10 +98,15 @@ typedef enum {
  *   snake_phi    snake rotation angle [rad]; axis (sin mu, 0, cos mu) in (x, y, s)
  *   n_slices     orbit slices N of a thick element with spin (sbend, quad)
  *   romberg_rows requested tableau rows R ≥ 1 (§4.3 eq. romberg); the rows
- *                used are R_e = min(R, 1 + ν2(N)), ν2 the power of 2 in N
+ *                used are R_e = min(R, 1 + ν2(N)), ν2 the power of 2 in N;
+ *                must be 1 unless spin_place is ST_SPIN_EDGES
+ *   spin_place   where the spin is integrated in a thick element
+ *                (st_spin_place); ST_SPIN_KICK needs DKD quadrupole or
+ *                TEAPOT bend slices
+ *   reserved     must be 0
  */
 typedef struct {
-  int32_t kind, orbit, n_slices, romberg_rows;
+  int32_t kind, orbit, n_slices, romberg_rows, spin_place, reserved;
   double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu;
 } st_element;
 

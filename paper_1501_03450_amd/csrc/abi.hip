@@ -26,6 +26,7 @@ struct st_ctx {
   int n_elems = 0;
   int n_unique = 0;
   int nt = 16;             // quaternion series terms
+  bool ext = false;        // lattice needs the extended kernel (TEAPOT, PWC placements)
   double ymax = 0.0;
   st::DevElem* d_tab = nullptr;
   uint32_t* d_seq = nullptr;
@@ -97,17 +98,23 @@ std::string validate(const st_element& e, int64_t i) {
   const std::string at = "element " + std::to_string(i) + ": ";
   if (!finite_all(e)) return at + "non-finite parameter";
   if (e.kind < ST_MARKER || e.kind > ST_SNAKE) return at + "unknown kind " + std::to_string(e.kind);
-  if (e.orbit < ST_ORB_EXACT || e.orbit > ST_ORB_MK) return at + "unknown orbit method";
+  if (e.orbit < ST_ORB_EXACT || e.orbit > ST_ORB_TEAPOT) return at + "unknown orbit method";
+  if (e.spin_place < ST_SPIN_EDGES || e.spin_place > ST_SPIN_MIDPOINT)
+    return at + "unknown spin placement";
+  if (e.reserved != 0) return at + "reserved field must be 0";
   if (e.L < 0.0) return at + "negative length";
   switch (e.kind) {
     case ST_DRIFT:
       if (e.orbit != ST_ORB_EXACT) return at + "drifts use the exact method";
       break;
     case ST_SBEND:
-      if (e.orbit != ST_ORB_EXACT) return at + "sector bends use the exact method";
+      if (e.orbit != ST_ORB_EXACT && e.orbit != ST_ORB_TEAPOT)
+        return at + "sector bends use the exact or the TEAPOT method";
       if (!(e.L > 0.0)) return at + "sector bend needs L > 0";
       if (e.angle == 0.0) return at + "sector bend needs a non-zero angle";
-      if (!(e.eta > 0.0)) return at + "sector bend needs eta > 0";
+      if (e.orbit == ST_ORB_EXACT && !(e.eta > 0.0)) return at + "exact sector bend needs eta > 0";
+      if (std::fabs(0.5 * e.angle / e.n_slices) >= 1.0)
+        return at + "slice angle too large for the TEAPOT drift";
       break;
     case ST_QUAD:
       if (e.orbit != ST_ORB_DKD && e.orbit != ST_ORB_MK) return at + "quadrupoles use DKD or MK";
@@ -120,6 +127,14 @@ std::string validate(const st_element& e, int64_t i) {
     if (e.n_slices < 1) return at + "n_slices must be >= 1";
     if (e.romberg_rows < 1 || e.romberg_rows > st::kMaxRows)
       return at + "romberg_rows must be in 1.." + std::to_string(st::kMaxRows);
+    if (e.spin_place != ST_SPIN_EDGES && e.romberg_rows != 1)
+      return at + "piece-wise constant spin placements take romberg_rows = 1";
+    if (e.spin_place == ST_SPIN_KICK && e.orbit != ST_ORB_DKD && e.orbit != ST_ORB_TEAPOT)
+      return at + "the kick spin placement needs drift-kick slices";
+    if (e.spin_place == ST_SPIN_MIDPOINT && e.n_slices > (1 << 29))
+      return at + "too many slices";
+  } else if (e.spin_place != ST_SPIN_EDGES || e.orbit == ST_ORB_TEAPOT) {
+    return at + "spin placements and TEAPOT slices apply to thick elements only";
   }
   return std::string();
 }
@@ -139,6 +154,7 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
   std::memset(&d, 0, sizeof(d));
   d.kind = e.kind;
   d.orbit = e.orbit;
+  d.place = e.spin_place;
   d.nsl = 1;
   d.K = 0;
   // Only the sliced elements: a thin element costs one rotation, and its
@@ -147,14 +163,31 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
   if (thick && (beam.precision == ST_MIXED_ALL ||
                 (beam.precision == ST_MIXED && design_angle(e, beam, 0.005) <= kSpin32MaxAngle)))
     d.flags |= st::F_SPIN32;
+  // orbit slices: the midpoint placement runs 2N half slices
+  const int n_orb = e.spin_place == ST_SPIN_MIDPOINT ? 2 * e.n_slices : e.n_slices;
   if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
-    d.nsl = e.n_slices;
+    d.nsl = n_orb;
     const int re = std::min(e.romberg_rows, 1 + v2(e.n_slices));
     d.K = re - 1;
   }
-  if (e.kind == ST_SBEND) {
+  if (e.kind == ST_SBEND && e.orbit == ST_ORB_TEAPOT) {
+    st::TeapotParams& t = d.tp;
+    t.ds = e.L / n_orb;
+    t.h = e.angle / e.L;
+    t.eta_h = e.eta * t.h;
+    t.half = 0.5 * t.ds;
+    t.half_ib0 = t.half / beta0;
+    const double a = t.h * t.half;
+    t.c = std::cos(a);
+    t.sn = std::sin(a);
+    t.tn = t.sn / t.c;
+    t.sec = 1.0 / t.c;
+    t.tn_h = t.tn / t.h;
+    const double s2 = std::sin(0.5 * a);
+    t.omc_h = 2.0 * s2 * s2 / (t.c * t.h);   // (sec - 1)/h
+  } else if (e.kind == ST_SBEND) {
     st::BendParams& b = d.b;
-    b.ds = e.L / e.n_slices;
+    b.ds = e.L / n_orb;
     b.h = e.angle / e.L;
     b.eta = e.eta;
     b.eta_h = e.eta * b.h;
@@ -174,7 +207,7 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
     b.whole = step(e.L);
   } else if (e.kind == ST_QUAD) {
     st::QuadParams& q = d.q;
-    q.ds = e.L / e.n_slices;
+    q.ds = e.L / n_orb;
     q.hds = 0.5 * q.ds;
     q.k1 = e.k1;
     q.k1ds = e.k1 * q.ds;
@@ -201,7 +234,7 @@ double design_angle(const st_element& e, const st_beam& b, double r_ref) {
   const double a1 = 1.0 + b.G * b.gamma0;
   if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
     const double ds = e.L / e.n_slices;
-    const double f = e.n_slices > 1 ? ds : 0.5 * ds;
+    const double f = (e.n_slices > 1 || e.spin_place != ST_SPIN_EDGES) ? ds : 0.5 * ds;
     double om;
     if (e.kind == ST_SBEND) {
       const double h = e.angle / e.L;
@@ -313,7 +346,9 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   std::vector<st_element> uniq;
   std::vector<uint32_t> seq((size_t)n);
   double theta = 0.0;
+  bool ext = false;
   for (int64_t i = 0; i < n; ++i) {
+    ext = ext || els[i].orbit == ST_ORB_TEAPOT || els[i].spin_place != ST_SPIN_EDGES;
     int k = -1;
     for (size_t u = 0; u < uniq.size(); ++u)
       if (std::memcmp(&uniq[u], &els[i], sizeof(st_element)) == 0) { k = (int)u; break; }
@@ -350,6 +385,7 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   c->ymax = series_ymax(c->nt);
   c->beam = *b;
   c->beta0 = beta0;
+  c->ext = ext;
   c->n_elems = (int)n;
   c->n_unique = (int)uniq.size();
   c->have_lattice = true;
@@ -402,7 +438,7 @@ st_status st_track(st_ctx* c, int64_t turns, void* stream) {
   a.turns = (int32_t)turns;
   a.report_every = rep_every;
   a.partials = c->d_partials;
-  if ((e = st::launch_track(a, c->nt, c->beam.precision != ST_FP64, s)) != hipSuccess)
+  if ((e = st::launch_track(a, c->nt, c->beam.precision != ST_FP64, c->ext, s)) != hipSuccess)
     return hip_fail(c, e, "launch track");
   if (n_rep > 0) {
     if ((e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol, s)) != hipSuccess)
@@ -514,7 +550,7 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
     a.turns = 1;
     if (audit) {
       a.qout = c->d_q64;
-      if ((e = st::launch_track(a, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "audit turn");
+      if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "audit turn");
       if ((e = st::launch_audit(c->alive, d_fallback, c->d_qnn, c->d_q64, n, threshold, (int32_t)t,
                                 s)) != hipSuccess)
         return hip_fail(c, e, "audit");
@@ -530,7 +566,7 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
       r.turns = (int)(t - last_audit);
       r.report_every = 0;
       r.partials = nullptr;
-      if ((e = st::launch_track(r, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "replay");
+      if ((e = st::launch_track(r, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "replay");
       if ((e = st::launch_replay_finish(d_fallback, (int32_t)t, c->d_ralive, c->alive, n, s)) !=
           hipSuccess)
         return hip_fail(c, e, "replay status");
@@ -538,7 +574,7 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
       last_audit = t;
     } else {
       a.fallback = d_fallback;
-      if ((e = st::launch_track(a, c->nt, false, s)) != hipSuccess) return hip_fail(c, e, "surrogate turn");
+      if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "surrogate turn");
       if ((e = st::launch_surrogate_spin(c->spin, c->alive, d_fallback, c->d_qnn, n, s)) != hipSuccess)
         return hip_fail(c, e, "surrogate spin");
     }

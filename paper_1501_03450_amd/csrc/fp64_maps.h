@@ -118,15 +118,52 @@ __device__ __forceinline__ void omega_straight(double bx, double by, double Px, 
 }
 
 // Precession vector in a sector bend, b = (0, ηh, 0), with the frame term h ŷ.
-__device__ __forceinline__ void omega_bend(const BendParams& e, double X, double Px, double Py,
-                                           double r, const Particle& p,
-                                           double& ox, double& oy, double& oz) {
-  double w = fma(e.h, X, 1.0) * e.eta_h;
+__device__ __forceinline__ void omega_dipole(double h, double eta_h, double X, double Px, double Py,
+                                             double r, const Particle& p,
+                                             double& ox, double& oy, double& oz) {
+  double w = fma(h, X, 1.0) * eta_h;
   double g = w * r;
   double a2py = p.a2() * Py * p.invP2();
   ox = g * a2py * Px;
-  oy = fma(-g, fma(-a2py, Py, p.a1()), e.h);
+  oy = fma(-g, fma(-a2py, Py, p.a1()), h);
   oz = w * a2py;
+}
+
+__device__ __forceinline__ void omega_bend(const BendParams& e, double X, double Px, double Py,
+                                           double r, const Particle& p,
+                                           double& ox, double& oy, double& oz) {
+  omega_dipole(e.h, e.eta_h, X, Px, Py, r, p, ox, oy, oz);
+}
+
+// Drift of the curved frame over half a drift-kick slice (§3.6 eq. teapotD),
+// a straight line seen from the rotating frame.  X(s) is evaluated as
+// [X sec + (sec - 1)/h + (Px/Ps) tan/h] / (1 - (Px/Ps) tan), the printed
+// form without its 1/h - 1/h cancellation; the flight time adds the
+// reference particle's (ds/2)/β0 (the Pt/β0 term of eq. generalH).
+__device__ __forceinline__ void teapot_drift(const TeapotParams& t, double& X, double& Px, double& Y,
+                                             double Py, double& T, const Particle& p) {
+  const double ps2 = p.P2() - fma(Px, Px, Py * Py);
+  const double r = rsqrt_nr(ps2);
+  const double ps = ps2 * r;
+  const double u = Px * r;
+  const double inv_den = rcp_nr(fma(-u, t.tn, 1.0));
+  const double path = fma(X, t.tn, t.tn_h) * inv_den;
+  X = fma(X, t.sec, fma(u, t.tn_h, t.omc_h)) * inv_den;
+  Px = fma(Px, t.c, ps * t.sn);
+  Y = fma(Py * r, path, Y);
+  T = fma(-p.ib() * r, path, T + t.half_ib0);
+}
+
+// Dipole kick of a TEAPOT bend over a length len: Px -= ηh (1 + hX) len.
+__device__ __forceinline__ void teapot_kick(const TeapotParams& t, double len, double X, double& Px) {
+  Px = fma(-t.eta_h * len, fma(t.h, X, 1.0), Px);
+}
+
+__device__ __forceinline__ void teapot_slice(const TeapotParams& t, double& X, double& Px, double& Y,
+                                             double Py, double& T, const Particle& p) {
+  teapot_drift(t, X, Px, Y, Py, T, p);
+  teapot_kick(t, t.ds, X, Px);
+  teapot_drift(t, X, Px, Y, Py, T, p);
 }
 
 // One step of the exact sector bend over the slice length (§3.1 eq. sbend),

@@ -14,7 +14,11 @@
 namespace st {
 
 enum : int32_t { K_MARKER = 0, K_DRIFT = 1, K_SBEND = 2, K_QUAD = 3, K_THIN = 4, K_SNAKE = 5 };
-enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2 };
+enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2, M_TEAPOT = 3 };
+// spin placement in thick elements: Romberg over the slice edges, or one
+// piece-wise constant rotation per slice between the half kicks or at the
+// slice's middle
+enum : int32_t { P_EDGES = 0, P_KICK = 1, P_MIDPOINT = 2 };
 
 constexpr int kMaxRows = 4;   // Romberg tableau rows supported by the kernels
 
@@ -36,19 +40,29 @@ struct QuadParams {        // quadrupole (§3.3, §3.4)
   double k1, k1ds;         // gradient, DKD kick k1·ds
   double kabs_hds2;        // |k1| (ds/2)²: (κ ds/2)² times P
 };
+struct TeapotParams {       // drift-kick sector bend (§3.6)
+  double ds;                // orbit slice length (kick length)
+  double h, eta_h;          // curvature and dipole field ηh
+  double half, half_ib0;    // drift half ds/2 and (ds/2)/β0
+  double c, sn, tn, sec;    // cos, sin, tan, 1/cos of h ds/2
+  double tn_h, omc_h;       // tan(h ds/2)/h and (1/cos(h ds/2) - 1)/h
+};
 struct DriftParams { double L; };
 struct ThinParams { double k1l, k2l; };             // thin multipole (§3.5)
 struct SnakeParams { double qw, qx, qy, qz; };      // fixed rotation quaternion
 
 constexpr int kElemWords = sizeof(BendParams) / sizeof(double);   // largest member
+static_assert(sizeof(TeapotParams) <= sizeof(BendParams), "element union size");
 
 enum : int32_t { F_SPIN32 = 1 };   // element flag: single-precision spin arithmetic
 
 struct DevElem {
   int32_t kind, orbit, nsl, K;   // K = R_e - 1: Romberg levels minus one
-  int32_t flags, pad_;
+  int32_t flags, place;          // place: P_EDGES, P_KICK or P_MIDPOINT (nsl = 2N orbit
+                                 // half slices for P_MIDPOINT)
   union {
     BendParams b;
+    TeapotParams tp;
     QuadParams q;
     DriftParams d;
     ThinParams t;

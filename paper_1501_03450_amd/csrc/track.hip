@@ -47,7 +47,8 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
 
 // Romberg spin integration through one thick element, fused with its orbit
 // slices (KIND: 0 sector bend, 1 MK quadrupole focusing in x, 3 MK
-// quadrupole focusing in y, 2 DKD quadrupole).  In the MIXED kernel,
+// quadrupole focusing in y, 2 DKD quadrupole, 4 drift-kick (TEAPOT) sector
+// bend).  In the MIXED kernel,
 // elements flagged F_SPIN32 use single-precision edge quaternions and
 // compensated single-precision level products.  Returns the normalised
 // element quaternion.
@@ -58,7 +59,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   static_assert(kMaxRows == 4, "the level products below are written out for four rows");
   const int N = el.nsl;
   const int K = el.K;
-  const double ds = KIND == 0 ? el.b.ds : el.q.ds;
+  const double ds = KIND == 0 ? el.b.ds : (KIND == 4 ? el.tp.ds : el.q.ds);
   const bool spin32 = MIXED && (el.flags & F_SPIN32);
   // running products of the Romberg levels: level m keeps every 2^m-th edge
   Quat Q0 = qident(), Q1 = qident(), Q2 = qident(), Q3 = qident();
@@ -85,7 +86,9 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
       if (KIND == 0) {
         bend_step(el.b, el.b.slice, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
       } else {
-        if (KIND == 1) {
+        if (KIND == 4) {
+          teapot_slice(el.tp, X, Px, Y, Py, T, p);
+        } else if (KIND == 1) {
           mk_linear(mc, X, Px, Y, Py, T, p);
           mk_nonlinear(ds, X, Px, Y, Py, T, p);
           mk_linear(mc, X, Px, Y, Py, T, p);
@@ -104,8 +107,9 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
       }
     }
     double ox, oy, oz;
-    if (KIND == 0) omega_bend(el.b, X, Px, Py, r, p, ox, oy, oz);
-    else           omega_straight(el.q.k1 * Y, el.q.k1 * X, Px, Py, r, p, ox, oy, oz);
+    if (KIND == 0)      omega_bend(el.b, X, Px, Py, r, p, ox, oy, oz);
+    else if (KIND == 4) omega_dipole(el.tp.h, el.tp.eta_h, X, Px, Py, r, p, ox, oy, oz);
+    else                omega_straight(el.q.k1 * Y, el.q.k1 * X, Px, Py, r, p, ox, oy, oz);
     const double om2 = fma(ox, ox, fma(oy, oy, oz * oz));
     // Level m keeps this edge when 2^m divides j, with step w 2^m ds: the
     // rotation about Ω by 2^m times the finest angle, i.e. the finest
@@ -192,7 +196,9 @@ __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double
   MKConst mc;
   if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
   for (int j = 0; j < el.nsl; ++j) {
-    if (KIND == 1) {
+    if (KIND == 4) {
+      teapot_slice(el.tp, X, Px, Y, Py, T, p);
+    } else if (KIND == 1) {
       mk_linear(mc, X, Px, Y, Py, T, p);
       mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
       mk_linear(mc, X, Px, Y, Py, T, p);
@@ -207,6 +213,97 @@ __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double
       drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
     }
   }
+}
+
+// Piece-wise constant spin through a thick element (§4.1 eq. pwcSpin): one
+// rotation by ds·Ω per slice, later slices on the left, Ω taken between the
+// two half kicks of a drift-kick slice (PLACE == P_KICK; KIND 2 or 4) or at
+// the middle of the slice (P_MIDPOINT: the element carries 2N orbit half
+// slices and the rotation follows every odd one).
+template <int NT, int KIND, int PLACE>
+__device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double& Px, double& Y,
+                                            double& Py, double& T, const Particle& p,
+                                            const TrackArgs& a) {
+  const double ds_orb = KIND == 0 ? el.b.ds : (KIND == 4 ? el.tp.ds : el.q.ds);
+  const double w = PLACE == P_MIDPOINT ? 2.0 * ds_orb : ds_orb;   // spin step
+  Quat Q = qident();
+  MKConst mc;
+  if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+  double Pa2 = 0.0, invPa2 = 0.0, W = 0.0, r = 0.0, wme = 0.0;
+  if (KIND == 0) {
+    Pa2 = p.P2() - Py * Py;
+    invPa2 = rcp_nr(Pa2);
+    const double ps2 = fma(-Px, Px, Pa2);
+    r = rsqrt_nr(ps2);
+    W = ps2 * r;
+    wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
+  }
+  for (int j = 1; j <= el.nsl; ++j) {
+    if (PLACE == P_KICK) {
+      if (KIND == 4) {
+        teapot_drift(el.tp, X, Px, Y, Py, T, p);
+        teapot_kick(el.tp, 0.5 * el.tp.ds, X, Px);
+      } else {
+        drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+        Px = fma(-0.5 * el.q.k1ds, X, Px);
+        Py = fma(0.5 * el.q.k1ds, Y, Py);
+      }
+    } else if (KIND == 0) {
+      bend_step(el.b, el.b.slice, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
+    } else if (KIND == 4) {
+      teapot_slice(el.tp, X, Px, Y, Py, T, p);
+    } else if (KIND == 1) {
+      mk_linear(mc, X, Px, Y, Py, T, p);
+      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
+      mk_linear(mc, X, Px, Y, Py, T, p);
+    } else if (KIND == 3) {
+      mk_linear(mc, Y, Py, X, Px, T, p);
+      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
+      mk_linear(mc, Y, Py, X, Px, T, p);
+    } else {
+      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+      Px = fma(-el.q.k1ds, X, Px);
+      Py = fma(el.q.k1ds, Y, Py);
+      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+    }
+    if (PLACE == P_KICK || (j & 1)) {
+      if (KIND != 0) r = rsqrt_nr(p.P2() - fma(Px, Px, Py * Py));
+      double ox, oy, oz;
+      if (KIND == 0)      omega_bend(el.b, X, Px, Py, r, p, ox, oy, oz);
+      else if (KIND == 4) omega_dipole(el.tp.h, el.tp.eta_h, X, Px, Py, r, p, ox, oy, oz);
+      else                omega_straight(el.q.k1 * Y, el.q.k1 * X, Px, Py, r, p, ox, oy, oz);
+      double c, sfac;
+      rot_half_angle<NT>(0.25 * w * w * fma(ox, ox, fma(oy, oy, oz * oz)), a.ymax, c, sfac);
+      const double g = sfac * w;
+      Q = qmul(Quat{c, g * ox, g * oy, g * oz}, Q);
+    }
+    if (PLACE == P_KICK) {
+      if (KIND == 4) {
+        teapot_kick(el.tp, 0.5 * el.tp.ds, X, Px);
+        teapot_drift(el.tp, X, Px, Y, Py, T, p);
+      } else {
+        Px = fma(-0.5 * el.q.k1ds, X, Px);
+        Py = fma(0.5 * el.q.k1ds, Y, Py);
+        drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+      }
+    }
+  }
+  const double inv = rsqrt_nr(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
+  return {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
+}
+
+// Spin and orbit of a thick element with the extended methods: TEAPOT bends
+// and the piece-wise constant placements.
+template <int NT, int KIND>
+__device__ __forceinline__ Quat thick_ext(const DevElem& el, double& X, double& Px, double& Y,
+                                       double& Py, double& T, const Particle& p,
+                                       const TrackArgs& a) {
+  if (el.place == P_KICK) {
+    if (KIND == 2 || KIND == 4) return pwc_element<NT, KIND, P_KICK>(el, X, Px, Y, Py, T, p, a);
+    return qident();   // rejected on the host
+  }
+  if (el.place == P_MIDPOINT) return pwc_element<NT, KIND, P_MIDPOINT>(el, X, Px, Y, Py, T, p, a);
+  return thick_element<NT, KIND, false>(el, X, Px, Y, Py, T, p, a);
 }
 
 template <int NT>
@@ -238,7 +335,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // SURR: surrogate tracking; lanes with fallback[j] == 0 leave the spin to the
 // network (the caller rotates it), and waves without a fallback lane skip the
 // spin arithmetic altogether.
-template <int NT, bool MIXED, bool SURR>
+// EXT: the kernel also knows the drift-kick sector bend and the piece-wise
+// constant spin placements (kept out of the other instantiations so that
+// their register allocation is not shaped by code they never run).
+template <int NT, bool MIXED, bool SURR, bool EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ST_WAVES_PER_EU)))
 track_kernel(const TrackArgs a) {
   __shared__ double red[kBlock / 64][4];
@@ -292,7 +392,8 @@ track_kernel(const TrackArgs a) {
       if (SURR && !__any(spin_lane)) {   // no lane of this wave needs the spin
         spin = false;
         if (e.kind == K_SBEND) {
-          thick_orbit<0>(e, X, Px, Y, Py, T, p, a);
+          if (EXT && e.orbit == M_TEAPOT) thick_orbit<4>(e, X, Px, Y, Py, T, p, a);
+          else                            thick_orbit<0>(e, X, Px, Y, Py, T, p, a);
         } else if (e.kind == K_QUAD) {
           if (e.orbit != M_MK)    thick_orbit<2>(e, X, Px, Y, Py, T, p, a);
           else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a);
@@ -303,6 +404,15 @@ track_kernel(const TrackArgs a) {
             Px -= fma(hk1, X, 0.5 * hk2 * (X * X - Y * Y));
             Py += fma(hk1, Y, hk2 * X * Y);
           }
+        }
+      } else if (EXT && (e.kind == K_SBEND || e.kind == K_QUAD)) {
+        if (e.kind == K_SBEND) {
+          if (e.orbit == M_TEAPOT) q = thick_ext<NT, 4>(e, X, Px, Y, Py, T, p, a);
+          else                     q = thick_ext<NT, 0>(e, X, Px, Y, Py, T, p, a);
+        } else {
+          if (e.orbit != M_MK)    q = thick_ext<NT, 2>(e, X, Px, Y, Py, T, p, a);
+          else if (e.q.k1 >= 0.0) q = thick_ext<NT, 1>(e, X, Px, Y, Py, T, p, a);
+          else                    q = thick_ext<NT, 3>(e, X, Px, Y, Py, T, p, a);
         }
       } else switch (e.kind) {
         case K_SBEND:
@@ -398,21 +508,25 @@ __global__ void __launch_bounds__(256) reduce_polarization_kernel(const double* 
 
 int track_block_size() { return kBlock; }
 
-template <bool MIXED, bool SURR>
+template <bool MIXED, bool SURR, bool EXT>
 hipError_t launch_nt(const TrackArgs& a, int nt, hipStream_t stream) {
   const dim3 grid((unsigned)a.n_blocks), block(kBlock);
   switch (nt) {
-    case 6:  hipLaunchKernelGGL((track_kernel<6, MIXED, SURR>), grid, block, 0, stream, a); break;
-    case 8:  hipLaunchKernelGGL((track_kernel<8, MIXED, SURR>), grid, block, 0, stream, a); break;
-    case 12: hipLaunchKernelGGL((track_kernel<12, MIXED, SURR>), grid, block, 0, stream, a); break;
-    default: hipLaunchKernelGGL((track_kernel<16, MIXED, SURR>), grid, block, 0, stream, a); break;
+    case 6:  hipLaunchKernelGGL((track_kernel<6, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;
+    case 8:  hipLaunchKernelGGL((track_kernel<8, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;
+    case 12: hipLaunchKernelGGL((track_kernel<12, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;
+    default: hipLaunchKernelGGL((track_kernel<16, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, hipStream_t stream) {
-  if (a.fallback) return launch_nt<false, true>(a, nt, stream);
-  return mixed ? launch_nt<true, false>(a, nt, stream) : launch_nt<false, false>(a, nt, stream);
+hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, bool ext, hipStream_t stream) {
+  // the extended methods run in double precision only
+  if (ext) return a.fallback ? launch_nt<false, true, true>(a, nt, stream)
+                             : launch_nt<false, false, true>(a, nt, stream);
+  if (a.fallback) return launch_nt<false, true, false>(a, nt, stream);
+  return mixed ? launch_nt<true, false, false>(a, nt, stream)
+               : launch_nt<false, false, false>(a, nt, stream);
 }
 
 namespace {

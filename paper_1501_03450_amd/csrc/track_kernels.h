@@ -12,7 +12,9 @@ int track_block_size();
 // nt: number of series terms of the double-precision quaternion half-angle
 // series (6, 8, 12, 16); mixed: the kernel with single-precision spin
 // arithmetic in the elements flagged for it.
-hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, hipStream_t stream);
+// ext: the lattice uses drift-kick (TEAPOT) bends or piece-wise constant
+// spin placements (run in double precision).
+hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, bool ext, hipStream_t stream);
 
 // a.fallback non-null selects the surrogate-tracking kernel.
 

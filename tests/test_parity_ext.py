@@ -1,0 +1,88 @@
+"""Parity of the drift-kick (TEAPOT) sector bend and of the piece-wise
+constant spin placements (kick, midpoint) with the CPU oracle, through the C
+ABI.  Same tolerances as the Romberg path: orbit |Δz_i| <= 1e-12 ·
+max(|z_i|, σ_i), spin components |ΔS_c| <= 1e-10."""
+
+import math
+
+import numpy as np
+import pytest
+
+from test_parity_fp64 import BEAM, ORBIT_TOL, SPIN_TOL, assert_multiturn_parity, assert_parity, both
+from workloads import Beam, gaussian_bunch, rhic_like_ring
+from workloads.lattice import drift, quad, sbend, snake
+
+pytestmark = pytest.mark.gpu
+
+TH = 2 * math.pi / 32
+ELEMENTS = {
+    "teapot_edges_R1": [sbend(10.0, TH, 8, 1, method="teapot")],
+    "teapot_edges_R3": [sbend(10.0, TH, 8, 3, method="teapot")],
+    "teapot_kick": [sbend(10.0, TH, 8, 1, method="teapot", spin="kick")],
+    "teapot_midpoint": [sbend(10.0, TH, 5, 1, method="teapot", spin="midpoint")],
+    "teapot_mispowered": [sbend(10.0, TH, 4, 1, eta=0.97, method="teapot", spin="kick")],
+    "curved_drift": [sbend(2.0, 0.02, 3, 1, eta=0.0, method="teapot", spin="midpoint")],
+    "exact_midpoint": [sbend(9.45, 2 * math.pi / 264, 8, 1, spin="midpoint")],
+    "dkd_kick": [quad(1.0, 0.05, "dkd", 8, 1, spin="kick")],
+    "dkd_kick_d": [quad(1.0, -0.05, "dkd", 3, 1, spin="kick")],
+    "dkd_midpoint": [quad(1.0, 0.05, "dkd", 4, 1, spin="midpoint")],
+    "mk_midpoint": [quad(1.1, 0.08, "mk", 4, 1, spin="midpoint")],
+    "mk_midpoint_d": [quad(1.1, -0.08, "mk", 6, 1, spin="midpoint")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(ELEMENTS))
+def test_single_element_parity(name):
+    z, s, a = gaussian_bunch(777, 1501034511, BEAM)
+    g, o = both(ELEMENTS[name], BEAM, z, s, a, want_q=True)
+    assert_parity(g, o, name)
+    assert np.abs(g["q"] - o["q"]).max() <= SPIN_TOL
+
+
+def dk_ring(N=8):
+    qf = quad(1.0, 0.05, "dkd", N, 1, "QF", spin="kick")
+    qd = quad(1.0, -0.05, "dkd", N, 1, "QD", spin="kick")
+    sb = sbend(10.0, TH, N, 1, method="teapot", spin="kick")
+    cell = [qf, drift(2.0), sb, drift(2.0), qd, drift(2.0), sb, drift(2.0)]
+    return cell * 16 + [snake(math.pi, 0.0)]
+
+
+def pwc_ring(N=4):
+    qf = quad(1.0, 0.05, "mk", N, 1, "QF", spin="midpoint")
+    qd = quad(1.0, -0.05, "mk", N, 1, "QD", spin="midpoint")
+    sb = sbend(10.0, TH, N, 1, spin="midpoint")
+    cell = [qf, drift(2.0), sb, drift(2.0), qd, drift(2.0), sb, drift(2.0)]
+    return cell * 16 + [snake(math.pi, 0.0)]
+
+
+@pytest.mark.parametrize("ring", ["dk", "pwc"])
+def test_small_ring_variants_over_several_turns(ring):
+    elems = dk_ring() if ring == "dk" else pwc_ring()
+    z, s, a = gaussian_bunch(1000, 1501034512, BEAM)
+    g, o = both(elems, BEAM, z, s, a, turns=1, report_every=1)
+    assert_parity(g, o, f"{ring} 1 turn")
+    np.testing.assert_allclose(g["pol"], o["pol"], rtol=0, atol=SPIN_TOL)
+    g, o = both(elems, BEAM, z, s, a, turns=16)
+    assert_multiturn_parity(g, o, elems, BEAM, z, s, a, 16, f"{ring} 16 turns")
+
+
+def test_rhic_ring_with_drift_kick_bends_one_turn():
+    elems = [sbend(e.L, e.angle, e.n_slices, 1, e.eta, method="teapot", spin="kick")
+             if e.kind == "sbend" else e for e in rhic_like_ring()]
+    z, s, a = gaussian_bunch(515, 1501034513, BEAM)
+    g, o = both(elems, BEAM, z, s, a, want_q=True)
+    assert_parity(g, o, "rhic dk")
+
+
+def test_invalid_placements_are_rejected_before_device_work():
+    from paper_1501_03450_amd import SpinTracker
+    from paper_1501_03450_amd.binding import SpinTrackError
+    bad = [
+        [sbend(10.0, TH, 4, 1, spin="kick")],                      # kick needs drift-kick slices
+        [quad(1.0, 0.05, "mk", 4, 2, spin="midpoint")],            # rows must be 1
+        [sbend(10.0, TH, 4, 1, method="dkd")],                     # bends: exact or teapot
+        [quad(1.0, 0.05, "teapot", 4, 1)],                         # teapot only for bends
+    ]
+    for elems in bad:
+        with pytest.raises(SpinTrackError):
+            SpinTracker(elems, BEAM)
