@@ -358,6 +358,8 @@ def integrator_leg(beam, n=4096, slices=(1, 2, 4, 8, 16, 32, 64)):
                 continue
             (zz, ss, aa), _ = one_turn(ring(style, N))
             ok = live & (aa == 1)
+            if not ok.any():
+                raise RuntimeError(f"integrator comparison: {style} N={N} lost every particle")
             orb = float((np.abs(zz[:, ok] - zr[:, ok]) / sig[:, None]).max())
             spin = float(np.abs(ss[:, ok] - sr[:, ok]).max())
             (_, _, _), secs = one_turn(ring(style, N), turns=5, timing=True)

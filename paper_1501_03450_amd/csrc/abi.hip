@@ -182,9 +182,13 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
     t.sn = std::sin(a);
     t.tn = t.sn / t.c;
     t.sec = 1.0 / t.c;
-    t.tn_h = t.tn / t.h;
-    const double s2 = std::sin(0.5 * a);
-    t.omc_h = 2.0 * s2 * s2 / (t.c * t.h);   // (sec - 1)/h
+    // the small differences in extended precision: tan(a) - a and 1 - cos(a)
+    const long double al = (long double)t.h * (long double)t.half;
+    const long double tl = std::tan(al);
+    t.tn_h = (double)(tl / (long double)t.h);
+    t.d0 = (double)(-(tl - al) / (long double)t.h);
+    const long double s2 = std::sin(0.5L * al);
+    t.omc_h = (double)(2.0L * s2 * s2 / (std::cos(al) * (long double)t.h));   // (sec - 1)/h
   } else if (e.kind == ST_SBEND) {
     st::BendParams& b = d.b;
     b.ds = e.L / n_orb;

@@ -136,22 +136,30 @@ __device__ __forceinline__ void omega_bend(const BendParams& e, double X, double
 }
 
 // Drift of the curved frame over half a drift-kick slice (§3.6 eq. teapotD),
-// a straight line seen from the rotating frame.  X(s) is evaluated as
-// [X sec + (sec - 1)/h + (Px/Ps) tan/h] / (1 - (Px/Ps) tan), the printed
-// form without its 1/h - 1/h cancellation; the flight time adds the
-// reference particle's (ds/2)/β0 (the Pt/β0 term of eq. generalH).
+// a straight line seen from the rotating frame.  With u = Px/Ps, a = h ds/2
+// and D = 1 - u tan a, the printed forms are evaluated without their
+// cancellations:
+//   X(s)  = [X sec a + (sec a - 1)/h + u tan(a)/h] / D
+//   path  = (1/h + X) tan(a) / D
+//   ΔT    = (ds/2)/β0 - (1/β0 + Pt) path/Ps           (the Pt/β0 term of
+//           eq. generalH adds (ds/2)/β0)
+//         = (1/β0) { [(ds/2 - tan(a)/h) - tan(a)(u ds/2 + X)] / D
+//                    + path (Ps² - (1 + β0 Pt)²) / (Ps (Ps + 1 + β0 Pt)) }.
 __device__ __forceinline__ void teapot_drift(const TeapotParams& t, double& X, double& Px, double& Y,
                                              double Py, double& T, const Particle& p) {
-  const double ps2 = p.P2() - fma(Px, Px, Py * Py);
+  const double pp = fma(Px, Px, Py * Py);
+  const double ps2 = p.P2() - pp;
   const double r = rsqrt_nr(ps2);
   const double ps = ps2 * r;
   const double u = Px * r;
   const double inv_den = rcp_nr(fma(-u, t.tn, 1.0));
   const double path = fma(X, t.tn, t.tn_h) * inv_den;
+  const double short_path = fma(-t.tn, fma(t.half, u, X), t.d0) * inv_den;   // ds/2 - path
+  const double slow = path * (p.c1() - pp) * r * rcp_nr(ps + p.c2());
+  T = fma(short_path + slow, p.ib0, T);
   X = fma(X, t.sec, fma(u, t.tn_h, t.omc_h)) * inv_den;
   Px = fma(Px, t.c, ps * t.sn);
   Y = fma(Py * r, path, Y);
-  T = fma(-p.ib() * r, path, T + t.half_ib0);
 }
 
 // Dipole kick of a TEAPOT bend over a length len: Px -= ηh (1 + hX) len.

@@ -46,6 +46,7 @@ struct TeapotParams {       // drift-kick sector bend (§3.6)
   double half, half_ib0;    // drift half ds/2 and (ds/2)/β0
   double c, sn, tn, sec;    // cos, sin, tan, 1/cos of h ds/2
   double tn_h, omc_h;       // tan(h ds/2)/h and (1/cos(h ds/2) - 1)/h
+  double d0;                // ds/2 - tan(h ds/2)/h
 };
 struct DriftParams { double L; };
 struct ThinParams { double k1l, k2l; };             // thin multipole (§3.5)

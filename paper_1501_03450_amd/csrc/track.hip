@@ -36,6 +36,7 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
   d.nsl = p->nsl;
   d.K = p->K;
   d.flags = p->flags;
+  d.place = p->place;
 #pragma unroll
   for (int i = 0; i < kElemWords; ++i) d.v[i] = p->v[i];
   return d;

@@ -8,7 +8,9 @@ import math
 import numpy as np
 import pytest
 
-from test_parity_fp64 import BEAM, ORBIT_TOL, SPIN_TOL, assert_multiturn_parity, assert_parity, both
+import oracle
+from test_parity_fp64 import (BEAM, SPIN_TOL, assert_multiturn_parity, assert_parity, both,
+                              orbit_rel_err)
 from workloads import Beam, gaussian_bunch, rhic_like_ring
 from workloads.lattice import drift, quad, sbend, snake
 
@@ -67,11 +69,21 @@ def test_small_ring_variants_over_several_turns(ring):
 
 
 def test_rhic_ring_with_drift_kick_bends_one_turn():
+    # In a drift-kick bend slice each half drift turns Px by about h ds/2
+    # (1.2e-2 here) and the kick takes it back: 6336 such O(1e-2) updates a
+    # turn leave ~1e-16 of double rounding in Px, 1e-12 of its RMS (1e-4),
+    # in any double-precision evaluation.  The bound for this lattice is
+    # therefore 2e-12, and the GPU must stay far below the divergence of a
+    # plain double evaluation of the printed maps.
     elems = [sbend(e.L, e.angle, e.n_slices, 1, e.eta, method="teapot", spin="kick")
              if e.kind == "sbend" else e for e in rhic_like_ring()]
     z, s, a = gaussian_bunch(515, 1501034513, BEAM)
     g, o = both(elems, BEAM, z, s, a, want_q=True)
-    assert_parity(g, o, "rhic dk")
+    assert_parity(g, o, "rhic dk", orbit_tol=2e-12)
+    plain, _ = orbit_rel_err(oracle.track(elems, BEAM, z, s, a, turns=1, extended=False), o)
+    err, _ = orbit_rel_err(g, o)
+    print(f"rhic dk: GPU orbit rel err {err:.3e}, plain FP64 {plain:.3e}")
+    assert err <= 0.01 * plain
 
 
 def test_invalid_placements_are_rejected_before_device_work():
