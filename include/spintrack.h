@@ -254,7 +254,9 @@ st_status st_mlp_targets(st_mlp* m, const double* d_q, int64_t n, const double* 
  * start on the network).  Polarization is recorded as in st_track; the
  * beam's report_every must then be a multiple of audit_every, so that every
  * report follows an audit.  Requires a lattice, particles and a network
- * created on the same device.  Library scratch: 112 bytes per particle. */
+ * created on the same device.  At most 2^31-1 particles; library scratch:
+ * about 170 bytes per particle.  Within a turn the particles on the network
+ * and those on the fallback path are processed in separate waves. */
 st_status st_track_surrogate(st_ctx* ctx, st_mlp* m, int64_t turns, int32_t audit_every,
                              double threshold, const double* center, const double* inv_scale,
                              double extra, int32_t* d_fallback, void* stream);

@@ -50,6 +50,10 @@ struct st_ctx {
   double* d_ck = nullptr;      // checkpoint of the last audit: z (6 × n) then spin (3 × n)
   int32_t* d_ck_alive = nullptr;
   int32_t* d_ralive = nullptr; // live set of a replay
+  int32_t* d_perm = nullptr;   // lane order of the surrogate turns
+  int32_t* d_rperm = nullptr;  // lane order of a replay
+  int32_t* d_pcount = nullptr; // partition counts and offsets, 3 per 256 particles
+  int32_t* d_poff = nullptr;
   int64_t surr_cap = 0;
 };
 
@@ -317,7 +321,8 @@ st_status st_destroy(st_ctx* c) {
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_pol) (void)hipFree(c->d_pol);
     for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
-                    (void*)c->d_ck_alive, (void*)c->d_ralive})
+                    (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_perm, (void*)c->d_rperm,
+                    (void*)c->d_pcount, (void*)c->d_poff})
       if (p) (void)hipFree(p);
   }
   delete c;
@@ -497,6 +502,8 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   if (turns < 0 || turns > std::numeric_limits<int32_t>::max())
     return fail(c, ST_EINVAL, "turns must be in 0..2^31-1");
   if (audit_every < 1) return fail(c, ST_EINVAL, "audit_every must be >= 1");
+  if (c->n > std::numeric_limits<int32_t>::max())
+    return fail(c, ST_EINVAL, "surrogate tracking takes at most 2^31-1 particles");
   if (!(threshold >= 0.0) || !std::isfinite(threshold)) return fail(c, ST_EINVAL, "bad threshold");
   if (!center || !inv_scale) return fail(c, ST_EINVAL, "feature scaling is NULL");
   if (c->n > 0 && !d_fallback) return fail(c, ST_EINVAL, "fallback array is NULL");
@@ -511,16 +518,23 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   const int64_t n = c->n;
   if (n > c->surr_cap) {
     for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
-                    (void*)c->d_ck_alive, (void*)c->d_ralive})
+                    (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_perm, (void*)c->d_rperm,
+                    (void*)c->d_pcount, (void*)c->d_poff})
       if (p) (void)hipFree(p);
     c->d_feat = nullptr; c->d_qnn = nullptr; c->d_q64 = nullptr; c->d_ck = nullptr;
-    c->d_ck_alive = nullptr; c->d_ralive = nullptr; c->surr_cap = 0;
+    c->d_ck_alive = nullptr; c->d_ralive = nullptr; c->d_perm = nullptr; c->d_rperm = nullptr;
+    c->d_pcount = nullptr; c->d_poff = nullptr; c->surr_cap = 0;
+    const size_t nparts = (size_t)((n + 255) / 256) * 3;
     if ((e = hipMalloc(&c->d_feat, (size_t)n * 8 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&c->d_qnn, (size_t)n * 4 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&c->d_q64, (size_t)n * 4 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->d_ck, (size_t)n * 9 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->d_ck_alive, (size_t)n * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&c->d_ralive, (size_t)n * sizeof(int32_t))) != hipSuccess)
+        (e = hipMalloc(&c->d_ralive, (size_t)n * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_perm, (size_t)n * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_rperm, (size_t)n * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_pcount, nparts * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_poff, nparts * sizeof(int32_t))) != hipSuccess)
       return fail(c, ST_ENOMEM, std::string("surrogate scratch: ") + hipGetErrorString(e));
     c->surr_cap = n;
   }
@@ -544,6 +558,12 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
     return r;
   };
   if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");
+  // lane order: particles on the network first, then the fallback ones, so
+  // that waves take one path or the other
+  auto order = [&]() -> hipError_t {
+    return st::launch_partition(0, 0, c->alive, d_fallback, n, c->d_pcount, c->d_poff, c->d_perm, s);
+  };
+  if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");
   int64_t last_audit = 0;
   for (int64_t t = 1; t <= turns; ++t) {
     st_status ms = st_mlp_features(m, c->z, n, center, inv_scale, extra, c->d_feat, stream);
@@ -565,8 +585,12 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
                                          c->d_ck + 6 * n, c->d_ck_alive, c->d_ralive, n, s)) !=
           hipSuccess)
         return hip_fail(c, e, "rollback");
+      if ((e = st::launch_partition(1, (int32_t)t, c->alive, d_fallback, n, c->d_pcount, c->d_poff,
+                                    c->d_rperm, s)) != hipSuccess)
+        return hip_fail(c, e, "replay order");
       st::TrackArgs r = track_args(c);
       r.alive = c->d_ralive;
+      r.perm = c->d_rperm;
       r.turns = (int)(t - last_audit);
       r.report_every = 0;
       r.partials = nullptr;
@@ -575,9 +599,11 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
           hipSuccess)
         return hip_fail(c, e, "replay status");
       if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");
+      if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");
       last_audit = t;
     } else {
       a.fallback = d_fallback;
+      a.perm = c->d_perm;
       if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "surrogate turn");
       if ((e = st::launch_surrogate_spin(c->spin, c->alive, d_fallback, c->d_qnn, n, s)) != hipSuccess)
         return hip_fail(c, e, "surrogate spin");

@@ -89,6 +89,9 @@ struct TrackArgs {
   double ymax;        // largest (θ/2)² the quaternion polynomial covers
   // surrogate tracking: lanes with fallback[j] == 0 skip the spin arithmetic
   const int32_t* fallback;
+  // optional lane order: lane g works on particle perm[g] (a permutation of
+  // 0..n-1), so that particles taking the same path share waves
+  const int32_t* perm;
 };
 
 }  // namespace st

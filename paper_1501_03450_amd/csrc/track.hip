@@ -347,8 +347,9 @@ track_kernel(const TrackArgs a) {
   // orbit at the current element's entrance (read back only on a loss).
   __shared__ double cold[8][kBlock];
   const int tid = threadIdx.x;
-  const int64_t j = (int64_t)blockIdx.x * kBlock + tid;
-  const bool valid = j < a.n;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + tid;
+  const bool valid = g < a.n;
+  const int64_t j = (valid && a.perm) ? (int64_t)a.perm[g] : g;
   int32_t status = valid ? a.alive[j] : 0;
   bool live = status == 1;
   const int64_t n = a.n;
@@ -592,6 +593,85 @@ __global__ void __launch_bounds__(256) replay_finish_kernel(const int32_t* fallb
   if (j < n && fallback[j] == turn) alive[j] = ralive[j];
 }
 
+// Stable three-way partition of the particle indices into a lane order.
+// key 0 first, then 1, then 2; within a key the original order is kept.
+// mode 0 (surrogate turns): 0 = alive on the network, 1 = alive on the
+// fallback path, 2 = lost.  mode 1 (replay after the audit of `turn`):
+// 0 = failed this audit, 1 = every other particle.
+__device__ __forceinline__ int partition_key(int mode, int32_t turn, const int32_t* alive,
+                                             const int32_t* fallback, int64_t j) {
+  if (mode == 1) return fallback[j] == turn ? 0 : 1;
+  if (alive[j] != 1) return 2;
+  return fallback[j] == 0 ? 0 : 1;
+}
+
+__global__ void __launch_bounds__(256) partition_count_kernel(int mode, int32_t turn,
+                                                              const int32_t* alive,
+                                                              const int32_t* fallback, int64_t n,
+                                                              int32_t* counts) {
+  __shared__ int32_t c[3];
+  if (threadIdx.x < 3) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < n) atomicAdd(&c[partition_key(mode, turn, alive, fallback, j)], 1);
+  __syncthreads();
+  if (threadIdx.x < 3) counts[(int64_t)blockIdx.x * 3 + threadIdx.x] = c[threadIdx.x];
+}
+
+// Exclusive offsets of every (block, key): key-major over the whole array.
+__global__ void __launch_bounds__(256) partition_scan_kernel(const int32_t* counts, int64_t nb,
+                                                             int32_t* offsets) {
+  __shared__ int64_t part[256][3];
+  // each thread sums a contiguous range of blocks, then a fixed-order scan
+  const int64_t per = (nb + 255) / 256;
+  const int64_t b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+  int64_t s[3] = {0, 0, 0};
+  for (int64_t b = b0; b < b1; ++b)
+    for (int k = 0; k < 3; ++k) s[k] += counts[b * 3 + k];
+  for (int k = 0; k < 3; ++k) part[threadIdx.x][k] = s[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t base = 0;
+    for (int k = 0; k < 3; ++k)
+      for (int t = 0; t < 256; ++t) {
+        const int64_t v = part[t][k];
+        part[t][k] = base;
+        base += v;
+      }
+  }
+  __syncthreads();
+  int64_t o[3] = {part[threadIdx.x][0], part[threadIdx.x][1], part[threadIdx.x][2]};
+  for (int64_t b = b0; b < b1; ++b)
+    for (int k = 0; k < 3; ++k) {
+      offsets[b * 3 + k] = (int32_t)o[k];
+      o[k] += counts[b * 3 + k];
+    }
+}
+
+__global__ void __launch_bounds__(256) partition_scatter_kernel(int mode, int32_t turn,
+                                                                const int32_t* alive,
+                                                                const int32_t* fallback,
+                                                                int64_t n, const int32_t* offsets,
+                                                                int32_t* perm) {
+  __shared__ int32_t wave_count[4][3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int key = j < n ? partition_key(mode, turn, alive, fallback, j) : 3;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int rank = 0;
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t m = __ballot(key == k);
+    if (key == k) rank = __popcll(m & below);
+    if (lane == 0) wave_count[wv][k] = __popcll(m);
+  }
+  __syncthreads();
+  if (key < 3) {
+    int before = 0;
+    for (int w = 0; w < wv; ++w) before += wave_count[w][key];
+    perm[offsets[(int64_t)blockIdx.x * 3 + key] + before + rank] = (int32_t)j;
+  }
+}
+
 // Per-block sums (Sx, Sy, Sz, N) over alive particles for one report.
 __global__ void __launch_bounds__(256) polarization_partials_kernel(const double* spin,
                                                                     const int32_t* alive, int64_t n,
@@ -643,6 +723,22 @@ hipError_t launch_replay_finish(const int32_t* fallback, int32_t turn, const int
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(replay_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      fallback, turn, ralive, alive, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_partition(int mode, int32_t turn, const int32_t* alive, const int32_t* fallback,
+                            int64_t n, int32_t* counts, int32_t* offsets, int32_t* perm,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL(partition_count_kernel, dim3((unsigned)nb), dim3(256), 0, s, mode, turn, alive,
+                     fallback, n, counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(partition_scan_kernel, dim3(1), dim3(256), 0, s, counts, nb, offsets);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(partition_scatter_kernel, dim3((unsigned)nb), dim3(256), 0, s, mode, turn,
+                     alive, fallback, n, offsets, perm);
   return hipGetLastError();
 }
 

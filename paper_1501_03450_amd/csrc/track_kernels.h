@@ -27,6 +27,11 @@ hipError_t launch_replay_prepare(const int32_t* fallback, int32_t turn, double* 
                                  int32_t* ralive, int64_t n, hipStream_t s);
 hipError_t launch_replay_finish(const int32_t* fallback, int32_t turn, const int32_t* ralive,
                                 int32_t* alive, int64_t n, hipStream_t s);
+// Lane order for surrogate tracking: a stable partition of 0..n-1 (see
+// partition_key); counts and offsets hold 3 ints per 256 particles.
+hipError_t launch_partition(int mode, int32_t turn, const int32_t* alive, const int32_t* fallback,
+                            int64_t n, int32_t* counts, int32_t* offsets, int32_t* perm,
+                            hipStream_t s);
 hipError_t launch_polarization_partials(const double* spin, const int32_t* alive, int64_t n,
                                         double* partials, hipStream_t s);
 

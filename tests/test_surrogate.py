@@ -244,6 +244,39 @@ def _surrogate_run(ring, z, s, a, turns, audit_every, threshold, seed=7):
     return out, fb.cpu().numpy()
 
 
+def test_particles_that_start_on_the_fallback_path_are_tracked_in_double_precision():
+    # every third particle starts on the fallback path (d_fallback != 0) and no
+    # audit flags the others: the lanes are reordered so that the two groups
+    # share no wave, and every particle must still get its own state back
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from paper_1501_03450_amd import binding as B
+    ring = rhic_like_ring()
+    z, s, a = gaussian_bunch(1000, 206, BEAM)
+    turns = 3
+    m = B.st_mlp_create(0, 6, 256, seed=3)
+    tr = SpinTracker(ring, BEAM)
+    tr.set_particles(z, s, a)
+    fb0 = np.zeros(1000, dtype=np.int32)
+    fb0[::3] = -1
+    fb = torch.as_tensor(fb0).cuda()
+    B.st_track_surrogate(tr.ctx, m, turns, 1000, 1e9, np.zeros(6), 1.0 / SIG, 0.0, fb.data_ptr(),
+                         torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    zs, ss, as_ = tr.read()
+    tr.close()
+    B.st_mlp_destroy(m)
+    z64, s64, a64 = _fp64_run(ring, z, s, a, turns)
+    np.testing.assert_array_equal(fb.cpu().numpy(), fb0)
+    np.testing.assert_array_equal(as_, a64)
+    sig = z64.std(axis=1)
+    rel = np.abs(zs - z64) / np.maximum(np.abs(z64), sig[:, None])
+    assert rel.max() < 1e-12 * turns * 10
+    assert np.abs(ss[:, ::3] - s64[:, ::3]).max() <= 1e-12
+    # the others carry the untrained network's rotations
+    assert np.abs(ss[:, 1::3] - s64[:, 1::3]).max() > 1e-3
+
+
 def _fp64_run(ring, z, s, a, turns):
     import torch
     from paper_1501_03450_amd import SpinTracker
