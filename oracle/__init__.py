@@ -30,7 +30,8 @@ _LIB = os.path.join(_BUILD, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-KIND_CODES = {"marker": 0, "drift": 1, "sbend": 2, "quad": 3, "thin": 4, "snake": 5}
+KIND_CODES = {"marker": 0, "drift": 1, "sbend": 2, "quad": 3, "thin": 4, "snake": 5,
+              "solenoid": 6}
 METHOD_CODES = {"exact": 0, "dkd": 1, "mk": 2, "teapot": 3}
 SPIN_CODES = {"edges": 0, "kick": 1, "midpoint": 2}
 
@@ -41,7 +42,7 @@ class _Elem(ctypes.Structure):
                 ("spin", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("L", ctypes.c_double), ("angle", ctypes.c_double), ("eta", ctypes.c_double),
                 ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
-                ("phi", ctypes.c_double), ("mu", ctypes.c_double)]
+                ("phi", ctypes.c_double), ("mu", ctypes.c_double), ("ks", ctypes.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -90,10 +91,18 @@ def _elems(elements):
         a.L, a.angle, a.eta = e.L, e.angle, e.eta
         a.k1, a.k1l, a.k2l = e.k1, e.k1l, e.k2l
         a.phi, a.mu = e.snake_phi, e.snake_mu
+        a.ks = getattr(e, "ks", 0.0)
         if e.kind == "sbend" and e.method not in ("exact", "teapot"):
             raise ValueError("sector bends use the exact map or teapot drift-kick slices")
         if e.kind == "quad" and e.method not in ("dkd", "mk"):
             raise ValueError("quadrupoles use dkd or mk slices")
+        if e.kind == "solenoid":
+            if e.method != "exact" or e.n_slices < 1 or e.rows < 1 or e.L <= 0 or e.ks == 0:
+                raise ValueError("solenoids: exact body, L > 0, ks != 0, n_slices, rows >= 1")
+            if a.spin == SPIN_CODES["kick"]:
+                raise ValueError("the kick spin placement needs drift-kick slices")
+            if a.spin != SPIN_CODES["edges"] and e.rows != 1:
+                raise ValueError("piece-wise constant spin placements take rows = 1")
         if e.kind in ("sbend", "quad"):
             if a.spin == SPIN_CODES["kick"] and e.method not in ("dkd", "teapot"):
                 raise ValueError("the kick spin placement needs drift-kick slices")

@@ -115,7 +115,7 @@ inline long double value_(long double a) { return a; }
 // Lattice and beam
 // ---------------------------------------------------------------------------
 
-enum Kind : int32_t { MARKER = 0, DRIFT = 1, SBEND = 2, QUAD = 3, THIN = 4, SNAKE = 5 };
+enum Kind : int32_t { MARKER = 0, DRIFT = 1, SBEND = 2, QUAD = 3, THIN = 4, SNAKE = 5, SOLENOID = 6 };
 enum Method : int32_t { EXACT = 0, DKD = 1, MK = 2, TEAPOT = 3 };
 // Where the spin is integrated inside a thick element:
 //   EDGES     Ω at the N + 1 slice edges, trapezoid products and Romberg (§4.3)
@@ -128,6 +128,7 @@ enum SpinPlace : int32_t { EDGES = 0, KICK = 1, MIDPOINT = 2 };
 struct Elem {             // the oracle's own element record
   int32_t kind, method, nsl, rows, spin, pad;
   double L, angle, eta, k1, k1l, k2l, phi, mu;
+  double ks;              // solenoid field b0/(Bρ)0 [1/m]
 };
 
 enum { X = 0, PX = 1, Y = 2, PY = 3, TT = 4, PT = 5 };
@@ -258,6 +259,67 @@ template <class T> void teapot_drift(T z[6], T s, T h, const Ref<T>& r) {
 // H_K = η h (X + h X²/2), so Px -= η h (1 + hX) s.
 template <class T> void bend_kick(T z[6], T s, T h, T eta) {
   z[PX] = z[PX] - eta * h * (T(1) + h * z[X]) * s;
+}
+
+// Solenoid body over a length s (§3.7 eq. solenoid): with η = b0/(2 (Bρ)0),
+// Ps from eq. Hsolenoid (kinetic transverse momenta Px + ηY, Py - ηX) and
+// κ = η/Ps, the commuting rotations R1 (eq. rotPS) and R2 (eq. rotXY) act on
+// (X, Px, Y, Py) and T moves by eq. solT.
+template <class T> T sol_ps(const T z[6], T eta, const Ref<T>& r) {
+  using std::sqrt;
+  T Pt = z[PT];
+  T kx = z[PX] + eta * z[Y], ky = z[PY] - eta * z[X];
+  return sqrt(T(1) + T(2) / r.beta0 * Pt + Pt * Pt - kx * kx - ky * ky);
+}
+
+template <class T> void solenoid_body(T z[6], T s, T eta, const Ref<T>& r) {
+  using std::cos; using std::sin;
+  T ps = sol_ps(z, eta, r);
+  T kap = eta / ps;
+  T c = cos(kap * s), sn = sin(kap * s);
+  // R2: rotation of (X, Y) and of (Px, Py) by the angle κs
+  T X2 = c * z[X] + sn * z[Y], Y2 = -sn * z[X] + c * z[Y];
+  T Px2 = c * z[PX] + sn * z[PY], Py2 = -sn * z[PX] + c * z[PY];
+  // R1: the focusing rotations in (X, Px) and (Y, Py)
+  z[X] = c * X2 + sn / eta * Px2;
+  z[PX] = -eta * sn * X2 + c * Px2;
+  z[Y] = c * Y2 + sn / eta * Py2;
+  z[PY] = -eta * sn * Y2 + c * Py2;
+  z[TT] = z[TT] - (T(1) / r.beta0 + z[PT]) * s / ps + s / r.beta0;
+}
+
+// Precession vector in the solenoid body (eq. t-bmt.so with b = (0, 0, ks)
+// and û from the kinetic momentum of eq. mgVSol).
+template <class T> void omega_solenoid(const T z[6], T ks, const Ref<T>& r, T out[3]) {
+  using std::sqrt;
+  T eta = ks / T(2);
+  T Pt = z[PT];
+  T P = sqrt(T(1) + T(2) / r.beta0 * Pt + Pt * Pt);
+  T ps = sol_ps(z, eta, r);
+  T u[3] = {(z[PX] + eta * z[Y]) / P, (z[PY] - eta * z[X]) / P, ps / P};
+  T gamma = r.gamma0 * (T(1) + r.beta0 * Pt);
+  T a1 = T(1) + r.G * gamma, a2 = r.G * (gamma - T(1));
+  T b[3] = {T(0), T(0), ks};
+  T ub = u[2] * ks;
+  for (int i = 0; i < 3; ++i) out[i] = -(T(1) / ps) * (a1 * b[i] - a2 * ub * u[i]);
+}
+
+// Thin-pancake fringe of a solenoid (§4.4 eq. solFringe): the orbit is
+// unchanged; the spin turns by ω = ±(b0/2)/((Bρ)0 Ps) [(1 + Gγ)(X, Y, 0)
+// - G(γ - 1)(X Px + Y Py)/P² mγV], with mγV and Ps taken at half the vector
+// potential; + at the entrance, - at the exit.
+template <class T> Quat<T> solenoid_fringe(const T z[6], T ks, T sign, const Ref<T>& r) {
+  using std::sqrt;
+  T eta_h = ks / T(4);                       // half of b0/(2 (Bρ)0)
+  T Pt = z[PT];
+  T P2 = T(1) + T(2) / r.beta0 * Pt + Pt * Pt;
+  T kx = z[PX] + eta_h * z[Y], ky = z[PY] - eta_h * z[X];
+  T ps = sqrt(P2 - kx * kx - ky * ky);
+  T gamma = r.gamma0 * (T(1) + r.beta0 * Pt);
+  T a1 = T(1) + r.G * gamma, a2 = r.G * (gamma - T(1));
+  T f = sign * (ks / T(2)) / ps;
+  T d = (z[X] * z[PX] + z[Y] * z[PY]) / P2;
+  return qrot(f * (a1 * z[X] - a2 * d * kx), f * (a1 * z[Y] - a2 * d * ky), f * (-a2 * d * ps));
 }
 
 // Matrix-kick quadrupole, linear part over a length s (§3.3 eq. quadL).  The
@@ -393,7 +455,9 @@ void dk_kick(const Elem& e, T z[6], T s) {
 
 template <class T>
 void slice(const Elem& e, T z[6], T ds, const Ref<T>& r) {
-  if (e.kind == SBEND && e.method == TEAPOT) {   // drift-kick-drift (§3.6)
+  if (e.kind == SOLENOID) {
+    solenoid_body(z, ds, T(e.ks) / T(2), r);
+  } else if (e.kind == SBEND && e.method == TEAPOT) {   // drift-kick-drift (§3.6)
     dk_drift(e, z, ds / T(2), r);
     dk_kick(e, z, ds);
     dk_drift(e, z, ds / T(2), r);
@@ -416,6 +480,34 @@ Quat<T> element(const Elem& e, T z[6], const Ref<T>& r) {
     case DRIFT:
       drift(z, T(e.L), r);
       return qident<T>();
+    case SOLENOID: {
+      // entrance fringe, body (edge Ω with Romberg, or midpoint PWC), exit fringe
+      Quat<T> qin = solenoid_fringe(z, T(e.ks), T(1), r);
+      int N = e.nsl;
+      T ds = T(e.L) / T(N);
+      Quat<T> Qb;
+      if (e.spin == MIDPOINT) {
+        Qb = qident<T>();
+        for (int j = 0; j < N; ++j) {
+          slice(e, z, ds / T(2), r);
+          T w[3];
+          omega_solenoid(z, T(e.ks), r, w);
+          Qb = qmul(qrot(ds * w[0], ds * w[1], ds * w[2]), Qb);
+          slice(e, z, ds / T(2), r);
+        }
+        Qb = qnormalise(Qb);
+      } else {
+        std::vector<T> om(3 * (N + 1));
+        omega_solenoid(z, T(e.ks), r, &om[0]);
+        for (int j = 1; j <= N; ++j) {
+          slice(e, z, ds, r);
+          omega_solenoid(z, T(e.ks), r, &om[3 * j]);
+        }
+        Qb = romberg_spin(om, N, ds, e.rows);
+      }
+      Quat<T> qout = solenoid_fringe(z, T(e.ks), T(-1), r);
+      return qmul(qout, qmul(Qb, qin));
+    }
     case SBEND:
     case QUAD: {
       int N = e.nsl;

@@ -88,6 +88,50 @@ def _rhs_thin(k1l, k2l, X, Y, beam):
     return f
 
 
+def _rhs_solenoid(ks, profile, beam):
+    """Hamilton's equations of eq. Hsolenoid with the vector potential of
+    eq. Asol scaled by a longitudinal profile S(s), and the spin in the field
+    b = (-X/2 ks S', -Y/2 ks S', ks S) (div b = 0), û from the kinetic
+    momentum (eq. mgVSol)."""
+    b0 = beam.beta0
+
+    def f(s, y):
+        X, Px, Y, Py, T, Pt, Sx, Sy, Sz = y
+        S, dS = profile(s)
+        eta = 0.5 * ks * S
+        kx, ky = Px + eta * Y, Py - eta * X
+        P2 = 1.0 + 2.0 * Pt / b0 + Pt * Pt
+        Ps = math.sqrt(P2 - kx * kx - ky * ky)
+        P = math.sqrt(P2)
+        b = np.array([-0.5 * X * ks * dS, -0.5 * Y * ks * dS, ks * S])
+        u = np.array([kx, ky, Ps]) / P
+        gamma = beam.gamma0 * (1.0 + b0 * Pt)
+        a1, a2 = 1.0 + beam.G * gamma, beam.G * (gamma - 1.0)
+        om = -(1.0 / Ps) * (a1 * b - a2 * float(u @ b) * u)
+        dSv = np.cross(om, np.array([Sx, Sy, Sz]))
+        return [kx / Ps, eta * ky / Ps, ky / Ps, -eta * kx / Ps,
+                -(1.0 / b0 + Pt) / Ps + 1.0 / b0, 0.0, dSv[0], dSv[1], dSv[2]]
+    return f
+
+
+def track_solenoid(L, ks, eps, beam, z, s, rtol=1e-13, atol=1e-16):
+    """A solenoid whose field rises linearly over [0, eps], stays at ks up to
+    L and falls linearly over [L, L + eps] (field integral ks L); eps = 0
+    integrates the body alone."""
+    y = np.concatenate([np.asarray(z, float), np.asarray(s, float)])
+    if eps == 0.0:
+        pieces = [(0.0, L, lambda t: (1.0, 0.0))]
+    else:
+        pieces = [(0.0, eps, lambda t: (t / eps, 1.0 / eps)),
+                  (eps, L, lambda t: (1.0, 0.0)),
+                  (L, L + eps, lambda t: ((L + eps - t) / eps, -1.0 / eps))]
+    for a, b, prof in pieces:
+        sol = solve_ivp(_rhs_solenoid(ks, prof, beam), (a, b), y, method="DOP853",
+                        rtol=rtol, atol=atol)
+        y = sol.y[:, -1]
+    return y[:6].copy(), y[6:].copy()
+
+
 def track_element(e, beam, z, s, rtol=1e-13, atol=1e-16):
     """Brute-force map of one element (workloads.Element) on one particle."""
     y0 = np.concatenate([np.asarray(z, float), np.asarray(s, float)])

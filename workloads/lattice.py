@@ -13,12 +13,19 @@ Element kinds
   thin    thin normal multipole: integrated quadrupole k1l and sextupole k2l
   snake   thin spin rotator: rotation angle snake_phi about the horizontal
           axis (sin mu, 0, cos mu) in (x, y, s); transparent to the orbit
+  solenoid  longitudinal field ks = b0/(Bρ)0 over L with thin-pancake fringes
   marker  does nothing
 
 Orbit integration methods
-  exact   exact flow (drift, sector bend)
+  exact   exact flow (drift, sector bend, solenoid)
   dkd     drift-kick-drift slices (quadrupoles)
   mk      matrix-kick-matrix slices (quadrupoles)
+  teapot  drift-kick-drift slices of a sector bend in its curved frame
+
+Spin placement in thick elements (`spin`)
+  edges     Ω at the slice edges, Romberg tableau over R rows (default)
+  kick      drift-kick slices: one rotation per slice between its half kicks
+  midpoint  one rotation per slice with Ω at the slice's middle
 
 `n_slices` is the number of orbit slices N; `rows` is the number R of
 Romberg tableau rows requested for the element's spin (R = 1 means the plain
@@ -33,7 +40,7 @@ from typing import List, Sequence
 
 import numpy as np
 
-KINDS = ("marker", "drift", "sbend", "quad", "thin", "snake")
+KINDS = ("marker", "drift", "sbend", "quad", "thin", "snake", "solenoid")
 METHODS = ("exact", "dkd", "mk", "teapot")
 SPIN_PLACES = ("edges", "kick", "midpoint")
 
@@ -54,6 +61,7 @@ class Element:
     rows: int = 1
     name: str = ""
     spin: str = "edges"
+    ks: float = 0.0
 
     def __post_init__(self):
         if self.kind not in KINDS:
@@ -77,6 +85,13 @@ def sbend(L: float, angle: float, n: int, rows: int, eta: float = 1.0, name: str
 def quad(L: float, k1: float, method: str, n: int, rows: int, name: str = "Q",
          spin: str = "edges") -> Element:
     return Element("quad", L=L, k1=k1, method=method, n_slices=n, rows=rows, name=name, spin=spin)
+
+
+def solenoid(L: float, ks: float, n: int, rows: int, name: str = "SOL",
+             spin: str = "edges") -> Element:
+    """Solenoid of length L and longitudinal field ks = b0/(Bρ)0 [1/m], with
+    thin-pancake fringes; n body slices and R Romberg rows for the spin."""
+    return Element("solenoid", L=L, ks=ks, n_slices=n, rows=rows, name=name, spin=spin)
 
 
 def thin(k1l: float = 0.0, k2l: float = 0.0, name: str = "M") -> Element:
