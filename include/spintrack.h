@@ -56,7 +56,10 @@ typedef enum {
   ST_SBEND = 2,     /* sector bend: L, angle, eta (§3.1 eq. sbend)             */
   ST_QUAD = 3,      /* normal quadrupole: L, k1 (§3.3 / §3.4)                  */
   ST_THIN = 4,      /* thin normal multipole: k1l, k2l (§3.5)                  */
-  ST_SNAKE = 5      /* thin spin rotator: snake_phi about (sin mu, 0, cos mu)  */
+  ST_SNAKE = 5,     /* thin spin rotator: snake_phi about (sin mu, 0, cos mu)  */
+  ST_SOLENOID = 6   /* solenoid: L, ks = b0/(Bρ)0, exact body map (§3.7 eq.
+                       solenoid) between thin-pancake fringes whose spin kicks
+                       follow §4.4 eq. solFringe; spin_place EDGES or MIDPOINT */
 } st_kind;
 
 typedef enum {
@@ -104,10 +107,11 @@ typedef enum {
  *                (st_spin_place); ST_SPIN_KICK needs DKD quadrupole or
  *                TEAPOT bend slices
  *   reserved     must be 0
+ *   ks           solenoid longitudinal field b0/(Bρ)0 [m^-1] (0 otherwise)
  */
 typedef struct {
   int32_t kind, orbit, n_slices, romberg_rows, spin_place, reserved;
-  double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu;
+  double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks;
 } st_element;
 
 /* Beam and run parameters.

@@ -81,7 +81,7 @@ st_status hip_fail(st_ctx* c, hipError_t e, const char* what) {
 }
 
 bool finite_all(const st_element& e) {
-  const double v[] = {e.L, e.angle, e.eta, e.k1, e.k1l, e.k2l, e.snake_phi, e.snake_mu};
+  const double v[] = {e.L, e.angle, e.eta, e.k1, e.k1l, e.k2l, e.snake_phi, e.snake_mu, e.ks};
   for (double x : v)
     if (!std::isfinite(x)) return false;
   return true;
@@ -101,7 +101,7 @@ double series_ymax(int nt) {
 std::string validate(const st_element& e, int64_t i) {
   const std::string at = "element " + std::to_string(i) + ": ";
   if (!finite_all(e)) return at + "non-finite parameter";
-  if (e.kind < ST_MARKER || e.kind > ST_SNAKE) return at + "unknown kind " + std::to_string(e.kind);
+  if (e.kind < ST_MARKER || e.kind > ST_SOLENOID) return at + "unknown kind " + std::to_string(e.kind);
   if (e.orbit < ST_ORB_EXACT || e.orbit > ST_ORB_TEAPOT) return at + "unknown orbit method";
   if (e.spin_place < ST_SPIN_EDGES || e.spin_place > ST_SPIN_MIDPOINT)
     return at + "unknown spin placement";
@@ -124,10 +124,17 @@ std::string validate(const st_element& e, int64_t i) {
       if (e.orbit != ST_ORB_DKD && e.orbit != ST_ORB_MK) return at + "quadrupoles use DKD or MK";
       if (!(e.L > 0.0)) return at + "quadrupole needs L > 0";
       break;
+    case ST_SOLENOID:
+      if (e.orbit != ST_ORB_EXACT) return at + "solenoids use the exact body map";
+      if (!(e.L > 0.0)) return at + "solenoid needs L > 0";
+      if (e.ks == 0.0) return at + "solenoid needs ks != 0";
+      if (e.spin_place == ST_SPIN_KICK) return at + "the kick spin placement needs drift-kick slices";
+      break;
     default:
       break;
   }
-  if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
+  if (e.kind != ST_SOLENOID && e.ks != 0.0) return at + "ks applies to solenoids only";
+  if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID) {
     if (e.n_slices < 1) return at + "n_slices must be >= 1";
     if (e.romberg_rows < 1 || e.romberg_rows > st::kMaxRows)
       return at + "romberg_rows must be in 1.." + std::to_string(st::kMaxRows);
@@ -163,13 +170,13 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
   d.K = 0;
   // Only the sliced elements: a thin element costs one rotation, and its
   // quaternion would need a double-precision renormalisation anyway.
-  const bool thick = e.kind == ST_SBEND || e.kind == ST_QUAD;
+  const bool thick = e.kind == ST_SBEND || e.kind == ST_QUAD;   // (solenoids: double only)
   if (thick && (beam.precision == ST_MIXED_ALL ||
                 (beam.precision == ST_MIXED && design_angle(e, beam, 0.005) <= kSpin32MaxAngle)))
     d.flags |= st::F_SPIN32;
   // orbit slices: the midpoint placement runs 2N half slices
   const int n_orb = e.spin_place == ST_SPIN_MIDPOINT ? 2 * e.n_slices : e.n_slices;
-  if (e.kind == ST_SBEND || e.kind == ST_QUAD) {
+  if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID) {
     d.nsl = n_orb;
     const int re = std::min(e.romberg_rows, 1 + v2(e.n_slices));
     d.K = re - 1;
@@ -220,6 +227,13 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
     q.k1 = e.k1;
     q.k1ds = e.k1 * q.ds;
     q.kabs_hds2 = std::fabs(e.k1) * q.hds * q.hds;
+  } else if (e.kind == ST_SOLENOID) {
+    st::SolenoidParams& sp = d.sol;
+    sp.ds = e.L / n_orb;
+    sp.ks = e.ks;
+    sp.eta = 0.5 * e.ks;
+    sp.inv_eta = 2.0 / e.ks;
+    sp.eta_q = 0.25 * e.ks;
   } else if (e.kind == ST_DRIFT) {
     d.d.L = e.L;
   } else if (e.kind == ST_THIN) {
@@ -253,6 +267,11 @@ double design_angle(const st_element& e, const st_beam& b, double r_ref) {
     return f * om;
   }
   if (e.kind == ST_THIN) return a1 * (std::fabs(e.k1l) * r_ref + 0.5 * std::fabs(e.k2l) * r_ref * r_ref);
+  if (e.kind == ST_SOLENOID) {
+    const double ds = e.L / e.n_slices;
+    const double f = (e.n_slices > 1 || e.spin_place != ST_SPIN_EDGES) ? ds : 0.5 * ds;
+    return a1 * std::fabs(e.ks) * f;
+  }
   return 0.0;
 }
 
@@ -357,7 +376,8 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   double theta = 0.0;
   bool ext = false;
   for (int64_t i = 0; i < n; ++i) {
-    ext = ext || els[i].orbit == ST_ORB_TEAPOT || els[i].spin_place != ST_SPIN_EDGES;
+    ext = ext || els[i].orbit == ST_ORB_TEAPOT || els[i].spin_place != ST_SPIN_EDGES ||
+          els[i].kind == ST_SOLENOID;
     int k = -1;
     for (size_t u = 0; u < uniq.size(); ++u)
       if (std::memcmp(&uniq[u], &els[i], sizeof(st_element)) == 0) { k = (int)u; break; }

@@ -167,6 +167,78 @@ __device__ __forceinline__ void teapot_kick(const TeapotParams& t, double len, d
   Px = fma(-t.eta_h * len, fma(t.h, X, 1.0), Px);
 }
 
+// Solenoid body (§3.7 eq. solenoid).  The kinetic transverse momentum
+// k = (Px + ηY, Py - ηX) keeps its length along the exact flow, so Ps,
+// κ = η/Ps, cos(κ ds), sin(κ ds) and the flight-time step are constants of
+// the particle in the element.
+struct SolState {
+  double ps, r;     // Ps and 1/Ps (eq. Hsolenoid)
+  double c, sn;     // cos and sin of κ ds
+  double dT;        // T step per slice: ds/β0 - (1/β0 + Pt) ds/Ps, cancellation-free
+};
+
+template <int NT>
+__device__ __forceinline__ SolState sol_state(const SolenoidParams& sp, double X, double Px,
+                                              double Y, double Py, const Particle& p, double ymax,
+                                              double inv_beta0) {
+  SolState st;
+  const double kx = fma(sp.eta, Y, Px), ky = fma(-sp.eta, X, Py);
+  const double kk = fma(kx, kx, ky * ky);
+  const double ps2 = p.P2() - kk;
+  st.r = rsqrt_nr(ps2);
+  st.ps = ps2 * st.r;
+  const double phi = sp.eta * st.r * sp.ds;
+  double sfac;
+  rot_half_angle<NT>(phi * phi, ymax, st.c, sfac);   // cos φ and sin(φ)/(2φ)
+  st.sn = 2.0 * phi * sfac;
+  st.dT = sp.ds * (p.c1() - kk) * st.r * inv_beta0 * rcp_nr(st.ps + p.c2());
+  return st;
+}
+
+__device__ __forceinline__ void solenoid_slice(const SolenoidParams& sp, const SolState& st,
+                                               double& X, double& Px, double& Y, double& Py,
+                                               double& T) {
+  // R2: rotation of (X, Y) and (Px, Py) by κ ds; R1: focusing rotations
+  const double X2 = fma(st.c, X, st.sn * Y), Y2 = fma(-st.sn, X, st.c * Y);
+  const double Px2 = fma(st.c, Px, st.sn * Py), Py2 = fma(-st.sn, Px, st.c * Py);
+  const double sie = st.sn * sp.inv_eta, es = sp.eta * st.sn;
+  X = fma(st.c, X2, sie * Px2);
+  Px = fma(-es, X2, st.c * Px2);
+  Y = fma(st.c, Y2, sie * Py2);
+  Py = fma(-es, Y2, st.c * Py2);
+  T += st.dT;
+}
+
+// Precession vector in the solenoid body: b = (0, 0, ks), û from the kinetic
+// momentum (eq. mgVSol).
+__device__ __forceinline__ void omega_solenoid(const SolenoidParams& sp, const SolState& st,
+                                               double X, double Px, double Y, double Py,
+                                               const Particle& p, double& ox, double& oy,
+                                               double& oz) {
+  const double kx = fma(sp.eta, Y, Px), ky = fma(-sp.eta, X, Py);
+  const double g = p.a2() * p.invP2();
+  ox = g * sp.ks * kx;
+  oy = g * sp.ks * ky;
+  oz = -sp.ks * st.r * fma(-g * st.ps, st.ps, p.a1());   // -(ks/Ps)(a1 - a2 Ps²/P²)
+}
+
+// Thin-pancake fringe spin kick (§4.4 eq. solFringe), sign +1 at the
+// entrance and -1 at the exit, with the kinetic momentum at half the vector
+// potential.  Returns ω.
+__device__ __forceinline__ void solenoid_fringe(const SolenoidParams& sp, double sign, double X,
+                                                double Px, double Y, double Py, const Particle& p,
+                                                double& wx, double& wy, double& wz) {
+  const double kx = fma(sp.eta_q, Y, Px), ky = fma(-sp.eta_q, X, Py);
+  const double ps2 = p.P2() - fma(kx, kx, ky * ky);
+  const double r = rsqrt_nr(ps2);
+  const double ps = ps2 * r;
+  const double f = sign * sp.eta * r;
+  const double d = p.a2() * fma(X, Px, Y * Py) * p.invP2();
+  wx = f * fma(p.a1(), X, -d * kx);
+  wy = f * fma(p.a1(), Y, -d * ky);
+  wz = -f * d * ps;
+}
+
 __device__ __forceinline__ void teapot_slice(const TeapotParams& t, double& X, double& Px, double& Y,
                                              double Py, double& T, const Particle& p) {
   teapot_drift(t, X, Px, Y, Py, T, p);

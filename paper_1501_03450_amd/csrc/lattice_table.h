@@ -13,7 +13,8 @@
 
 namespace st {
 
-enum : int32_t { K_MARKER = 0, K_DRIFT = 1, K_SBEND = 2, K_QUAD = 3, K_THIN = 4, K_SNAKE = 5 };
+enum : int32_t { K_MARKER = 0, K_DRIFT = 1, K_SBEND = 2, K_QUAD = 3, K_THIN = 4, K_SNAKE = 5,
+                 K_SOLENOID = 6 };
 enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2, M_TEAPOT = 3 };
 // spin placement in thick elements: Romberg over the slice edges, or one
 // piece-wise constant rotation per slice between the half kicks or at the
@@ -48,12 +49,19 @@ struct TeapotParams {       // drift-kick sector bend (§3.6)
   double tn_h, omc_h;       // tan(h ds/2)/h and (1/cos(h ds/2) - 1)/h
   double d0;                // ds/2 - tan(h ds/2)/h
 };
+struct SolenoidParams {     // solenoid (§3.7, §4.4)
+  double ds;                // orbit slice length
+  double ks;                // b0/(Bρ)0
+  double eta, inv_eta;      // ks/2 and its inverse
+  double eta_q;             // ks/4: half the vector potential at a fringe
+};
 struct DriftParams { double L; };
 struct ThinParams { double k1l, k2l; };             // thin multipole (§3.5)
 struct SnakeParams { double qw, qx, qy, qz; };      // fixed rotation quaternion
 
 constexpr int kElemWords = sizeof(BendParams) / sizeof(double);   // largest member
 static_assert(sizeof(TeapotParams) <= sizeof(BendParams), "element union size");
+static_assert(sizeof(SolenoidParams) <= sizeof(BendParams), "element union size");
 
 enum : int32_t { F_SPIN32 = 1 };   // element flag: single-precision spin arithmetic
 
@@ -64,6 +72,7 @@ struct DevElem {
   union {
     BendParams b;
     TeapotParams tp;
+    SolenoidParams sol;
     QuadParams q;
     DriftParams d;
     ThinParams t;

@@ -293,6 +293,80 @@ __device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double
   return {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
 }
 
+// Solenoid (§3.7, §4.4): entrance fringe kick, body slices with the spin at
+// the slice edges (Romberg) or at the slice middles (PLACE == P_MIDPOINT: 2N
+// orbit half slices), exit fringe kick; later rotations on the left.
+template <int NT, int PLACE>
+__device__ __forceinline__ Quat solenoid_element(const DevElem& el, double& X, double& Px,
+                                                 double& Y, double& Py, double& T,
+                                                 const Particle& p, const TrackArgs& a) {
+  const SolenoidParams& sp = el.sol;
+  auto rot = [&](double wx, double wy, double wz) {
+    double c, sfac;
+    rot_half_angle<NT>(0.25 * fma(wx, wx, fma(wy, wy, wz * wz)), a.ymax, c, sfac);
+    return Quat{c, sfac * wx, sfac * wy, sfac * wz};
+  };
+  double wx, wy, wz;
+  solenoid_fringe(sp, 1.0, X, Px, Y, Py, p, wx, wy, wz);
+  const Quat qin = rot(wx, wy, wz);
+  const SolState st = sol_state<NT>(sp, X, Px, Y, Py, p, a.ymax, a.inv_beta0);
+  Quat Q;
+  if (PLACE == P_MIDPOINT) {
+    Q = qident();
+    const double w = 2.0 * sp.ds;
+    for (int j = 1; j <= el.nsl; ++j) {
+      solenoid_slice(sp, st, X, Px, Y, Py, T);
+      if (j & 1) {
+        double ox, oy, oz;
+        omega_solenoid(sp, st, X, Px, Y, Py, p, ox, oy, oz);
+        Q = qmul(rot(w * ox, w * oy, w * oz), Q);
+      }
+    }
+  } else {
+    // Romberg levels over the slice edges, as for the other thick elements
+    const int N = el.nsl, K = el.K;
+    const double ds = sp.ds;
+    Quat Q0 = qident(), Q1 = qident(), Q2 = qident(), Q3 = qident();
+    for (int j = 0; j <= N; ++j) {
+      if (j > 0) solenoid_slice(sp, st, X, Px, Y, Py, T);
+      double ox, oy, oz;
+      omega_solenoid(sp, st, X, Px, Y, Py, p, ox, oy, oz);
+      const double f = ((j == 0 || j == N) ? 0.5 : 1.0) * ds;
+      Quat qb = rot(f * ox, f * oy, f * oz);
+      Q0 = qmul(qb, Q0);
+      if (K >= 1 && (j & 1) == 0) {
+        qb = qsquare(qb);
+        Q1 = qmul(qb, Q1);
+        if (K >= 2 && (j & 3) == 0) {
+          qb = qsquare(qb);
+          Q2 = qmul(qb, Q2);
+          if (K >= 3 && (j & 7) == 0) {
+            qb = qsquare(qb);
+            Q3 = qmul(qb, Q3);
+          }
+        }
+      }
+    }
+    if (K >= 1) {
+      Q0 = qextrapolate(Q0, Q1, 4.0);
+      if (K >= 2) {
+        Q1 = qextrapolate(Q1, Q2, 4.0);
+        if (K >= 3) Q2 = qextrapolate(Q2, Q3, 4.0);
+        Q0 = qextrapolate(Q0, Q1, 16.0);
+        if (K >= 3) {
+          Q1 = qextrapolate(Q1, Q2, 16.0);
+          Q0 = qextrapolate(Q0, Q1, 64.0);
+        }
+      }
+    }
+    Q = Q0;
+  }
+  const double inv = rsqrt_nr(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
+  Q = {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
+  solenoid_fringe(sp, -1.0, X, Px, Y, Py, p, wx, wy, wz);
+  return qmul(rot(wx, wy, wz), qmul(Q, qin));
+}
+
 // Spin and orbit of a thick element with the extended methods: TEAPOT bends
 // and the piece-wise constant placements.
 template <int NT, int KIND>
@@ -400,6 +474,9 @@ track_kernel(const TrackArgs a) {
           if (e.orbit != M_MK)    thick_orbit<2>(e, X, Px, Y, Py, T, p, a);
           else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a);
           else                    thick_orbit<3>(e, X, Px, Y, Py, T, p, a);
+        } else if (EXT && e.kind == K_SOLENOID) {
+          const SolState st = sol_state<NT>(e.sol, X, Px, Y, Py, p, a.ymax, a.inv_beta0);
+          for (int jj = 0; jj < e.nsl; ++jj) solenoid_slice(e.sol, st, X, Px, Y, Py, T);
         } else if (e.kind == K_THIN) {
           const double hk1 = 0.5 * e.t.k1l, hk2 = 0.5 * e.t.k2l;
           for (int h = 0; h < 2; ++h) {
@@ -407,6 +484,9 @@ track_kernel(const TrackArgs a) {
             Py += fma(hk1, Y, hk2 * X * Y);
           }
         }
+      } else if (EXT && e.kind == K_SOLENOID) {
+        if (e.place == P_MIDPOINT) q = solenoid_element<NT, P_MIDPOINT>(e, X, Px, Y, Py, T, p, a);
+        else                       q = solenoid_element<NT, P_EDGES>(e, X, Px, Y, Py, T, p, a);
       } else if (EXT && (e.kind == K_SBEND || e.kind == K_QUAD)) {
         if (e.kind == K_SBEND) {
           if (e.orbit == M_TEAPOT) q = thick_ext<NT, 4>(e, X, Px, Y, Py, T, p, a);

@@ -98,3 +98,31 @@ def test_midpoint_body_spin_is_second_order():
     errs = [np.abs(run([solenoid(L, ks, N, 1, spin="midpoint")])[1] - ref).max() for N in (4, 8, 16)]
     ratios = np.array(errs[:-1]) / np.array(errs[1:])
     assert np.all(np.abs(ratios - 4.0) < 0.3), (errs, ratios)
+
+
+def test_paper_solenoid_at_200_GeV_four_slices_and_romberg_reach_round_off():
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_elements.json")))
+    p, sol = g["proton"], g["solenoid"]
+    gamma0 = p["total_energy_GeV"] / p["mass_GeV"]
+    beam = Beam(G=p["G"], gamma0=gamma0)
+    brho = math.sqrt(p["total_energy_GeV"] ** 2 - p["mass_GeV"] ** 2) / 0.299792458
+    ks = sol["field_T"] / brho
+    fp = g["footnote_particle"]
+    b0 = beam.beta0
+    Pt = math.sqrt((1 + fp["delta"]) ** 2 + 1 / (b0 * gamma0) ** 2) - 1 / b0
+    z0 = np.array([fp["X"], fp["Px"], fp["Y"], fp["Py"], fp["T"], Pt])
+    s0 = np.array(fp["spin"]) / np.linalg.norm(fp["spin"])
+
+    def spin(N, R):
+        r = oracle.track([solenoid(sol["L"], ks, N, R)], beam, z0[:, None], s0[:, None])
+        return r["spin"][:, 0]
+    ref = spin(128, 4)
+    # the on-axis rotation (1 + G) ks L is of the printed order (about 10 mrad)
+    rot = (1 + p["G"]) * ks * sol["L"]
+    assert 0.5 * sol["rotation_200GeV_rad_order"] < rot < 2 * sol["rotation_200GeV_rad_order"]
+    # plain trapezoid products at four slices are far from round-off, one or
+    # two Romberg steps reach it
+    assert np.abs(spin(4, 1) - ref).max() > 1e-12
+    assert np.abs(spin(4, 2) - ref).max() < 1e-15
+    assert np.abs(spin(4, 3) - ref).max() < 1e-15

@@ -12,7 +12,7 @@ import oracle
 from test_parity_fp64 import (BEAM, SPIN_TOL, assert_multiturn_parity, assert_parity, both,
                               orbit_rel_err)
 from workloads import Beam, gaussian_bunch, rhic_like_ring
-from workloads.lattice import drift, quad, sbend, snake
+from workloads.lattice import drift, quad, sbend, snake, solenoid
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +30,11 @@ ELEMENTS = {
     "dkd_midpoint": [quad(1.0, 0.05, "dkd", 4, 1, spin="midpoint")],
     "mk_midpoint": [quad(1.1, 0.08, "mk", 4, 1, spin="midpoint")],
     "mk_midpoint_d": [quad(1.1, -0.08, "mk", 6, 1, spin="midpoint")],
+    # 2.1 m at 1.3 T for γ0 = 25 protons (ks = b0/(Bρ)0), and stronger fields
+    "solenoid_R2": [solenoid(2.1, 1.3 / 78.1, 4, 2)],
+    "solenoid_R4_strong": [solenoid(2.1, 0.5, 8, 4)],
+    "solenoid_negative": [solenoid(1.0, -0.3, 6, 2)],
+    "solenoid_midpoint": [solenoid(2.1, 0.5, 8, 1, spin="midpoint")],
 }
 
 
@@ -68,6 +73,29 @@ def test_small_ring_variants_over_several_turns(ring):
     assert_multiturn_parity(g, o, elems, BEAM, z, s, a, 16, f"{ring} 16 turns")
 
 
+def test_small_ring_with_a_solenoid_in_a_straight():
+    ring = []
+    for i, e in enumerate(dk_ring(N=4)[:-1]):
+        ring.append(solenoid(2.0, 0.2, 8, 3) if (i == 1) else e)
+    ring = [quad(1.0, 0.05, "mk", 4, 3) if e.kind == "quad" and e.k1 > 0 else e for e in ring]
+    ring.append(snake(math.pi, 0.0))
+    z, s, a = gaussian_bunch(700, 1501034514, BEAM)
+    g, o = both(ring, BEAM, z, s, a, turns=1, want_q=True)
+    assert_parity(g, o, "small ring + solenoid")
+    g, o = both(ring, BEAM, z, s, a, turns=8)
+    assert_multiturn_parity(g, o, ring, BEAM, z, s, a, 8, "small ring + solenoid, 8 turns")
+
+
+def test_low_energy_solenoid():
+    # 1.2 GeV protons through the 2.1 m, 1.3 T solenoid: a large spin rotation
+    beam = Beam(gamma0=1.2 / 0.938272)
+    brho = beam.beta0 * beam.gamma0 * 0.938272 / 0.299792458
+    elems = [solenoid(2.1, 1.3 / brho, 8, 3)]
+    z, s, a = gaussian_bunch(500, 1501034515, beam)
+    g, o = both(elems, beam, z, s, a, want_q=True)
+    assert_parity(g, o, "low-energy solenoid")
+
+
 def test_rhic_ring_with_drift_kick_bends_one_turn():
     # In a drift-kick bend slice each half drift turns Px by about h ds/2
     # (1.2e-2 here) and the kick takes it back: 6336 such O(1e-2) updates a
@@ -94,6 +122,8 @@ def test_invalid_placements_are_rejected_before_device_work():
         [quad(1.0, 0.05, "mk", 4, 2, spin="midpoint")],            # rows must be 1
         [sbend(10.0, TH, 4, 1, method="dkd")],                     # bends: exact or teapot
         [quad(1.0, 0.05, "teapot", 4, 1)],                         # teapot only for bends
+        [solenoid(2.0, 0.2, 4, 1, spin="kick")],                   # no kick in a solenoid
+        [solenoid(2.0, 0.0, 4, 1)],                                # ks must be non-zero
     ]
     for elems in bad:
         with pytest.raises(SpinTrackError):
