@@ -31,7 +31,7 @@ _lock = threading.Lock()
 _lib = None
 
 KIND_CODES = {"marker": 0, "drift": 1, "sbend": 2, "quad": 3, "thin": 4, "snake": 5,
-              "solenoid": 6}
+              "solenoid": 6, "rbend": 7}
 METHOD_CODES = {"exact": 0, "dkd": 1, "mk": 2, "teapot": 3}
 SPIN_CODES = {"edges": 0, "kick": 1, "midpoint": 2}
 
@@ -75,6 +75,7 @@ def _load():
                                              ctypes.c_double, dp, ctypes.c_int, P(ctypes.c_longlong)]
             lib.oracle_romberg.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, ctypes.c_int]
             lib.oracle_omega.argtypes = [dp, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
+            lib.oracle_rotate.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
             assert lib.oracle_elem_size() == ctypes.sizeof(_Elem)
             _lib = lib
     return _lib
@@ -96,6 +97,13 @@ def _elems(elements):
             raise ValueError("sector bends use the exact map or teapot drift-kick slices")
         if e.kind == "quad" and e.method not in ("dkd", "mk"):
             raise ValueError("quadrupoles use dkd or mk slices")
+        if e.kind == "rbend":
+            if e.method != "exact" or e.n_slices < 1 or e.rows < 1 or e.L <= 0 or e.angle == 0:
+                raise ValueError("rectangular bends: exact body, L > 0, angle != 0, n_slices, rows >= 1")
+            if a.spin == SPIN_CODES["kick"]:
+                raise ValueError("the kick spin placement needs drift-kick slices")
+            if a.spin != SPIN_CODES["edges"] and e.rows != 1:
+                raise ValueError("piece-wise constant spin placements take rows = 1")
         if e.kind == "solenoid":
             if e.method != "exact" or e.n_slices < 1 or e.rows < 1 or e.L <= 0 or e.ks == 0:
                 raise ValueError("solenoids: exact body, L > 0, ks != 0, n_slices, rows >= 1")
@@ -140,6 +148,15 @@ def track(elements, beam, z, spin, alive=None, turns=1, report_every=0, extended
                      int(report_every), _dp(pol), _dp(q) if q is not None else None,
                      int(threads), 1 if extended else 0)
     return {"z": z, "spin": spin, "alive": alive, "pol": pol[:n_rep] if n_rep else None, "q": q}
+
+
+def rotate(z, phi, beam):
+    """The frame rotation of a rectangular-bend face (eq. prot) on one state."""
+    lib = _load()
+    zi = np.ascontiguousarray(z, dtype=np.float64)
+    zo = np.zeros(6)
+    lib.oracle_rotate(_dp(zi), float(phi), beam.G, beam.gamma0, _dp(zo))
+    return zo
 
 
 def jacobian(elements, beam, z0, s0=(0.0, 1.0, 0.0), turns=1):

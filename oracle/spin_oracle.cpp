@@ -115,7 +115,8 @@ inline long double value_(long double a) { return a; }
 // Lattice and beam
 // ---------------------------------------------------------------------------
 
-enum Kind : int32_t { MARKER = 0, DRIFT = 1, SBEND = 2, QUAD = 3, THIN = 4, SNAKE = 5, SOLENOID = 6 };
+enum Kind : int32_t { MARKER = 0, DRIFT = 1, SBEND = 2, QUAD = 3, THIN = 4, SNAKE = 5, SOLENOID = 6,
+                      RBEND = 7 };
 enum Method : int32_t { EXACT = 0, DKD = 1, MK = 2, TEAPOT = 3 };
 // Where the spin is integrated inside a thick element:
 //   EDGES     Ω at the N + 1 slice edges, trapezoid products and Romberg (§4.3)
@@ -322,6 +323,70 @@ template <class T> Quat<T> solenoid_fringe(const T z[6], T ks, T sign, const Ref
   return qrot(f * (a1 * z[X] - a2 * d * kx), f * (a1 * z[Y] - a2 * d * ky), f * (-a2 * d * ps));
 }
 
+// ---- Rectangular bend (§3.2), symmetric: the design orbit enters and leaves
+// at half the bend angle θ to the magnet faces; field b1/(Bρ)0 = 1/ρb =
+// η 2 sin(θ/2)/L in the magnet's Cartesian frame.
+
+// Dynamic rotation of the frame by φ: the flow of eq. Hprot, H = -X Ps,
+// over the angle φ (eq. prot).  T follows that flow, dT/dφ = -X (1/β0 +
+// Pt)/Ps, so a particle outside the reference (X > 0) reaches the rotated
+// face later; the printed T(φ) carries the opposite sign, at odds with the
+// printed Hamiltonian whose X, Px and Y flows it matches.
+template <class T> void prot(T z[6], T phi, const Ref<T>& r) {
+  using std::cos; using std::sin;
+  T ps = ps_of(z, r);
+  T c = cos(phi), sn = sin(phi), tn = sn / c;
+  T Xi = z[X], Pxi = z[PX];
+  T den = T(1) - (Pxi / ps) * tn;
+  z[X] = Xi * (T(1) / c) / den;
+  z[PX] = Pxi * c + ps * sn;
+  z[Y] = z[Y] + (z[PY] / ps) * Xi * tn / den;
+  z[TT] = z[TT] - (T(1) / r.beta0 + z[PT]) / ps * Xi * tn / den;
+}
+
+// Thin dipole fringe without gap correction (eq. dipolefringe); sign +1 at
+// the entrance, -1 at the exit; fb = b1/(Bρ)0.
+template <class T> void dipole_fringe(T z[6], T fb, T sign, const Ref<T>& r) {
+  using std::sqrt;
+  T ps = ps_of(z, r);
+  T xp = z[PX] / ps, yp = z[PY] / ps;
+  T q = T(1) + yp * yp;
+  T sf = sign * fb;
+  T Yf = T(2) * z[Y] / (T(1) + sqrt(T(1) + sf * (xp * yp / q) * T(2) * z[Y]));
+  z[X] = z[X] + sf / (T(2) * ps) * ((T(1) + xp * xp) / q - T(2) * (xp * yp) * (xp * yp) / (q * q)) * Yf * Yf;
+  z[PY] = z[PY] - sf * xp / q * Yf;
+  z[TT] = z[TT] - sf * (T(1) / r.beta0 + z[PT]) * xp / (T(2) * ps * ps) * (T(1) - yp * yp) / (q * q) * Yf * Yf;
+  z[Y] = Yf;
+}
+
+// Body of the rectangular bend over a length s (eq. rbend; Pα of eq.
+// planarP).  The printed T has no reference flight time; the element adds the
+// design arc's L_arc/β0 at its end (eq. Toffset).
+template <class T> void rbend_body(T z[6], T s, T fb, const Ref<T>& r) {
+  using std::asin; using std::sqrt;
+  T Pt = z[PT], Py = z[PY];
+  T Pa = sqrt(T(1) + T(2) / r.beta0 * Pt + Pt * Pt - Py * Py);
+  T rhob = T(1) / fb;
+  T Pxi = z[PX];
+  T Px = Pxi - s * fb;
+  T D = asin(Pxi / Pa) - asin(Px / Pa);
+  z[X] = z[X] + rhob * (sqrt(Pa * Pa - Px * Px) - sqrt(Pa * Pa - Pxi * Pxi));
+  z[PX] = Px;
+  z[Y] = z[Y] + Py * rhob * D;
+  z[TT] = z[TT] - (T(1) / r.beta0 + Pt) * rhob * D;
+}
+
+// Spin kick across a rectangular-bend fringe (§4.5 eq. skfringe with m = 1
+// and eq. skfringeRB).  The longitudinal fringe field integrates to b1 Y;
+// the printed x̂ term lacks that Y (as printed it is not dimensionless), and
+// splitting b1 Y ẑ into parts along and across the velocity (of slope Px)
+// gives ω = ±(b1/(Bρ)0) [-(1 + G) Y ẑ + G(γ - 1) Px Y x̂].
+template <class T> Quat<T> rbend_fringe_spin(const T z[6], T fb, T sign, const Ref<T>& r) {
+  T gamma = r.gamma0 * (T(1) + r.beta0 * z[PT]);
+  T f = sign * fb * z[Y];
+  return qrot(f * r.G * (gamma - T(1)) * z[PX], T(0), -f * (T(1) + r.G));
+}
+
 // Matrix-kick quadrupole, linear part over a length s (§3.3 eq. quadL).  The
 // printed solution is for a focusing gradient; a defocusing one (k1 < 0) is
 // the same map with the roles of (X, Px) and (Y, Py) exchanged.
@@ -453,9 +518,16 @@ void dk_kick(const Elem& e, T z[6], T s) {
   else                 kick(z, T(e.k1) * s, T(0));
 }
 
+template <class T> T rbend_fb(const Elem& e) {
+  using std::sin;
+  return T(e.eta) * T(2) * sin(T(e.angle) / T(2)) / T(e.L);
+}
+
 template <class T>
 void slice(const Elem& e, T z[6], T ds, const Ref<T>& r) {
-  if (e.kind == SOLENOID) {
+  if (e.kind == RBEND) {
+    rbend_body(z, ds, rbend_fb<T>(e), r);
+  } else if (e.kind == SOLENOID) {
     solenoid_body(z, ds, T(e.ks) / T(2), r);
   } else if (e.kind == SBEND && e.method == TEAPOT) {   // drift-kick-drift (§3.6)
     dk_drift(e, z, ds / T(2), r);
@@ -480,6 +552,47 @@ Quat<T> element(const Elem& e, T z[6], const Ref<T>& r) {
     case DRIFT:
       drift(z, T(e.L), r);
       return qident<T>();
+    case RBEND: {
+      // frame rotation into the magnet, fringe, body, fringe, rotation out;
+      // the rotations turn the spin components with the frame about ŷ
+      using std::sin;
+      T half = T(e.angle) / T(2);
+      T fb = rbend_fb<T>(e);
+      Quat<T> qf = qrot(T(0), half, T(0));
+      prot(z, half, r);
+      dipole_fringe(z, fb, T(1), r);
+      Quat<T> qin = rbend_fringe_spin(z, fb, T(1), r);
+      int N = e.nsl;
+      T ds = T(e.L) / T(N);
+      T b[3] = {T(0), fb, T(0)};
+      Quat<T> Qb;
+      if (e.spin == MIDPOINT) {
+        Qb = qident<T>();
+        for (int j = 0; j < N; ++j) {
+          slice(e, z, ds / T(2), r);
+          T w[3];
+          omega(z, T(0), b, r, w);
+          Qb = qmul(qrot(ds * w[0], ds * w[1], ds * w[2]), Qb);
+          slice(e, z, ds / T(2), r);
+        }
+        Qb = qnormalise(Qb);
+      } else {
+        std::vector<T> om(3 * (N + 1));
+        omega(z, T(0), b, r, &om[0]);
+        for (int j = 1; j <= N; ++j) {
+          slice(e, z, ds, r);
+          omega(z, T(0), b, r, &om[3 * j]);
+        }
+        Qb = romberg_spin(om, N, ds, e.rows);
+      }
+      Quat<T> qout = rbend_fringe_spin(z, fb, T(-1), r);
+      dipole_fringe(z, fb, T(-1), r);
+      prot(z, half, r);
+      // T as a deviation from the design particle's flight time over the arc
+      T larc = T(e.angle) * T(e.L) / (T(2) * sin(half));
+      z[TT] = z[TT] + larc / r.beta0;
+      return qmul(qf, qmul(qout, qmul(Qb, qmul(qin, qf))));
+    }
     case SOLENOID: {
       // entrance fringe, body (edge Ω with Romberg, or midpoint PWC), exit fringe
       Quat<T> qin = solenoid_fringe(z, T(e.ks), T(1), r);
@@ -749,6 +862,17 @@ int oracle_omega(const double* z, double h, const double* b, double G, double ga
   for (int i = 0; i < 3; ++i) bb[i] = b[i];
   omega(zz, (long double)h, bb, r, o);
   for (int i = 0; i < 3; ++i) out[i] = (double)o[i];
+  return 0;
+}
+
+// The dynamic rotation of a rectangular-bend face alone (eq. prot), for the
+// pins: z (6) rotated by phi in extended precision.
+int oracle_rotate(const double* z_in, double phi, double G, double gamma0, double* z_out) {
+  Ref<long double> r(G, gamma0);
+  long double z[6];
+  for (int i = 0; i < 6; ++i) z[i] = z_in[i];
+  prot(z, (long double)phi, r);
+  for (int i = 0; i < 6; ++i) z_out[i] = (double)z[i];
   return 0;
 }
 

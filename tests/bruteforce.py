@@ -172,3 +172,68 @@ def track_line(elements, beam, z, s, **kw):
     for e in elements:
         z, s = track_element(e, beam, z, s, **kw)
     return z, s
+
+
+def track_prot(phi, beam, z, rtol=1e-13, atol=1e-16):
+    """Flow of H = -X Ps over the frame angle φ (no spin)."""
+    b0 = beam.beta0
+
+    def f(t, y):
+        X, Px, Y, Py, T, Pt = y
+        Ps = math.sqrt(1.0 + 2.0 * Pt / b0 + Pt * Pt - Px * Px - Py * Py)
+        return [X * Px / Ps, Ps, X * Py / Ps, 0.0, -X * (1.0 / b0 + Pt) / Ps, 0.0]
+    sol = solve_ivp(f, (0.0, phi), np.asarray(z, float), method="DOP853", rtol=rtol, atol=atol)
+    return sol.y[:, -1].copy()
+
+
+def _rhs_rect_dipole(fb, profile, beam):
+    """A dipole field b_y = fb f(z) in a Cartesian frame, with the lowest-order
+    fringe vector potential of eq. vecArb: a_z = -fb f X, a_x = -fb f' Y²/2,
+    so b = (0, fb f, fb f' Y); spin with û from the kinetic momentum."""
+    b0 = beam.beta0
+
+    def f(s, y):
+        X, Px, Y, Py, T, Pt, Sx, Sy, Sz = y
+        F, dF = profile(s)
+        ax = -fb * dF * Y * Y / 2.0
+        kx = Px - ax
+        P2 = 1.0 + 2.0 * Pt / b0 + Pt * Pt
+        Ps = math.sqrt(P2 - kx * kx - Py * Py)
+        b = np.array([0.0, fb * F, fb * dF * Y])
+        u = np.array([kx, Py, Ps]) / math.sqrt(P2)
+        gamma = beam.gamma0 * (1.0 + b0 * Pt)
+        a1, a2 = 1.0 + beam.G * gamma, beam.G * (gamma - 1.0)
+        om = -(1.0 / Ps) * (a1 * b - a2 * float(u @ b) * u)
+        dS = np.cross(om, np.array([Sx, Sy, Sz]))
+        return [kx / Ps, -fb * F, Py / Ps, -kx * fb * dF * Y / Ps,
+                -(1.0 / b0 + Pt) / Ps + 1.0 / b0, 0.0, dS[0], dS[1], dS[2]]
+    return f
+
+
+def track_rbend(L, angle, eta, eps, beam, z, s, rtol=1e-13, atol=1e-16):
+    """Symmetric rectangular bend: frame rotation by angle/2, a dipole field
+    rising linearly over [0, eps], flat to L, falling over [L, L + eps], frame
+    rotation by angle/2; spin components turned with each frame rotation; T
+    referred to the design arc."""
+    fb = eta * 2.0 * math.sin(angle / 2) / L
+    half = angle / 2
+    zz = track_prot(half, beam, z, rtol, atol)
+    S = np.asarray(s, float)
+
+    def roty(S, a):          # active rotation about ŷ by a
+        c, sn = math.cos(a), math.sin(a)
+        return np.array([c * S[0] + sn * S[2], S[1], -sn * S[0] + c * S[2]])
+    S = roty(S, half)
+    y = np.concatenate([zz, S])
+    pieces = [(0.0, eps, lambda t: (t / eps, 1.0 / eps)),
+              (eps, L, lambda t: (1.0, 0.0)),
+              (L, L + eps, lambda t: ((L + eps - t) / eps, -1.0 / eps))]
+    for a, b, prof in pieces:
+        sol = solve_ivp(_rhs_rect_dipole(fb, prof, beam), (a, b), y, method="DOP853",
+                        rtol=rtol, atol=atol)
+        y = sol.y[:, -1]
+    zz = track_prot(half, beam, y[:6], rtol, atol)
+    S = roty(y[6:], half)
+    larc = angle * L / (2 * math.sin(half))
+    zz[4] += (larc - (L + eps)) / beam.beta0
+    return zz, S

@@ -14,6 +14,9 @@ Element kinds
   snake   thin spin rotator: rotation angle snake_phi about the horizontal
           axis (sin mu, 0, cos mu) in (x, y, s); transparent to the orbit
   solenoid  longitudinal field ks = b0/(Bρ)0 over L with thin-pancake fringes
+  rbend   rectangular bend of straight length L bending the design orbit by
+          `angle`, entered and left symmetrically (half the angle at each
+          face); eta is the powering ratio
   marker  does nothing
 
 Orbit integration methods
@@ -40,7 +43,7 @@ from typing import List, Sequence
 
 import numpy as np
 
-KINDS = ("marker", "drift", "sbend", "quad", "thin", "snake", "solenoid")
+KINDS = ("marker", "drift", "sbend", "quad", "thin", "snake", "solenoid", "rbend")
 METHODS = ("exact", "dkd", "mk", "teapot")
 SPIN_PLACES = ("edges", "kick", "midpoint")
 
@@ -92,6 +95,11 @@ def solenoid(L: float, ks: float, n: int, rows: int, name: str = "SOL",
     """Solenoid of length L and longitudinal field ks = b0/(Bρ)0 [1/m], with
     thin-pancake fringes; n body slices and R Romberg rows for the spin."""
     return Element("solenoid", L=L, ks=ks, n_slices=n, rows=rows, name=name, spin=spin)
+
+
+def rbend(L: float, angle: float, n: int, rows: int, eta: float = 1.0, name: str = "RB",
+          spin: str = "edges") -> Element:
+    return Element("rbend", L=L, angle=angle, eta=eta, n_slices=n, rows=rows, name=name, spin=spin)
 
 
 def thin(k1l: float = 0.0, k2l: float = 0.0, name: str = "M") -> Element:
