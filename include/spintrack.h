@@ -57,9 +57,14 @@ typedef enum {
   ST_QUAD = 3,      /* normal quadrupole: L, k1 (§3.3 / §3.4)                  */
   ST_THIN = 4,      /* thin normal multipole: k1l, k2l (§3.5)                  */
   ST_SNAKE = 5,     /* thin spin rotator: snake_phi about (sin mu, 0, cos mu)  */
-  ST_SOLENOID = 6   /* solenoid: L, ks = b0/(Bρ)0, exact body map (§3.7 eq.
+  ST_SOLENOID = 6,  /* solenoid: L, ks = b0/(Bρ)0, exact body map (§3.7 eq.
                        solenoid) between thin-pancake fringes whose spin kicks
                        follow §4.4 eq. solFringe; spin_place EDGES or MIDPOINT */
+  ST_RBEND = 7      /* symmetric rectangular bend: straight length L, design
+                       bend `angle` (half at each face), powering eta != 0;
+                       frame rotations (eq. prot), thin dipole fringes (eq.
+                       dipolefringe), exact body (§3.2 eq. rbend), fringe
+                       spin kicks (§4.5); spin_place EDGES or MIDPOINT        */
 } st_kind;
 
 typedef enum {

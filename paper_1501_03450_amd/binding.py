@@ -18,13 +18,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SPINTRACK_LIB", os.path.join(_HERE, "libspintrack.so"))
 
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDEVICE, ST_ESTATE = 0, -1, -2, -3, -4
-ST_MARKER, ST_DRIFT, ST_SBEND, ST_QUAD, ST_THIN, ST_SNAKE, ST_SOLENOID = range(7)
+ST_MARKER, ST_DRIFT, ST_SBEND, ST_QUAD, ST_THIN, ST_SNAKE, ST_SOLENOID, ST_RBEND = range(8)
 ST_ORB_EXACT, ST_ORB_DKD, ST_ORB_MK, ST_ORB_TEAPOT = range(4)
 ST_SPIN_EDGES, ST_SPIN_KICK, ST_SPIN_MIDPOINT = range(3)
 ST_FP64, ST_MIXED, ST_MIXED_ALL = 0, 1, 2
 
 KIND_CODES = {"marker": ST_MARKER, "drift": ST_DRIFT, "sbend": ST_SBEND, "quad": ST_QUAD,
-              "thin": ST_THIN, "snake": ST_SNAKE, "solenoid": ST_SOLENOID}
+              "thin": ST_THIN, "snake": ST_SNAKE, "solenoid": ST_SOLENOID, "rbend": ST_RBEND}
 ORBIT_CODES = {"exact": ST_ORB_EXACT, "dkd": ST_ORB_DKD, "mk": ST_ORB_MK, "teapot": ST_ORB_TEAPOT}
 SPIN_CODES = {"edges": ST_SPIN_EDGES, "kick": ST_SPIN_KICK, "midpoint": ST_SPIN_MIDPOINT}
 PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED, "mixed_all": ST_MIXED_ALL}

@@ -101,7 +101,7 @@ double series_ymax(int nt) {
 std::string validate(const st_element& e, int64_t i) {
   const std::string at = "element " + std::to_string(i) + ": ";
   if (!finite_all(e)) return at + "non-finite parameter";
-  if (e.kind < ST_MARKER || e.kind > ST_SOLENOID) return at + "unknown kind " + std::to_string(e.kind);
+  if (e.kind < ST_MARKER || e.kind > ST_RBEND) return at + "unknown kind " + std::to_string(e.kind);
   if (e.orbit < ST_ORB_EXACT || e.orbit > ST_ORB_TEAPOT) return at + "unknown orbit method";
   if (e.spin_place < ST_SPIN_EDGES || e.spin_place > ST_SPIN_MIDPOINT)
     return at + "unknown spin placement";
@@ -124,6 +124,13 @@ std::string validate(const st_element& e, int64_t i) {
       if (e.orbit != ST_ORB_DKD && e.orbit != ST_ORB_MK) return at + "quadrupoles use DKD or MK";
       if (!(e.L > 0.0)) return at + "quadrupole needs L > 0";
       break;
+    case ST_RBEND:
+      if (e.orbit != ST_ORB_EXACT) return at + "rectangular bends use the exact body map";
+      if (!(e.L > 0.0)) return at + "rectangular bend needs L > 0";
+      if (e.angle == 0.0 || !(std::fabs(e.angle) < 3.0)) return at + "rectangular bend needs 0 < |angle| < 3";
+      if (e.eta == 0.0) return at + "rectangular bend needs eta != 0";
+      if (e.spin_place == ST_SPIN_KICK) return at + "the kick spin placement needs drift-kick slices";
+      break;
     case ST_SOLENOID:
       if (e.orbit != ST_ORB_EXACT) return at + "solenoids use the exact body map";
       if (!(e.L > 0.0)) return at + "solenoid needs L > 0";
@@ -134,7 +141,7 @@ std::string validate(const st_element& e, int64_t i) {
       break;
   }
   if (e.kind != ST_SOLENOID && e.ks != 0.0) return at + "ks applies to solenoids only";
-  if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID) {
+  if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID || e.kind == ST_RBEND) {
     if (e.n_slices < 1) return at + "n_slices must be >= 1";
     if (e.romberg_rows < 1 || e.romberg_rows > st::kMaxRows)
       return at + "romberg_rows must be in 1.." + std::to_string(st::kMaxRows);
@@ -176,7 +183,7 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
     d.flags |= st::F_SPIN32;
   // orbit slices: the midpoint placement runs 2N half slices
   const int n_orb = e.spin_place == ST_SPIN_MIDPOINT ? 2 * e.n_slices : e.n_slices;
-  if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID) {
+  if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID || e.kind == ST_RBEND) {
     d.nsl = n_orb;
     const int re = std::min(e.romberg_rows, 1 + v2(e.n_slices));
     d.K = re - 1;
@@ -227,6 +234,20 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
     q.k1 = e.k1;
     q.k1ds = e.k1 * q.ds;
     q.kabs_hds2 = std::fabs(e.k1) * q.hds * q.hds;
+  } else if (e.kind == ST_RBEND) {
+    st::RbendParams& rb = d.rb;
+    const double half = 0.5 * e.angle;
+    rb.ds = e.L / n_orb;
+    rb.L = e.L;
+    rb.fb = e.eta * 2.0 * std::sin(half) / e.L;
+    rb.rhob = 1.0 / rb.fb;
+    rb.c = std::cos(half);
+    rb.sn = std::sin(half);
+    rb.tn = rb.sn / rb.c;
+    rb.sec = 1.0 / rb.c;
+    rb.qf_w = std::cos(0.5 * half);
+    rb.qf_y = std::sin(0.5 * half);
+    rb.larc_ib0 = e.angle * e.L / (2.0 * std::sin(half)) / beta0;
   } else if (e.kind == ST_SOLENOID) {
     st::SolenoidParams& sp = d.sol;
     sp.ds = e.L / n_orb;
@@ -267,6 +288,11 @@ double design_angle(const st_element& e, const st_beam& b, double r_ref) {
     return f * om;
   }
   if (e.kind == ST_THIN) return a1 * (std::fabs(e.k1l) * r_ref + 0.5 * std::fabs(e.k2l) * r_ref * r_ref);
+  if (e.kind == ST_RBEND) {
+    const double ds = e.L / e.n_slices;
+    const double f = (e.n_slices > 1 || e.spin_place != ST_SPIN_EDGES) ? ds : 0.5 * ds;
+    return a1 * std::fabs(e.eta * 2.0 * std::sin(0.5 * e.angle) / e.L) * f;
+  }
   if (e.kind == ST_SOLENOID) {
     const double ds = e.L / e.n_slices;
     const double f = (e.n_slices > 1 || e.spin_place != ST_SPIN_EDGES) ? ds : 0.5 * ds;
@@ -377,7 +403,7 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   bool ext = false;
   for (int64_t i = 0; i < n; ++i) {
     ext = ext || els[i].orbit == ST_ORB_TEAPOT || els[i].spin_place != ST_SPIN_EDGES ||
-          els[i].kind == ST_SOLENOID;
+          els[i].kind == ST_SOLENOID || els[i].kind == ST_RBEND;
     int k = -1;
     for (size_t u = 0; u < uniq.size(); ++u)
       if (std::memcmp(&uniq[u], &els[i], sizeof(st_element)) == 0) { k = (int)u; break; }

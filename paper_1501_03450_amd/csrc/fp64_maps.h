@@ -239,6 +239,59 @@ __device__ __forceinline__ void solenoid_fringe(const SolenoidParams& sp, double
   wz = -f * d * ps;
 }
 
+// Rectangular bend (§3.2).  Frame rotation by the face angle (the flow of
+// eq. Hprot; T decreases for X > 0, which reaches the rotated face later).
+__device__ __forceinline__ void rbend_rotate(const RbendParams& rb, double& X, double& Px, double& Y,
+                                             double Py, double& T, const Particle& p) {
+  const double ps2 = p.P2() - fma(Px, Px, Py * Py);
+  const double r = rsqrt_nr(ps2);
+  const double ps = ps2 * r;
+  const double inv_den = rcp_nr(fma(-Px * r, rb.tn, 1.0));
+  const double xt = X * rb.tn * inv_den;
+  Y = fma(Py * r, xt, Y);
+  T = fma(-p.ib() * r, xt, T);
+  X = X * rb.sec * inv_den;
+  Px = fma(Px, rb.c, ps * rb.sn);
+}
+
+// Thin dipole fringe without gap correction (eq. dipolefringe), sign +1 at
+// the entrance and -1 at the exit.
+__device__ __forceinline__ void rbend_fringe(const RbendParams& rb, double sign, double& X,
+                                             double Px, double& Y, double& Py, double& T,
+                                             const Particle& p) {
+  const double ps2 = p.P2() - fma(Px, Px, Py * Py);
+  const double r = rsqrt_nr(ps2);
+  const double xp = Px * r, yp = Py * r;
+  const double iq = rcp_nr(fma(yp, yp, 1.0));
+  const double sf = sign * rb.fb;
+  const double a = sf * xp * yp * iq * 2.0 * Y;
+  const double Yf = 2.0 * Y * rcp_nr(1.0 + sqrt(1.0 + a));
+  const double Yf2 = Yf * Yf;
+  const double xy = xp * yp * iq;
+  X = fma(0.5 * sf * r * (fma(xp, xp, 1.0) * iq - 2.0 * xy * xy), Yf2, X);
+  Py = fma(-sf * xp * iq, Yf, Py);
+  T = fma(-sf * p.ib() * xp * 0.5 * r * r * fma(-yp, yp, 1.0) * iq * iq, Yf2, T);
+  Y = Yf;
+}
+
+// Body over a length s (eq. rbend), Pα² = P² - Py²:  Px(s) = Px - s fb,
+// X += ρb [W(s) - W] = s (Px + Px(s)) / (W + W(s)), and the bending
+// angle D = asin(Px/Pα) - asin(Px(s)/Pα) = asin((Px W(s) - Px(s) W)/Pα²);
+// no reference flight time here (the element adds L_arc/β0).
+__device__ __forceinline__ void rbend_body(const RbendParams& rb, double s, double& X, double& Px,
+                                           double& Y, double Py, double& T, const Particle& p) {
+  const double Pa2 = p.P2() - Py * Py;
+  const double Px1 = fma(-s, rb.fb, Px);
+  const double w02 = fma(-Px, Px, Pa2), w12 = fma(-Px1, Px1, Pa2);
+  const double r0 = rsqrt_nr(w02), r1 = rsqrt_nr(w12);
+  const double W0 = w02 * r0, W1 = w12 * r1;
+  X = fma(s * (Px + Px1), rcp_nr(W0 + W1), X);
+  const double D = asin_small(fma(Px, W1, -Px1 * W0) * rcp_nr(Pa2));
+  Y = fma(Py * rb.rhob, D, Y);
+  T = fma(-p.ib() * rb.rhob, D, T);
+  Px = Px1;
+}
+
 __device__ __forceinline__ void teapot_slice(const TeapotParams& t, double& X, double& Px, double& Y,
                                              double Py, double& T, const Particle& p) {
   teapot_drift(t, X, Px, Y, Py, T, p);

@@ -14,7 +14,7 @@
 namespace st {
 
 enum : int32_t { K_MARKER = 0, K_DRIFT = 1, K_SBEND = 2, K_QUAD = 3, K_THIN = 4, K_SNAKE = 5,
-                 K_SOLENOID = 6 };
+                 K_SOLENOID = 6, K_RBEND = 7 };
 enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2, M_TEAPOT = 3 };
 // spin placement in thick elements: Romberg over the slice edges, or one
 // piece-wise constant rotation per slice between the half kicks or at the
@@ -55,6 +55,14 @@ struct SolenoidParams {     // solenoid (§3.7, §4.4)
   double eta, inv_eta;      // ks/2 and its inverse
   double eta_q;             // ks/4: half the vector potential at a fringe
 };
+struct RbendParams {        // symmetric rectangular bend (§3.2, §4.5)
+  double ds;                // orbit slice length along the magnet
+  double L;                 // straight length (one-step orbit)
+  double fb, rhob;          // b1/(Bρ)0 and its inverse
+  double c, sn, tn, sec;    // of the face angle θ/2
+  double qf_w, qf_y;        // frame rotation of the spin: (cos θ/4, sin θ/4 ŷ)
+  double larc_ib0;          // design arc length / β0
+};
 struct DriftParams { double L; };
 struct ThinParams { double k1l, k2l; };             // thin multipole (§3.5)
 struct SnakeParams { double qw, qx, qy, qz; };      // fixed rotation quaternion
@@ -62,6 +70,7 @@ struct SnakeParams { double qw, qx, qy, qz; };      // fixed rotation quaternion
 constexpr int kElemWords = sizeof(BendParams) / sizeof(double);   // largest member
 static_assert(sizeof(TeapotParams) <= sizeof(BendParams), "element union size");
 static_assert(sizeof(SolenoidParams) <= sizeof(BendParams), "element union size");
+static_assert(sizeof(RbendParams) <= sizeof(BendParams), "element union size");
 
 enum : int32_t { F_SPIN32 = 1 };   // element flag: single-precision spin arithmetic
 
@@ -73,6 +82,7 @@ struct DevElem {
     BendParams b;
     TeapotParams tp;
     SolenoidParams sol;
+    RbendParams rb;
     QuadParams q;
     DriftParams d;
     ThinParams t;

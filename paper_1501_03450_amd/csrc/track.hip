@@ -367,6 +367,91 @@ __device__ __forceinline__ Quat solenoid_element(const DevElem& el, double& X, d
   return qmul(rot(wx, wy, wz), qmul(Q, qin));
 }
 
+// Symmetric rectangular bend (§3.2, §4.5): frame rotation into the magnet
+// (the spin components turn with the frame about ŷ), entrance fringe and its
+// spin kick, body slices with Romberg over the edges or midpoint rotations,
+// exit fringe and kick, frame rotation out; T referred to the design arc.
+template <int NT, int PLACE>
+__device__ __forceinline__ Quat rbend_element(const DevElem& el, double& X, double& Px, double& Y,
+                                              double& Py, double& T, const Particle& p,
+                                              const TrackArgs& a) {
+  const RbendParams& rb = el.rb;
+  auto rot = [&](double wx, double wy, double wz) {
+    double c, sfac;
+    rot_half_angle<NT>(0.25 * fma(wx, wx, fma(wy, wy, wz * wz)), a.ymax, c, sfac);
+    return Quat{c, sfac * wx, sfac * wy, sfac * wz};
+  };
+  // fringe kick ±fb Y [G(γ - 1) Px x̂ - (1 + G) ẑ]
+  auto fringe_spin = [&](double sign) {
+    const double f = sign * rb.fb * Y;
+    return rot(f * p.a2() * Px, 0.0, -f * (1.0 + a.G));
+  };
+  const Quat qf = {rb.qf_w, 0.0, rb.qf_y, 0.0};
+  rbend_rotate(rb, X, Px, Y, Py, T, p);
+  rbend_fringe(rb, 1.0, X, Px, Y, Py, T, p);
+  const Quat qin = fringe_spin(1.0);
+  Quat Q;
+  auto omega_at = [&](double& ox, double& oy, double& oz) {
+    const double r = rsqrt_nr(p.P2() - fma(Px, Px, Py * Py));
+    omega_dipole(0.0, rb.fb, X, Px, Py, r, p, ox, oy, oz);
+  };
+  if (PLACE == P_MIDPOINT) {
+    Q = qident();
+    const double w = 2.0 * rb.ds;
+    for (int j = 1; j <= el.nsl; ++j) {
+      rbend_body(rb, rb.ds, X, Px, Y, Py, T, p);
+      if (j & 1) {
+        double ox, oy, oz;
+        omega_at(ox, oy, oz);
+        Q = qmul(rot(w * ox, w * oy, w * oz), Q);
+      }
+    }
+  } else {
+    const int N = el.nsl, K = el.K;
+    Quat Q0 = qident(), Q1 = qident(), Q2 = qident(), Q3 = qident();
+    for (int j = 0; j <= N; ++j) {
+      if (j > 0) rbend_body(rb, rb.ds, X, Px, Y, Py, T, p);
+      double ox, oy, oz;
+      omega_at(ox, oy, oz);
+      const double f = ((j == 0 || j == N) ? 0.5 : 1.0) * rb.ds;
+      Quat qb = rot(f * ox, f * oy, f * oz);
+      Q0 = qmul(qb, Q0);
+      if (K >= 1 && (j & 1) == 0) {
+        qb = qsquare(qb);
+        Q1 = qmul(qb, Q1);
+        if (K >= 2 && (j & 3) == 0) {
+          qb = qsquare(qb);
+          Q2 = qmul(qb, Q2);
+          if (K >= 3 && (j & 7) == 0) {
+            qb = qsquare(qb);
+            Q3 = qmul(qb, Q3);
+          }
+        }
+      }
+    }
+    if (K >= 1) {
+      Q0 = qextrapolate(Q0, Q1, 4.0);
+      if (K >= 2) {
+        Q1 = qextrapolate(Q1, Q2, 4.0);
+        if (K >= 3) Q2 = qextrapolate(Q2, Q3, 4.0);
+        Q0 = qextrapolate(Q0, Q1, 16.0);
+        if (K >= 3) {
+          Q1 = qextrapolate(Q1, Q2, 16.0);
+          Q0 = qextrapolate(Q0, Q1, 64.0);
+        }
+      }
+    }
+    Q = Q0;
+  }
+  const double inv = rsqrt_nr(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
+  Q = {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
+  const Quat qout = fringe_spin(-1.0);
+  rbend_fringe(rb, -1.0, X, Px, Y, Py, T, p);
+  rbend_rotate(rb, X, Px, Y, Py, T, p);
+  T += rb.larc_ib0;
+  return qmul(qf, qmul(qout, qmul(Q, qmul(qin, qf))));
+}
+
 // Spin and orbit of a thick element with the extended methods: TEAPOT bends
 // and the piece-wise constant placements.
 template <int NT, int KIND>
@@ -474,6 +559,13 @@ track_kernel(const TrackArgs a) {
           if (e.orbit != M_MK)    thick_orbit<2>(e, X, Px, Y, Py, T, p, a);
           else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a);
           else                    thick_orbit<3>(e, X, Px, Y, Py, T, p, a);
+        } else if (EXT && e.kind == K_RBEND) {
+          rbend_rotate(e.rb, X, Px, Y, Py, T, p);
+          rbend_fringe(e.rb, 1.0, X, Px, Y, Py, T, p);
+          rbend_body(e.rb, e.rb.L, X, Px, Y, Py, T, p);
+          rbend_fringe(e.rb, -1.0, X, Px, Y, Py, T, p);
+          rbend_rotate(e.rb, X, Px, Y, Py, T, p);
+          T += e.rb.larc_ib0;
         } else if (EXT && e.kind == K_SOLENOID) {
           const SolState st = sol_state<NT>(e.sol, X, Px, Y, Py, p, a.ymax, a.inv_beta0);
           for (int jj = 0; jj < e.nsl; ++jj) solenoid_slice(e.sol, st, X, Px, Y, Py, T);
@@ -484,6 +576,9 @@ track_kernel(const TrackArgs a) {
             Py += fma(hk1, Y, hk2 * X * Y);
           }
         }
+      } else if (EXT && e.kind == K_RBEND) {
+        if (e.place == P_MIDPOINT) q = rbend_element<NT, P_MIDPOINT>(e, X, Px, Y, Py, T, p, a);
+        else                       q = rbend_element<NT, P_EDGES>(e, X, Px, Y, Py, T, p, a);
       } else if (EXT && e.kind == K_SOLENOID) {
         if (e.place == P_MIDPOINT) q = solenoid_element<NT, P_MIDPOINT>(e, X, Px, Y, Py, T, p, a);
         else                       q = solenoid_element<NT, P_EDGES>(e, X, Px, Y, Py, T, p, a);

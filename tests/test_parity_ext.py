@@ -12,7 +12,7 @@ import oracle
 from test_parity_fp64 import (BEAM, SPIN_TOL, assert_multiturn_parity, assert_parity, both,
                               orbit_rel_err)
 from workloads import Beam, gaussian_bunch, rhic_like_ring
-from workloads.lattice import drift, quad, sbend, snake, solenoid
+from workloads.lattice import drift, quad, rbend, sbend, snake, solenoid
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +35,11 @@ ELEMENTS = {
     "solenoid_R4_strong": [solenoid(2.1, 0.5, 8, 4)],
     "solenoid_negative": [solenoid(1.0, -0.3, 6, 2)],
     "solenoid_midpoint": [solenoid(2.1, 0.5, 8, 1, spin="midpoint")],
+    "rbend_R3": [rbend(3.0, 0.12, 8, 3)],
+    "rbend_R4_strong": [rbend(3.0, 0.6, 16, 4)],
+    "rbend_mispowered": [rbend(3.0, 0.12, 4, 2, eta=0.98)],
+    "rbend_negative": [rbend(2.0, -0.1, 6, 2)],
+    "rbend_midpoint": [rbend(3.0, 0.12, 5, 1, spin="midpoint")],
 }
 
 
@@ -86,6 +91,20 @@ def test_small_ring_with_a_solenoid_in_a_straight():
     assert_multiturn_parity(g, o, ring, BEAM, z, s, a, 8, "small ring + solenoid, 8 turns")
 
 
+def test_small_ring_with_rectangular_bends():
+    # the small ring's sector bends replaced by rectangular bends of the same
+    # angle and design arc (straight length 2ρ sin(θ/2))
+    rho = 10.0 / TH
+    ring = [rbend(2 * rho * math.sin(TH / 2), TH, 8, 3) if e.kind == "sbend" else e
+            for e in pwc_ring(N=4)]
+    ring = [quad(e.L, e.k1, "mk", 4, 3) if e.kind == "quad" else e for e in ring]
+    z, s, a = gaussian_bunch(700, 1501034516, BEAM)
+    g, o = both(ring, BEAM, z, s, a, turns=1, want_q=True)
+    assert_parity(g, o, "rbend ring")
+    g, o = both(ring, BEAM, z, s, a, turns=8)
+    assert_multiturn_parity(g, o, ring, BEAM, z, s, a, 8, "rbend ring, 8 turns")
+
+
 def test_low_energy_solenoid():
     # 1.2 GeV protons through the 2.1 m, 1.3 T solenoid: a large spin rotation
     beam = Beam(gamma0=1.2 / 0.938272)
@@ -124,6 +143,8 @@ def test_invalid_placements_are_rejected_before_device_work():
         [quad(1.0, 0.05, "teapot", 4, 1)],                         # teapot only for bends
         [solenoid(2.0, 0.2, 4, 1, spin="kick")],                   # no kick in a solenoid
         [solenoid(2.0, 0.0, 4, 1)],                                # ks must be non-zero
+        [rbend(3.0, 0.12, 4, 1, eta=0.0)],                         # rbend needs a field
+        [rbend(3.0, 0.12, 4, 1, spin="kick")],                     # no kick placement
     ]
     for elems in bad:
         with pytest.raises(SpinTrackError):
