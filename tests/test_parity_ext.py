@@ -98,9 +98,18 @@ def test_small_ring_with_rectangular_bends():
     ring = [rbend(2 * rho * math.sin(TH / 2), TH, 8, 3) if e.kind == "sbend" else e
             for e in pwc_ring(N=4)]
     ring = [quad(e.L, e.k1, "mk", 4, 3) if e.kind == "quad" else e for e in ring]
+    # Px swings from +sin(θ/2) to -sin(θ/2) (1e-1) inside each magnet and back
+    # to 1e-4 at the exit rotation: double rounding of those terms leaves
+    # ~1e-16 in Px per turn, 1e-12 of its RMS, so the one-turn bound here is
+    # 2e-12, and a fraction of the error of a plain double evaluation of the
+    # printed maps
     z, s, a = gaussian_bunch(700, 1501034516, BEAM)
     g, o = both(ring, BEAM, z, s, a, turns=1, want_q=True)
-    assert_parity(g, o, "rbend ring")
+    assert_parity(g, o, "rbend ring", orbit_tol=2e-12)
+    plain, _ = orbit_rel_err(oracle.track(ring, BEAM, z, s, a, turns=1, extended=False), o)
+    err, _ = orbit_rel_err(g, o)
+    print(f"rbend ring: GPU orbit rel err {err:.3e}, plain FP64 {plain:.3e}")
+    assert err <= 0.25 * plain
     g, o = both(ring, BEAM, z, s, a, turns=8)
     assert_multiturn_parity(g, o, ring, BEAM, z, s, a, 8, "rbend ring, 8 turns")
 
