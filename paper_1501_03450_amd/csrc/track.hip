@@ -42,8 +42,14 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
   return d;
 }
 
+// Waves per SIMD the register allocation aims at: three for the plain double
+// kernel (168 VGPRs, a few spilled; measured faster than two waves at 209
+// VGPRs), two for the variants with more live state.
 #ifndef ST_WAVES_PER_EU
-#define ST_WAVES_PER_EU 2
+#define ST_WAVES_PER_EU 3
+#endif
+#ifndef ST_WAVES_PER_EU_WIDE
+#define ST_WAVES_PER_EU_WIDE 2
 #endif
 
 // Romberg spin integration through one thick element, fused with its orbit
@@ -499,7 +505,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // constant spin placements (kept out of the other instantiations so that
 // their register allocation is not shaped by code they never run).
 template <int NT, bool MIXED, bool SURR, bool EXT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ST_WAVES_PER_EU)))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((MIXED || SURR || EXT) ? ST_WAVES_PER_EU_WIDE : ST_WAVES_PER_EU)))
 track_kernel(const TrackArgs a) {
   __shared__ double red[kBlock / 64][4];
   // Cold per-lane data in LDS: the spin (touched once per turn) and the
