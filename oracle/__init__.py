@@ -39,7 +39,7 @@ SPIN_CODES = {"edges": 0, "kick": 1, "midpoint": 2}
 class _Elem(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("nsl", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("spin", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("spin", ctypes.c_int32), ("fringe", ctypes.c_int32),
                 ("L", ctypes.c_double), ("angle", ctypes.c_double), ("eta", ctypes.c_double),
                 ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
                 ("phi", ctypes.c_double), ("mu", ctypes.c_double), ("ks", ctypes.c_double)]
@@ -93,6 +93,9 @@ def _elems(elements):
         a.k1, a.k1l, a.k2l = e.k1, e.k1l, e.k2l
         a.phi, a.mu = e.snake_phi, e.snake_mu
         a.ks = getattr(e, "ks", 0.0)
+        a.fringe = int(bool(getattr(e, "fringe", False)))
+        if a.fringe and e.kind not in ("sbend", "quad"):
+            raise ValueError("fringe spin kicks apply to sector bends and quadrupoles")
         if e.kind == "sbend" and e.method not in ("exact", "teapot"):
             raise ValueError("sector bends use the exact map or teapot drift-kick slices")
         if e.kind == "quad" and e.method not in ("dkd", "mk"):

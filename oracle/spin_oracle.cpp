@@ -127,7 +127,8 @@ enum Method : int32_t { EXACT = 0, DKD = 1, MK = 2, TEAPOT = 3 };
 enum SpinPlace : int32_t { EDGES = 0, KICK = 1, MIDPOINT = 2 };
 
 struct Elem {             // the oracle's own element record
-  int32_t kind, method, nsl, rows, spin, pad;
+  int32_t kind, method, nsl, rows, spin;
+  int32_t fringe;         // sector bend or quadrupole: 1 adds the fringe spin kicks
   double L, angle, eta, k1, k1l, k2l, phi, mu;
   double ks;              // solenoid field b0/(Bρ)0 [1/m]
 };
@@ -387,6 +388,24 @@ template <class T> Quat<T> rbend_fringe_spin(const T z[6], T fb, T sign, const R
   return qrot(f * r.G * (gamma - T(1)) * z[PX], T(0), -f * (T(1) + r.G));
 }
 
+// Spin kick across the thin fringe of a normal 2m-pole crossed about
+// normally (§4.5 eq. skfringe): a rotation about ẑ by
+//   -sign (b_m/(Bρ)0) (1 + G) r^m sin(m φ)/m,   r^m sin(m φ) = Im (X + iY)^m,
+// sign +1 at the entrance and -1 at the exit.  A sector bend is the m = 1
+// case with b1/(Bρ)0 = η h, a quadrupole the m = 2 case with b2/(Bρ)0 = k1.
+template <class T> Quat<T> multipole_fringe_spin(const Elem& e, const T z[6], T sign,
+                                                 const Ref<T>& r) {
+  int m = e.kind == SBEND ? 1 : 2;
+  T bm = e.kind == SBEND ? T(e.eta) * T(e.angle) / T(e.L) : T(e.k1);
+  T re = T(1), im = T(0);                       // (X + iY)^m
+  for (int k = 0; k < m; ++k) {
+    T nre = re * z[X] - im * z[Y];
+    im = re * z[Y] + im * z[X];
+    re = nre;
+  }
+  return qrot(T(0), T(0), -sign * bm * (T(1) + r.G) * im / T(m));
+}
+
 // Matrix-kick quadrupole, linear part over a length s (§3.3 eq. quadL).  The
 // printed solution is for a focusing gradient; a defocusing one (k1 < 0) is
 // the same map with the roles of (X, Px) and (Y, Py) exchanged.
@@ -623,6 +642,14 @@ Quat<T> element(const Elem& e, T z[6], const Ref<T>& r) {
     }
     case SBEND:
     case QUAD: {
+      if (e.fringe) {   // fringe spin kicks around the body (§4.5)
+        Quat<T> qin = multipole_fringe_spin(e, z, T(1), r);
+        Elem body = e;
+        body.fringe = 0;
+        Quat<T> Qb = element(body, z, r);
+        Quat<T> qout = multipole_fringe_spin(e, z, T(-1), r);
+        return qmul(qout, qmul(Qb, qin));
+      }
       int N = e.nsl;
       T ds = T(e.L) / T(N);
       T h = e.kind == SBEND ? T(e.angle) / T(e.L) : T(0);

@@ -237,3 +237,71 @@ def track_rbend(L, angle, eta, eps, beam, z, s, rtol=1e-13, atol=1e-16):
     larc = angle * L / (2 * math.sin(half))
     zz[4] += (larc - (L + eps)) / beam.beta0
     return zz, S
+
+
+def _rhs_fringed(h, b1, k1, profile, beam):
+    """A dipole b1 = b1/(Bρ)0 (in a frame of curvature h) or a quadrupole
+    k1 (h = 0) scaled by a longitudinal profile F(s), from the vector
+    potential
+        a_x = -b1 F' Y²/2 - (k1/4) F' X Y²,   a_y = (k1/4) F' X² Y,
+        (1 + hX) a_s = -b1 F (X + hX²/2) - (k1/2) F (X² - Y²),
+    whose curl inside a linear ramp (F'' = 0) is
+        b = (k1 F Y, b1 F + k1 F X, b1 F' Y + k1 F' X Y):
+    the longitudinal field of the fringe to lowest order.  Hamilton's
+    equations of H = -(1 + hX) Ps - (1 + hX) a_s + Pt/β0 with Ps from the
+    kinetic momenta (Px - a_x, Py - a_y); the spin precesses about Ω of
+    eq. t-bmt.s with û along the kinetic momentum."""
+    b0 = beam.beta0
+    assert h == 0.0 or k1 == 0.0
+
+    def f(s, y):
+        X, Px, Y, Py, T, Pt, Sx, Sy, Sz = y
+        F, dF = profile(s)
+        w = 1.0 + h * X
+        ax = -b1 * dF * Y * Y / 2.0 - 0.25 * k1 * dF * X * Y * Y
+        ay = 0.25 * k1 * dF * X * X * Y
+        kx, ky = Px - ax, Py - ay
+        P2 = 1.0 + 2.0 * Pt / b0 + Pt * Pt
+        Ps = math.sqrt(P2 - kx * kx - ky * ky)
+        dax_dx, day_dx = -0.25 * k1 * dF * Y * Y, 0.5 * k1 * dF * X * Y
+        dax_dy, day_dy = -b1 * dF * Y - 0.5 * k1 * dF * X * Y, 0.25 * k1 * dF * X * X
+        dwas_dx = -b1 * F * w - k1 * F * X
+        dwas_dy = k1 * F * Y
+        b = np.array([k1 * F * Y, b1 * F + k1 * F * X, b1 * dF * Y + k1 * dF * X * Y])
+        u = np.array([kx, ky, Ps]) / math.sqrt(P2)
+        gamma = beam.gamma0 * (1.0 + b0 * Pt)
+        a1, a2 = 1.0 + beam.G * gamma, beam.G * (gamma - 1.0)
+        om = -(w / Ps) * (a1 * b - a2 * float(u @ b) * u)
+        om[1] += h
+        dS = np.cross(om, np.array([Sx, Sy, Sz]))
+        return [w * kx / Ps,
+                h * Ps + w * (kx * dax_dx + ky * day_dx) / Ps + dwas_dx,
+                w * ky / Ps,
+                w * (kx * dax_dy + ky * day_dy) / Ps + dwas_dy,
+                -w * (1.0 / b0 + Pt) / Ps + 1.0 / b0, 0.0, dS[0], dS[1], dS[2]]
+    return f
+
+
+def track_fringed(e, eps, beam, z, s, rtol=1e-13, atol=1e-16):
+    """A sector bend or quadrupole (workloads.Element) whose field rises
+    linearly over [-eps/2, eps/2] about the entrance face and falls over
+    [L - eps/2, L + eps/2] about the exit face, so the field integral is
+    that of the hard-edge magnet.  A bend's curved frame covers [0, L]; the
+    outer halves of its ramps lie in straight frames.  Compare with the
+    hard-edge magnet between two drifts of eps/2."""
+    L = e.L
+    if e.kind == "sbend":
+        h, b1, k1 = e.angle / L, e.eta * e.angle / L, 0.0
+    else:
+        h, b1, k1 = 0.0, 0.0, e.k1
+    rise = lambda t: ((t + eps / 2) / eps, 1.0 / eps)
+    flat = lambda t: (1.0, 0.0)
+    fall = lambda t: ((L + eps / 2 - t) / eps, -1.0 / eps)
+    pieces = [(-eps / 2, 0.0, 0.0, rise), (0.0, eps / 2, h, rise), (eps / 2, L - eps / 2, h, flat),
+              (L - eps / 2, L, h, fall), (L, L + eps / 2, 0.0, fall)]
+    y = np.concatenate([np.asarray(z, float), np.asarray(s, float)])
+    for a, b, hh, prof in pieces:
+        sol = solve_ivp(_rhs_fringed(hh, b1, k1, prof, beam), (a, b), y, method="DOP853",
+                        rtol=rtol, atol=atol)
+        y = sol.y[:, -1]
+    return y[:6].copy(), y[6:].copy()

@@ -30,6 +30,9 @@ Spin placement in thick elements (`spin`)
   kick      drift-kick slices: one rotation per slice between its half kicks
   midpoint  one rotation per slice with Ω at the slice's middle
 
+`fringe` (sector bends and quadrupoles) adds the spin kicks of thin magnet
+fringes at both faces; the orbit is unchanged.
+
 `n_slices` is the number of orbit slices N; `rows` is the number R of
 Romberg tableau rows requested for the element's spin (R = 1 means the plain
 trapezoid product with no extrapolation).
@@ -65,6 +68,7 @@ class Element:
     name: str = ""
     spin: str = "edges"
     ks: float = 0.0
+    fringe: bool = False
 
     def __post_init__(self):
         if self.kind not in KINDS:
@@ -73,6 +77,8 @@ class Element:
             raise ValueError(f"unknown integration method {self.method!r}")
         if self.spin not in SPIN_PLACES:
             raise ValueError(f"unknown spin placement {self.spin!r}")
+        if self.fringe and self.kind not in ("sbend", "quad"):
+            raise ValueError("fringe spin kicks apply to sector bends and quadrupoles")
 
 
 def drift(L: float, name: str = "D") -> Element:
@@ -80,14 +86,17 @@ def drift(L: float, name: str = "D") -> Element:
 
 
 def sbend(L: float, angle: float, n: int, rows: int, eta: float = 1.0, name: str = "SB",
-          method: str = "exact", spin: str = "edges") -> Element:
+          method: str = "exact", spin: str = "edges", fringe: bool = False) -> Element:
+    """Sector bend; fringe=True adds the thin-fringe spin kicks of its faces."""
     return Element("sbend", L=L, angle=angle, eta=eta, n_slices=n, rows=rows, name=name,
-                   method=method, spin=spin)
+                   method=method, spin=spin, fringe=fringe)
 
 
 def quad(L: float, k1: float, method: str, n: int, rows: int, name: str = "Q",
-         spin: str = "edges") -> Element:
-    return Element("quad", L=L, k1=k1, method=method, n_slices=n, rows=rows, name=name, spin=spin)
+         spin: str = "edges", fringe: bool = False) -> Element:
+    """Quadrupole; fringe=True adds the thin-fringe spin kicks of its faces."""
+    return Element("quad", L=L, k1=k1, method=method, n_slices=n, rows=rows, name=name, spin=spin,
+                   fringe=fringe)
 
 
 def solenoid(L: float, ks: float, n: int, rows: int, name: str = "SOL",
