@@ -32,7 +32,7 @@ _lib = None
 
 KIND_CODES = {"marker": 0, "drift": 1, "sbend": 2, "quad": 3, "thin": 4, "snake": 5,
               "solenoid": 6, "rbend": 7}
-METHOD_CODES = {"exact": 0, "dkd": 1, "mk": 2, "teapot": 3}
+METHOD_CODES = {"exact": 0, "dkd": 1, "mk": 2, "teapot": 3, "dkd4": 4, "mk4": 5}
 SPIN_CODES = {"edges": 0, "kick": 1, "midpoint": 2}
 
 
@@ -98,8 +98,10 @@ def _elems(elements):
             raise ValueError("fringe spin kicks apply to sector bends and quadrupoles")
         if e.kind == "sbend" and e.method not in ("exact", "teapot"):
             raise ValueError("sector bends use the exact map or teapot drift-kick slices")
-        if e.kind == "quad" and e.method not in ("dkd", "mk"):
-            raise ValueError("quadrupoles use dkd or mk slices")
+        if e.kind == "quad" and e.method not in ("dkd", "mk", "dkd4", "mk4"):
+            raise ValueError("quadrupoles use dkd, mk, dkd4 or mk4 slices")
+        if e.kind != "quad" and e.method in ("dkd4", "mk4"):
+            raise ValueError("fourth-order compositions apply to quadrupoles")
         if e.kind == "rbend":
             if e.method != "exact" or e.n_slices < 1 or e.rows < 1 or e.L <= 0 or e.angle == 0:
                 raise ValueError("rectangular bends: exact body, L > 0, angle != 0, n_slices, rows >= 1")

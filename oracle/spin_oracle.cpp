@@ -117,7 +117,9 @@ inline long double value_(long double a) { return a; }
 
 enum Kind : int32_t { MARKER = 0, DRIFT = 1, SBEND = 2, QUAD = 3, THIN = 4, SNAKE = 5, SOLENOID = 6,
                       RBEND = 7 };
-enum Method : int32_t { EXACT = 0, DKD = 1, MK = 2, TEAPOT = 3 };
+enum Method : int32_t { EXACT = 0, DKD = 1, MK = 2, TEAPOT = 3, DKD4 = 4, MK4 = 5 };
+// DKD4 and MK4: quadrupole slices composed of three second-order slices into
+// a fourth-order symmetric integrator (Yoshida's triple jump).
 // Where the spin is integrated inside a thick element:
 //   EDGES     Ω at the N + 1 slice edges, trapezoid products and Romberg (§4.3)
 //   KICK      drift-kick slices only: the rotation by Δs Ω sits between the two
@@ -542,6 +544,21 @@ template <class T> T rbend_fb(const Elem& e) {
   return T(e.eta) * T(2) * sin(T(e.angle) / T(2)) / T(e.L);
 }
 
+// One second-order quadrupole slice: drift-kick-drift (§3.4 applied to
+// m = 2) or matrix-kick-matrix (§3.3 eq. quadConcat).
+template <class T>
+void quad_slice2(const Elem& e, T z[6], T ds, const Ref<T>& r) {
+  if (e.method == DKD || e.method == DKD4) {
+    drift(z, ds / T(2), r);
+    kick(z, T(e.k1) * ds, T(0));
+    drift(z, ds / T(2), r);
+  } else {
+    quad_linear(z, ds / T(2), T(e.k1), r);
+    quad_nonlinear(z, ds, r);
+    quad_linear(z, ds / T(2), T(e.k1), r);
+  }
+}
+
 template <class T>
 void slice(const Elem& e, T z[6], T ds, const Ref<T>& r) {
   if (e.kind == RBEND) {
@@ -554,14 +571,19 @@ void slice(const Elem& e, T z[6], T ds, const Ref<T>& r) {
     dk_drift(e, z, ds / T(2), r);
   } else if (e.kind == SBEND) {
     sbend_step(z, ds, T(e.angle) / T(e.L), T(e.eta), r);
-  } else if (e.method == DKD) {           // drift-kick-drift (§3.4 applied to m = 2)
-    drift(z, ds / T(2), r);
-    kick(z, T(e.k1) * ds, T(0));
-    drift(z, ds / T(2), r);
-  } else {                                // matrix-kick-matrix (§3.3 eq. quadConcat)
-    quad_linear(z, ds / T(2), T(e.k1), r);
-    quad_nonlinear(z, ds, r);
-    quad_linear(z, ds / T(2), T(e.k1), r);
+  } else if (e.method == DKD4 || e.method == MK4) {
+    // The symmetric second-order slice S2 has an error odd in ds starting at
+    // ds^3; S2(x1 ds) S2(x0 ds) S2(x1 ds) with 2 x1 + x0 = 1 and
+    // 2 x1^3 + x0^3 = 0 cancels it, leaving fourth order (the higher-order
+    // compositions §3.3 refers to).
+    using std::cbrt;
+    T c2 = T(cbrt(2.0L));
+    T x1 = T(1) / (T(2) - c2), x0 = -c2 / (T(2) - c2);
+    quad_slice2(e, z, x1 * ds, r);
+    quad_slice2(e, z, x0 * ds, r);
+    quad_slice2(e, z, x1 * ds, r);
+  } else {
+    quad_slice2(e, z, ds, r);
   }
 }
 

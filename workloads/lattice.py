@@ -24,6 +24,8 @@ Orbit integration methods
   dkd     drift-kick-drift slices (quadrupoles)
   mk      matrix-kick-matrix slices (quadrupoles)
   teapot  drift-kick-drift slices of a sector bend in its curved frame
+  dkd4, mk4  quadrupole slices of three dkd or mk steps of lengths
+          x1 ds, x0 ds, x1 ds (x1 = 1/(2 - 2^(1/3)), x0 = 1 - 2 x1): fourth order
 
 Spin placement in thick elements (`spin`)
   edges     Ω at the slice edges, Romberg tableau over R rows (default)
@@ -47,7 +49,7 @@ from typing import List, Sequence
 import numpy as np
 
 KINDS = ("marker", "drift", "sbend", "quad", "thin", "snake", "solenoid", "rbend")
-METHODS = ("exact", "dkd", "mk", "teapot")
+METHODS = ("exact", "dkd", "mk", "teapot", "dkd4", "mk4")
 SPIN_PLACES = ("edges", "kick", "midpoint")
 
 
