@@ -71,9 +71,14 @@ typedef enum {
   ST_ORB_EXACT = 0, /* exact flow: drifts and sector bends                     */
   ST_ORB_DKD = 1,   /* drift-kick-drift slices (quadrupoles)                   */
   ST_ORB_MK = 2,    /* matrix-kick-matrix slices (§3.3 eq. quadConcat)         */
-  ST_ORB_TEAPOT = 3 /* sector bend in drift-kick-drift slices: the drift of the
+  ST_ORB_TEAPOT = 3, /* sector bend in drift-kick-drift slices: the drift of the
                        curved frame (§3.6 eq. teapotD) and the dipole kick
                        Px -= eta h (1 + hX) ds (from eq. teapotHK)             */
+  ST_ORB_DKD4 = 4,  /* quadrupoles: each slice is three DKD slices of lengths
+                       x1 ds, x0 ds, x1 ds, x1 = 1/(2 - 2^(1/3)), x0 = 1 - 2 x1
+                       (a fourth-order symmetric composition; §3.3 after eq.
+                       quadConcat); spin_place EDGES or MIDPOINT             */
+  ST_ORB_MK4 = 5    /* quadrupoles: the same composition of MK slices          */
 } st_orbit;
 
 typedef enum {
@@ -111,11 +116,16 @@ typedef enum {
  *   spin_place   where the spin is integrated in a thick element
  *                (st_spin_place); ST_SPIN_KICK needs DKD quadrupole or
  *                TEAPOT bend slices
- *   reserved     must be 0
+ *   fringe       sector bends and quadrupoles: 1 adds the spin kicks of thin
+ *                magnet fringes at both faces (§4.5 eq. skfringe): rotations
+ *                about the longitudinal axis by -(1 + G) b1 Y / (Bρ)0 (bend,
+ *                b1/(Bρ)0 = eta·h) or -(1 + G) k1 X Y (quadrupole) at the
+ *                entrance and the opposite expression at the exit; the orbit
+ *                is unchanged.  0 for every other kind
  *   ks           solenoid longitudinal field b0/(Bρ)0 [m^-1] (0 otherwise)
  */
 typedef struct {
-  int32_t kind, orbit, n_slices, romberg_rows, spin_place, reserved;
+  int32_t kind, orbit, n_slices, romberg_rows, spin_place, fringe;
   double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks;
 } st_element;
 

@@ -19,13 +19,14 @@ LIB_PATH = os.environ.get("SPINTRACK_LIB", os.path.join(_HERE, "libspintrack.so"
 
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDEVICE, ST_ESTATE = 0, -1, -2, -3, -4
 ST_MARKER, ST_DRIFT, ST_SBEND, ST_QUAD, ST_THIN, ST_SNAKE, ST_SOLENOID, ST_RBEND = range(8)
-ST_ORB_EXACT, ST_ORB_DKD, ST_ORB_MK, ST_ORB_TEAPOT = range(4)
+ST_ORB_EXACT, ST_ORB_DKD, ST_ORB_MK, ST_ORB_TEAPOT, ST_ORB_DKD4, ST_ORB_MK4 = range(6)
 ST_SPIN_EDGES, ST_SPIN_KICK, ST_SPIN_MIDPOINT = range(3)
 ST_FP64, ST_MIXED, ST_MIXED_ALL = 0, 1, 2
 
 KIND_CODES = {"marker": ST_MARKER, "drift": ST_DRIFT, "sbend": ST_SBEND, "quad": ST_QUAD,
               "thin": ST_THIN, "snake": ST_SNAKE, "solenoid": ST_SOLENOID, "rbend": ST_RBEND}
-ORBIT_CODES = {"exact": ST_ORB_EXACT, "dkd": ST_ORB_DKD, "mk": ST_ORB_MK, "teapot": ST_ORB_TEAPOT}
+ORBIT_CODES = {"exact": ST_ORB_EXACT, "dkd": ST_ORB_DKD, "mk": ST_ORB_MK, "teapot": ST_ORB_TEAPOT,
+               "dkd4": ST_ORB_DKD4, "mk4": ST_ORB_MK4}
 SPIN_CODES = {"edges": ST_SPIN_EDGES, "kick": ST_SPIN_KICK, "midpoint": ST_SPIN_MIDPOINT}
 PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED, "mixed_all": ST_MIXED_ALL}
 
@@ -39,7 +40,7 @@ EXPORTS = ("st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
 class st_element(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("orbit", ctypes.c_int32),
                 ("n_slices", ctypes.c_int32), ("romberg_rows", ctypes.c_int32),
-                ("spin_place", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("spin_place", ctypes.c_int32), ("fringe", ctypes.c_int32),
                 ("L", ctypes.c_double), ("angle", ctypes.c_double), ("eta", ctypes.c_double),
                 ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
                 ("snake_phi", ctypes.c_double), ("snake_mu", ctypes.c_double),
@@ -135,6 +136,7 @@ def element_array(elements):
         a.k1, a.k1l, a.k2l = float(e.k1), float(e.k1l), float(e.k2l)
         a.snake_phi, a.snake_mu = float(e.snake_phi), float(e.snake_mu)
         a.ks = float(getattr(e, "ks", 0.0))
+        a.fringe = int(getattr(e, "fringe", 0))
     return arr
 
 

@@ -26,7 +26,8 @@ struct st_ctx {
   int n_elems = 0;
   int n_unique = 0;
   int nt = 16;             // quaternion series terms
-  bool ext = false;        // lattice needs the extended kernel (TEAPOT, PWC placements)
+  bool ext = false;        // lattice needs the extended kernel (TEAPOT, PWC placements,
+                           // solenoids, rectangular bends, fringe spin kicks)
   double ymax = 0.0;
   st::DevElem* d_tab = nullptr;
   uint32_t* d_seq = nullptr;
@@ -102,10 +103,14 @@ std::string validate(const st_element& e, int64_t i) {
   const std::string at = "element " + std::to_string(i) + ": ";
   if (!finite_all(e)) return at + "non-finite parameter";
   if (e.kind < ST_MARKER || e.kind > ST_RBEND) return at + "unknown kind " + std::to_string(e.kind);
-  if (e.orbit < ST_ORB_EXACT || e.orbit > ST_ORB_TEAPOT) return at + "unknown orbit method";
+  if (e.orbit < ST_ORB_EXACT || e.orbit > ST_ORB_MK4) return at + "unknown orbit method";
+  if ((e.orbit == ST_ORB_DKD4 || e.orbit == ST_ORB_MK4) && e.kind != ST_QUAD)
+    return at + "fourth-order slices apply to quadrupoles";
   if (e.spin_place < ST_SPIN_EDGES || e.spin_place > ST_SPIN_MIDPOINT)
     return at + "unknown spin placement";
-  if (e.reserved != 0) return at + "reserved field must be 0";
+  if (e.fringe != 0 && e.fringe != 1) return at + "fringe must be 0 or 1";
+  if (e.fringe != 0 && e.kind != ST_SBEND && e.kind != ST_QUAD)
+    return at + "fringe spin kicks apply to sector bends and quadrupoles";
   if (e.L < 0.0) return at + "negative length";
   switch (e.kind) {
     case ST_DRIFT:
@@ -121,7 +126,9 @@ std::string validate(const st_element& e, int64_t i) {
         return at + "slice angle too large for the TEAPOT drift";
       break;
     case ST_QUAD:
-      if (e.orbit != ST_ORB_DKD && e.orbit != ST_ORB_MK) return at + "quadrupoles use DKD or MK";
+      if (e.orbit != ST_ORB_DKD && e.orbit != ST_ORB_MK && e.orbit != ST_ORB_DKD4 &&
+          e.orbit != ST_ORB_MK4)
+        return at + "quadrupoles use DKD, MK, DKD4 or MK4";
       if (!(e.L > 0.0)) return at + "quadrupole needs L > 0";
       break;
     case ST_RBEND:
@@ -181,6 +188,7 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
   if (thick && (beam.precision == ST_MIXED_ALL ||
                 (beam.precision == ST_MIXED && design_angle(e, beam, 0.005) <= kSpin32MaxAngle)))
     d.flags |= st::F_SPIN32;
+  if (e.fringe) d.flags |= st::F_FRINGE;
   // orbit slices: the midpoint placement runs 2N half slices
   const int n_orb = e.spin_place == ST_SPIN_MIDPOINT ? 2 * e.n_slices : e.n_slices;
   if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID || e.kind == ST_RBEND) {
@@ -228,12 +236,22 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
     b.slice = step(b.ds);
     b.whole = step(e.L);
   } else if (e.kind == ST_QUAD) {
-    st::QuadParams& q = d.q;
-    q.ds = e.L / n_orb;
-    q.hds = 0.5 * q.ds;
-    q.k1 = e.k1;
-    q.k1ds = e.k1 * q.ds;
-    q.kabs_hds2 = std::fabs(e.k1) * q.hds * q.hds;
+    auto fill = [&](st::QuadParams& q, double ds) {
+      q.ds = ds;
+      q.hds = 0.5 * ds;
+      q.k1 = e.k1;
+      q.k1ds = e.k1 * ds;
+      q.kabs_hds2 = std::fabs(e.k1) * q.hds * q.hds;
+    };
+    fill(d.q, e.L / n_orb);
+    if (e.orbit == ST_ORB_DKD4 || e.orbit == ST_ORB_MK4) {
+      // triple jump: 2 x1 + x0 = 1, 2 x1^3 + x0^3 = 0
+      const long double c2 = std::cbrt(2.0L);
+      const long double x1 = 1.0L / (2.0L - c2), x0 = -c2 / (2.0L - c2);
+      const long double ds = (long double)e.L / n_orb;
+      fill(d.q4.s1, (double)(x1 * ds));
+      fill(d.q4.s0, (double)(x0 * ds));
+    }
   } else if (e.kind == ST_RBEND) {
     st::RbendParams& rb = d.rb;
     const double half = 0.5 * e.angle;
@@ -402,8 +420,9 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   double theta = 0.0;
   bool ext = false;
   for (int64_t i = 0; i < n; ++i) {
-    ext = ext || els[i].orbit == ST_ORB_TEAPOT || els[i].spin_place != ST_SPIN_EDGES ||
-          els[i].kind == ST_SOLENOID || els[i].kind == ST_RBEND;
+    ext = ext || els[i].orbit == ST_ORB_TEAPOT || els[i].orbit == ST_ORB_DKD4 ||
+          els[i].orbit == ST_ORB_MK4 || els[i].spin_place != ST_SPIN_EDGES ||
+          els[i].kind == ST_SOLENOID || els[i].kind == ST_RBEND || els[i].fringe != 0;
     int k = -1;
     for (size_t u = 0; u < uniq.size(); ++u)
       if (std::memcmp(&uniq[u], &els[i], sizeof(st_element)) == 0) { k = (int)u; break; }

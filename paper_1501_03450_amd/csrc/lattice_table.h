@@ -15,7 +15,7 @@ namespace st {
 
 enum : int32_t { K_MARKER = 0, K_DRIFT = 1, K_SBEND = 2, K_QUAD = 3, K_THIN = 4, K_SNAKE = 5,
                  K_SOLENOID = 6, K_RBEND = 7 };
-enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2, M_TEAPOT = 3 };
+enum : int32_t { M_EXACT = 0, M_DKD = 1, M_MK = 2, M_TEAPOT = 3, M_DKD4 = 4, M_MK4 = 5 };
 // spin placement in thick elements: Romberg over the slice edges, or one
 // piece-wise constant rotation per slice between the half kicks or at the
 // slice's middle
@@ -40,6 +40,10 @@ struct QuadParams {        // quadrupole (§3.3, §3.4)
   double ds, hds;          // slice length and half of it
   double k1, k1ds;         // gradient, DKD kick k1·ds
   double kabs_hds2;        // |k1| (ds/2)²: (κ ds/2)² times P
+};
+struct Quad4Params {       // fourth-order quadrupole slice (M_DKD4, M_MK4)
+  QuadParams q;            // the whole slice (Ω weights, k1)
+  QuadParams s1, s0;       // the composed steps of lengths x1 ds and x0 ds
 };
 struct TeapotParams {       // drift-kick sector bend (§3.6)
   double ds;                // orbit slice length (kick length)
@@ -71,8 +75,11 @@ constexpr int kElemWords = sizeof(BendParams) / sizeof(double);   // largest mem
 static_assert(sizeof(TeapotParams) <= sizeof(BendParams), "element union size");
 static_assert(sizeof(SolenoidParams) <= sizeof(BendParams), "element union size");
 static_assert(sizeof(RbendParams) <= sizeof(BendParams), "element union size");
+static_assert(sizeof(Quad4Params) <= sizeof(BendParams), "element union size");
 
-enum : int32_t { F_SPIN32 = 1 };   // element flag: single-precision spin arithmetic
+// element flags: single-precision spin arithmetic; thin-fringe spin kicks at
+// both faces (sector bends and quadrupoles, extended kernels only)
+enum : int32_t { F_SPIN32 = 1, F_FRINGE = 2 };
 
 struct DevElem {
   int32_t kind, orbit, nsl, K;   // K = R_e - 1: Romberg levels minus one
@@ -84,6 +91,7 @@ struct DevElem {
     SolenoidParams sol;
     RbendParams rb;
     QuadParams q;
+    Quad4Params q4;
     DriftParams d;
     ThinParams t;
     SnakeParams s;

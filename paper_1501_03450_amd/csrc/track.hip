@@ -59,7 +59,43 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
 // elements flagged F_SPIN32 use single-precision edge quaternions and
 // compensated single-precision level products.  Returns the normalised
 // element quaternion.
-template <int NT, int KIND, bool MIXED>
+// One second-order quadrupole step over the length of q: matrix-kick-matrix
+// (KIND 1 focusing in x, 3 focusing in y) or drift-kick-drift (KIND 2).
+template <int KIND>
+__device__ __forceinline__ void quad_step2(const QuadParams& q, const MKConst& mc, double& X,
+                                           double& Px, double& Y, double& Py, double& T,
+                                           const Particle& p, const TrackArgs& a) {
+  if (KIND == 1) {
+    mk_linear(mc, X, Px, Y, Py, T, p);
+    mk_nonlinear(q.ds, X, Px, Y, Py, T, p);
+    mk_linear(mc, X, Px, Y, Py, T, p);
+  } else if (KIND == 3) {
+    mk_linear(mc, Y, Py, X, Px, T, p);
+    mk_nonlinear(q.ds, X, Px, Y, Py, T, p);
+    mk_linear(mc, Y, Py, X, Px, T, p);
+  } else {
+    drift(q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+    Px = fma(-q.k1ds, X, Px);
+    Py = fma(q.k1ds, Y, Py);
+    drift(q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+  }
+}
+
+// Fourth-order quadrupole slice (orbit methods DKD4, MK4): the second-order
+// step over x1 ds, x0 ds and x1 ds (2 x1 + x0 = 1, 2 x1^3 + x0^3 = 0).  m1 and
+// m0 are the MK constants of the two step lengths.
+template <int KIND>
+__device__ __forceinline__ void quad_slice4(const Quad4Params& q4, const MKConst& m1,
+                                            const MKConst& m0, double& X, double& Px, double& Y,
+                                            double& Py, double& T, const Particle& p,
+                                            const TrackArgs& a) {
+  quad_step2<KIND>(q4.s1, m1, X, Px, Y, Py, T, p, a);
+  quad_step2<KIND>(q4.s0, m0, X, Px, Y, Py, T, p, a);
+  quad_step2<KIND>(q4.s1, m1, X, Px, Y, Py, T, p, a);
+}
+
+// Y4: quadrupoles with the fourth-order slice (extended kernels only).
+template <int NT, int KIND, bool MIXED, bool Y4 = false>
 __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, double& Px, double& Y,
                                               double& Py, double& T, const Particle& p,
                                               const TrackArgs& a) {
@@ -74,8 +110,12 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
 
   // bend invariants of this particle: Py and Pt do not change in a bend
   double Pa2 = p.P2() - Py * Py;
-  MKConst mc;
-  if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+  MKConst mc, mc0;
+  if constexpr (Y4) {
+    if (KIND == 1 || KIND == 3) { mc = mk_const(el.q4.s1, p); mc0 = mk_const(el.q4.s0, p); }
+  } else {
+    if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+  }
 
   // Ps and 1/Ps at the entrance edge
   double ps2 = fma(-Px, Px, Pa2);
@@ -95,6 +135,8 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
       } else {
         if (KIND == 4) {
           teapot_slice(el.tp, X, Px, Y, Py, T, p);
+        } else if (Y4) {
+          quad_slice4<KIND>(el.q4, mc, mc0, X, Px, Y, Py, T, p, a);
         } else if (KIND == 1) {
           mk_linear(mc, X, Px, Y, Py, T, p);
           mk_nonlinear(ds, X, Px, Y, Py, T, p);
@@ -187,7 +229,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
 // Orbit only through a thick element (surrogate tracking, no spin): the
 // sector bend is an exact flow and is crossed in one step; quadrupoles keep
 // their slices.
-template <int KIND>
+template <int KIND, bool Y4 = false>
 __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double& Px, double& Y,
                                             double& Py, double& T, const Particle& p,
                                             const TrackArgs& a) {
@@ -198,6 +240,12 @@ __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double
     double W = ps2 * r;
     double wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
     bend_step(el.b, el.b.whole, X, Px, Py, Y, T, W, r, wme, Pa2, rcp_nr(Pa2), p);
+    return;
+  }
+  if constexpr (Y4) {
+    MKConst m1, m0;
+    if (KIND == 1 || KIND == 3) { m1 = mk_const(el.q4.s1, p); m0 = mk_const(el.q4.s0, p); }
+    for (int j = 0; j < el.nsl; ++j) quad_slice4<KIND>(el.q4, m1, m0, X, Px, Y, Py, T, p, a);
     return;
   }
   MKConst mc;
@@ -227,15 +275,19 @@ __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double
 // two half kicks of a drift-kick slice (PLACE == P_KICK; KIND 2 or 4) or at
 // the middle of the slice (P_MIDPOINT: the element carries 2N orbit half
 // slices and the rotation follows every odd one).
-template <int NT, int KIND, int PLACE>
+template <int NT, int KIND, int PLACE, bool Y4 = false>
 __device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double& Px, double& Y,
                                             double& Py, double& T, const Particle& p,
                                             const TrackArgs& a) {
   const double ds_orb = KIND == 0 ? el.b.ds : (KIND == 4 ? el.tp.ds : el.q.ds);
   const double w = PLACE == P_MIDPOINT ? 2.0 * ds_orb : ds_orb;   // spin step
   Quat Q = qident();
-  MKConst mc;
-  if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+  MKConst mc, mc0;
+  if constexpr (Y4) {
+    if (KIND == 1 || KIND == 3) { mc = mk_const(el.q4.s1, p); mc0 = mk_const(el.q4.s0, p); }
+  } else {
+    if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+  }
   double Pa2 = 0.0, invPa2 = 0.0, W = 0.0, r = 0.0, wme = 0.0;
   if (KIND == 0) {
     Pa2 = p.P2() - Py * Py;
@@ -259,6 +311,8 @@ __device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double
       bend_step(el.b, el.b.slice, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
     } else if (KIND == 4) {
       teapot_slice(el.tp, X, Px, Y, Py, T, p);
+    } else if (Y4) {
+      quad_slice4<KIND>(el.q4, mc, mc0, X, Px, Y, Py, T, p, a);
     } else if (KIND == 1) {
       mk_linear(mc, X, Px, Y, Py, T, p);
       mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
@@ -458,18 +512,56 @@ __device__ __forceinline__ Quat rbend_element(const DevElem& el, double& X, doub
   return qmul(qf, qmul(qout, qmul(Q, qmul(qin, qf))));
 }
 
-// Spin and orbit of a thick element with the extended methods: TEAPOT bends
-// and the piece-wise constant placements.
+// Spin kick across the thin fringe of a normal 2m-pole face crossed about
+// normally (§4.5 eq. skfringe): a rotation about ẑ by
+// -sign (1 + G) (b_m/(Bρ)0) Im[(X + iY)^m]/m, sign +1 at the entrance.
+// Sector bends (KIND 0, 4) are m = 1 with b1/(Bρ)0 = ηh; quadrupoles m = 2
+// with b2/(Bρ)0 = k1.
+template <int NT, int KIND>
+__device__ __forceinline__ Quat fringe_kick(const DevElem& el, double X, double Y, double sign,
+                                            const TrackArgs& a) {
+  const double im = (KIND == 0) ? el.b.eta_h * Y : (KIND == 4) ? el.tp.eta_h * Y : el.q.k1 * X * Y;
+  const double w = -sign * (1.0 + a.G) * im;
+  double c, sfac;
+  rot_half_angle<NT>(0.25 * w * w, a.ymax, c, sfac);
+  return Quat{c, 0.0, 0.0, sfac * w};
+}
+
+// Spin and orbit of a thick element with the extended methods: TEAPOT bends,
+// the piece-wise constant placements and the fringe spin kicks.
+template <int NT, int KIND, bool Y4>
+__device__ __forceinline__ Quat thick_body_ext(const DevElem& el, double& X, double& Px, double& Y,
+                                            double& Py, double& T, const Particle& p,
+                                            const TrackArgs& a) {
+  if (el.place == P_KICK) {   // one kick per slice: not with the composed slices
+    if constexpr (!Y4 && (KIND == 2 || KIND == 4))
+      return pwc_element<NT, KIND, P_KICK>(el, X, Px, Y, Py, T, p, a);
+    return qident();   // rejected on the host
+  }
+  if (el.place == P_MIDPOINT)
+    return pwc_element<NT, KIND, P_MIDPOINT, Y4>(el, X, Px, Y, Py, T, p, a);
+  return thick_element<NT, KIND, false, Y4>(el, X, Px, Y, Py, T, p, a);
+}
+
+template <int NT, int KIND, bool Y4>
+__device__ __forceinline__ Quat thick_ext_y(const DevElem& el, double& X, double& Px, double& Y,
+                                         double& Py, double& T, const Particle& p,
+                                         const TrackArgs& a) {
+  if (!(el.flags & F_FRINGE)) return thick_body_ext<NT, KIND, Y4>(el, X, Px, Y, Py, T, p, a);
+  const Quat qin = fringe_kick<NT, KIND>(el, X, Y, 1.0, a);
+  const Quat Q = thick_body_ext<NT, KIND, Y4>(el, X, Px, Y, Py, T, p, a);
+  return qmul(fringe_kick<NT, KIND>(el, X, Y, -1.0, a), qmul(Q, qin));
+}
+
 template <int NT, int KIND>
 __device__ __forceinline__ Quat thick_ext(const DevElem& el, double& X, double& Px, double& Y,
                                        double& Py, double& T, const Particle& p,
                                        const TrackArgs& a) {
-  if (el.place == P_KICK) {
-    if (KIND == 2 || KIND == 4) return pwc_element<NT, KIND, P_KICK>(el, X, Px, Y, Py, T, p, a);
-    return qident();   // rejected on the host
+  if constexpr (KIND == 1 || KIND == 2 || KIND == 3) {
+    if (el.orbit == M_DKD4 || el.orbit == M_MK4)
+      return thick_ext_y<NT, KIND, true>(el, X, Px, Y, Py, T, p, a);
   }
-  if (el.place == P_MIDPOINT) return pwc_element<NT, KIND, P_MIDPOINT>(el, X, Px, Y, Py, T, p, a);
-  return thick_element<NT, KIND, false>(el, X, Px, Y, Py, T, p, a);
+  return thick_ext_y<NT, KIND, false>(el, X, Px, Y, Py, T, p, a);
 }
 
 template <int NT>
@@ -562,6 +654,10 @@ track_kernel(const TrackArgs a) {
         if (e.kind == K_SBEND) {
           if (EXT && e.orbit == M_TEAPOT) thick_orbit<4>(e, X, Px, Y, Py, T, p, a);
           else                            thick_orbit<0>(e, X, Px, Y, Py, T, p, a);
+        } else if (EXT && e.kind == K_QUAD && (e.orbit == M_DKD4 || e.orbit == M_MK4)) {
+          if (e.orbit == M_DKD4)  thick_orbit<2, true>(e, X, Px, Y, Py, T, p, a);
+          else if (e.q.k1 >= 0.0) thick_orbit<1, true>(e, X, Px, Y, Py, T, p, a);
+          else                    thick_orbit<3, true>(e, X, Px, Y, Py, T, p, a);
         } else if (e.kind == K_QUAD) {
           if (e.orbit != M_MK)    thick_orbit<2>(e, X, Px, Y, Py, T, p, a);
           else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a);
@@ -594,7 +690,7 @@ track_kernel(const TrackArgs a) {
           if (e.orbit == M_TEAPOT) q = thick_ext<NT, 4>(e, X, Px, Y, Py, T, p, a);
           else                     q = thick_ext<NT, 0>(e, X, Px, Y, Py, T, p, a);
         } else {
-          if (e.orbit != M_MK)    q = thick_ext<NT, 2>(e, X, Px, Y, Py, T, p, a);
+          if (e.orbit == M_DKD || e.orbit == M_DKD4) q = thick_ext<NT, 2>(e, X, Px, Y, Py, T, p, a);
           else if (e.q.k1 >= 0.0) q = thick_ext<NT, 1>(e, X, Px, Y, Py, T, p, a);
           else                    q = thick_ext<NT, 3>(e, X, Px, Y, Py, T, p, a);
         }

@@ -42,7 +42,7 @@ def test_struct_layouts_match_the_header():
     assert binding.st_element.L.offset == 24
     assert ctypes.sizeof(binding.st_beam) == 3 * 8 + 2 * 4
     text = open(HEADER).read()
-    assert "int32_t kind, orbit, n_slices, romberg_rows, spin_place, reserved;" in text
+    assert "int32_t kind, orbit, n_slices, romberg_rows, spin_place, fringe;" in text
     assert "double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks;" in text
     assert "double G, gamma0, aperture;" in text
     assert "int32_t precision, report_every;" in text

@@ -3,7 +3,9 @@ constant spin placements (kick, midpoint) with the CPU oracle, through the C
 ABI.  Same tolerances as the Romberg path: orbit |Δz_i| <= 1e-12 ·
 max(|z_i|, σ_i), spin components |ΔS_c| <= 1e-10."""
 
+import dataclasses
 import math
+import types
 
 import numpy as np
 import pytest
@@ -40,6 +42,19 @@ ELEMENTS = {
     "rbend_mispowered": [rbend(3.0, 0.12, 4, 2, eta=0.98)],
     "rbend_negative": [rbend(2.0, -0.1, 6, 2)],
     "rbend_midpoint": [rbend(3.0, 0.12, 5, 1, spin="midpoint")],
+    "fringe_bend_R3": [sbend(10.0, TH, 8, 3, fringe=True)],
+    "fringe_bend_teapot_kick": [sbend(10.0, TH, 8, 1, method="teapot", spin="kick", fringe=True)],
+    "fringe_quad_mk_R3": [quad(1.1, 0.08, "mk", 4, 3, fringe=True)],
+    "fringe_quad_mk_d": [quad(1.1, -0.08, "mk", 4, 2, fringe=True)],
+    "fringe_quad_dkd_midpoint": [quad(1.0, 0.05, "dkd", 4, 1, spin="midpoint", fringe=True)],
+    "dkd4_R2": [quad(1.0, 0.05, "dkd4", 4, 2)],
+    "dkd4_d": [quad(1.0, -0.05, "dkd4", 3, 1)],
+    "mk4_R3": [quad(1.1, 0.08, "mk4", 4, 3)],
+    "mk4_d": [quad(1.1, -0.08, "mk4", 6, 2)],
+    "mk4_midpoint": [quad(1.1, 0.08, "mk4", 4, 1, spin="midpoint")],
+    "dkd4_midpoint_fringe": [quad(1.0, -0.05, "dkd4", 4, 1, spin="midpoint", fringe=True)],
+    # x1 ds/2 = 1.5 m: past the series range of the MK phase (halving fallback)
+    "mk4_strong": [quad(1.1, 2.0, "mk4", 1, 1)],
 }
 
 
@@ -146,6 +161,51 @@ def test_rhic_ring_with_drift_kick_bends_one_turn():
     assert err <= 0.01 * plain
 
 
+def with_fringes(elems):
+    return [dataclasses.replace(e, fringe=True) if e.kind in ("sbend", "quad") else e
+            for e in elems]
+
+
+def test_rhic_ring_with_fringe_spin_kicks():
+    # every quadrupole and sector bend of the ring kicks the spin at both faces
+    elems = with_fringes(rhic_like_ring())
+    z, s, a = gaussian_bunch(515, 1501034517, BEAM)
+    g, o = both(elems, BEAM, z, s, a, want_q=True)
+    assert_parity(g, o, "rhic + fringe kicks")
+    assert np.abs(g["q"] - o["q"]).max() <= SPIN_TOL
+    # the kicks are exercised: the turn differs from the ring without them by
+    # far more than the tolerance
+    o0 = oracle.track(rhic_like_ring(), BEAM, z, s, a, want_quaternion=True)
+    assert np.abs(o0["q"] - o["q"]).max() > 1e3 * SPIN_TOL
+    np.testing.assert_array_equal(o0["z"], o["z"])
+
+
+def test_rhic_ring_with_fourth_order_quadrupoles():
+    elems = [dataclasses.replace(e, method="mk4") if e.kind == "quad" else e
+             for e in rhic_like_ring()]
+    z, s, a = gaussian_bunch(515, 1501034519, BEAM)
+    g, o = both(elems, BEAM, z, s, a, want_q=True, turns=1, report_every=1)
+    # Each fourth-order slice takes three MK steps (one backwards; 4.4 ds of
+    # steps in all), so the rounding budget is three times the MK ring's;
+    # the GPU must also stay far below a plain double evaluation of the maps
+    assert_parity(g, o, "rhic mk4", orbit_tol=3e-12)
+    plain, _ = orbit_rel_err(oracle.track(elems, BEAM, z, s, a, extended=False), o)
+    err, _ = orbit_rel_err(g, o)
+    print(f"rhic mk4: GPU orbit rel err {err:.3e}, plain FP64 {plain:.3e}")
+    assert err <= 0.01 * plain
+    np.testing.assert_allclose(g["pol"], o["pol"], rtol=0, atol=SPIN_TOL)
+    # a different orbit integrator: the turn differs from the mk ring
+    o2 = oracle.track(rhic_like_ring(), BEAM, z, s, a)
+    assert np.abs(o2["z"] - o["z"]).max() > 1e-12
+
+
+def test_small_ring_with_fringe_spin_kicks_over_several_turns():
+    elems = with_fringes(dk_ring(N=4))
+    z, s, a = gaussian_bunch(700, 1501034518, BEAM)
+    g, o = both(elems, BEAM, z, s, a, turns=8)
+    assert_multiturn_parity(g, o, elems, BEAM, z, s, a, 8, "dk ring + fringe kicks, 8 turns")
+
+
 def test_invalid_placements_are_rejected_before_device_work():
     from paper_1501_03450_amd import SpinTracker
     from paper_1501_03450_amd.binding import SpinTrackError
@@ -159,6 +219,17 @@ def test_invalid_placements_are_rejected_before_device_work():
         [rbend(3.0, 0.12, 4, 1, eta=0.0)],                         # rbend needs a field
         [rbend(3.0, 0.12, 4, 1, spin="kick")],                     # no kick placement
     ]
+    # fringe kicks only on sector bends and quadrupoles, flag 0 or 1
+    bad.append([types.SimpleNamespace(**{**dataclasses.asdict(drift(1.0)), "fringe": 1})])
+    bad.append([types.SimpleNamespace(**{**dataclasses.asdict(rbend(3.0, 0.12, 4, 1)),
+                                         "fringe": 1})])
+    bad.append([types.SimpleNamespace(**{**dataclasses.asdict(quad(1.0, 0.05, "mk", 4, 1)),
+                                         "fringe": 2})])
+    # fourth-order slices: quadrupoles only, and no kick placement
+    bad.append([types.SimpleNamespace(**{**dataclasses.asdict(sbend(10.0, TH, 4, 1)),
+                                         "method": "dkd4"})])
+    bad.append([types.SimpleNamespace(**{**dataclasses.asdict(quad(1.0, 0.05, "dkd", 4, 1)),
+                                         "method": "dkd4", "spin": "kick"})])
     for elems in bad:
         with pytest.raises(SpinTrackError):
             SpinTracker(elems, BEAM)
