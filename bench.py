@@ -298,9 +298,10 @@ def integrator_leg(beam, n=4096, slices=(1, 2, 4, 8, 16, 32, 64)):
     """The paper's integrator comparison (§5.2) on the small ring: one-turn
     orbit and spin errors of drift-kick (TEAPOT bends and DKD quadrupoles,
     DKS and DKDS spin placements) against bend-kick/matrix-kick orbits
-    (midpoint PWC spin, and Romberg over the slice edges), against a
-    reference of bend-kick/matrix-kick with 256 slices and 3 Romberg rows;
-    plus each method's throughput on the same ring."""
+    (midpoint PWC spin, and Romberg over the slice edges) and with
+    fourth-order matrix-kick quadrupoles, against a reference of exact bends
+    and fourth-order matrix-kick quadrupoles with 256 slices and 3 Romberg
+    rows; plus each method's throughput on the same ring."""
     import math as m
     import torch
     from paper_1501_03450_amd import SpinTracker
@@ -319,10 +320,11 @@ def integrator_leg(beam, n=4096, slices=(1, 2, 4, 8, 16, 32, 64)):
             qf = quad(1.0, 0.05, "mk", N, 1, "QF", spin="midpoint")
             qd = quad(1.0, -0.05, "mk", N, 1, "QD", spin="midpoint")
             sb = sbend(10.0, th, N, 1, spin="midpoint")
-        else:                                   # bkmk_romberg{R}
+        else:                                   # bkmk_romberg{R}, bkmk4_romberg{R}
             R = int(style[-1])
-            qf = quad(1.0, 0.05, "mk", N, R, "QF")
-            qd = quad(1.0, -0.05, "mk", N, R, "QD")
+            mq = "mk4" if style.startswith("bkmk4") else "mk"
+            qf = quad(1.0, 0.05, mq, N, R, "QF")
+            qd = quad(1.0, -0.05, mq, N, R, "QD")
             sb = sbend(10.0, th, N, R)
         cell = [qf, drift(2.0), sb, drift(2.0), qd, drift(2.0), sb, drift(2.0)]
         return cell * 16 + [snake(m.pi, 0.0)]
@@ -347,14 +349,15 @@ def integrator_leg(beam, n=4096, slices=(1, 2, 4, 8, 16, 32, 64)):
         tr.close()
         return out, ev0.elapsed_time(ev1) / 1e3
 
-    (zr, sr, ar), _ = one_turn(ring("bkmk_romberg3", 256))
+    (zr, sr, ar), _ = one_turn(ring("bkmk4_romberg3", 256))
     live = ar == 1
     sig = zr[:, live].std(axis=1)
     table = {}
-    for style in ("dk_kick", "dk_midpoint", "bkmk_midpoint", "bkmk_romberg2", "bkmk_romberg3"):
+    for style in ("dk_kick", "dk_midpoint", "bkmk_midpoint", "bkmk_romberg2", "bkmk_romberg3",
+                  "bkmk4_romberg2", "bkmk4_romberg3"):
         rows = []
         for N in slices:
-            if style.startswith("bkmk_romberg") and N < 2 ** (int(style[-1]) - 1):
+            if "_romberg" in style and N < 2 ** (int(style[-1]) - 1):
                 continue
             (zz, ss, aa), _ = one_turn(ring(style, N))
             ok = live & (aa == 1)
@@ -368,7 +371,8 @@ def integrator_leg(beam, n=4096, slices=(1, 2, 4, 8, 16, 32, 64)):
             log(f"[bench] integrators {style} N={N}: orbit {orb:.2e} spin {spin:.2e}")
         table[style] = rows
     return {"workload": f"small ring (129 elements), {n} protons, all spin directions; "
-                        "reference: bend-kick/matrix-kick, 256 slices, 3 Romberg rows",
+                        "reference: exact bends and fourth-order matrix-kick quadrupoles, "
+                        "256 slices, 3 Romberg rows",
             "one_turn": table}
 
 
