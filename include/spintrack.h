@@ -7,7 +7,9 @@
  * multipoles) fused with Thomas-BMT spin integration, where Ω at each slice
  * edge becomes a rotation quaternion, Romberg extrapolation over slice
  * refinements accelerates convergence, and quaternions compose element by
- * element.
+ * element.  The paper's comparison methods are there too: drift-kick (TEAPOT)
+ * sector bends, piece-wise constant spin placements, solenoids, rectangular
+ * bends, fringe spin kicks, and fourth-order quadrupole slices.
  *
  * Conventions shared by every entry point
  *   - Every call returns st_status.  Invalid arguments are rejected with
@@ -150,10 +152,14 @@ st_status st_create(st_ctx** out, int device);
 st_status st_destroy(st_ctx* ctx);
 
 /* Copy n elements (host memory) and the beam into the context.  Validation:
- * known kind and orbit method; finite parameters; L ≥ 0; sbends need L > 0,
- * angle ≠ 0 and eta > 0 with the exact method; quadrupoles need L > 0 and the
- * DKD or MK method; thick elements with spin need n_slices ≥ 1 and
- * romberg_rows in 1..4; gamma0 > 1; aperture > 0; report_every ≥ 0.
+ * known kind, orbit method and spin placement; finite parameters; L ≥ 0;
+ * sbends need L > 0, angle ≠ 0, the exact or TEAPOT method and, with the
+ * exact method, eta > 0; quadrupoles need L > 0 and the DKD, MK, DKD4 or MK4
+ * method; solenoids need L > 0 and ks ≠ 0; rectangular bends need L > 0,
+ * 0 < |angle| < 3 and eta ≠ 0; thick elements need n_slices ≥ 1 and
+ * romberg_rows in 1..4 (1 with a piece-wise constant placement); the kick
+ * placement needs DKD or TEAPOT slices; fringe is 0 or 1 and only on sbends
+ * and quadrupoles; gamma0 > 1; aperture > 0; report_every ≥ 0.
  * Synchronous; replaces any earlier lattice. */
 st_status st_load_lattice(st_ctx* ctx, const st_element* host_elems, int64_t n,
                           const st_beam* beam);

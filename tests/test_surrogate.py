@@ -360,3 +360,53 @@ def test_without_fallback_the_orbit_is_the_double_precision_orbit():
     rel = np.abs(zs - z64) / np.maximum(np.abs(z64), sig[:, None])
     assert rel.max() < 1e-12 * turns * 10      # bends crossed in one exact step
     np.testing.assert_allclose(np.linalg.norm(ss, axis=0), 1.0, atol=1e-6)
+
+
+def test_what_a_trained_network_gains_over_tracking_without_it():
+    # Surrogate tracking hands the spin of every particle that passes its
+    # audit to the network, so those particles skip the double-precision spin
+    # arithmetic.  A network trained on tracked one-turn quaternions keeps most
+    # of the bunch on that path at a 1e-2 audit threshold, with the
+    # polarization still following the plain tracker; the same network
+    # untrained keeps almost none.
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from paper_1501_03450_amd import surrogate as S
+    ring = rhic_like_ring()
+    widen = 3.0
+    ref = S.design_quaternion(ring, BEAM)
+    c, inv = S.feature_map(BEAM, widen)
+    z, _, _ = gaussian_bunch(1 << 17, 301, BEAM, scale=widen)
+
+    def network(trained):
+        sur = S.new_surrogate(6, 3, c, inv, ref)
+        x, t = S.label_bunch(sur, ring, BEAM, z)
+        S.set_scale(sur, S.frame_from_targets(t[:65536].cpu().numpy(), ref))
+        if trained:
+            S.train(sur, x, t, 80, 16384, 3e-3)
+        return sur
+
+    zb, sb, ab = gaussian_bunch(1 << 14, 302, BEAM)
+    turns, audit, thr = 100, 50, 1e-2
+    ref_run = SpinTracker(ring, BEAM, report_every=turns)
+    ref_run.set_particles(zb, sb, ab)
+    ref_run.track(turns)
+    p64 = ref_run.polarization().cpu().numpy()[-1, :3]
+    ref_run.close()
+    frac, perr = {}, {}
+    for trained in (True, False):
+        sur = network(trained)
+        tr = SpinTracker(ring, BEAM, report_every=turns)
+        tr.set_particles(zb, sb, ab)
+        fb = torch.zeros(zb.shape[1], dtype=torch.int32, device="cuda")
+        S.track(sur, tr, turns, audit, thr, fb)
+        torch.cuda.synchronize()
+        frac[trained] = float((fb.cpu().numpy() != 0).mean())
+        perr[trained] = float(np.abs(tr.polarization().cpu().numpy()[-1, :3] - p64).max())
+        tr.close()
+        sur.close()
+    print(f"fallback fraction: trained {frac[True]:.3f}, untrained {frac[False]:.3f}; "
+          f"polarization error trained {perr[True]:.2e}")
+    assert frac[True] < 0.5
+    assert frac[False] > 0.95
+    assert perr[True] < 1e-2
