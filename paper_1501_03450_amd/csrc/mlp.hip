@@ -381,17 +381,34 @@ __global__ void __launch_bounds__(NT) mlp_weight_grad_kernel(const MlpArgs a) {
         out[(size_t)(n0 + i * 16 + rq + e) * W + k0 + j * 16 + c] = acc[i][j][e];
 }
 
-// Partial sums part[r][i] (r < parts, i < len) reduced over r in a fixed
-// order, 64 parts per workgroup row: out[blockIdx.y][i] = Σ_{r in chunk} part[r][i].
-// A workgroup covers C columns (C = 64, or fewer for short rows) with 256/C
-// threads per column; every thread sums a strided subset of the chunk and
-// the subsets are combined in LDS in thread order.
-__global__ void __launch_bounds__(256) sum_partials_kernel(const float* part, int64_t len, int parts,
-                                                           int C, float* out) {
+// Column sums of row-major partials [rows][len], 64 rows per workgroup and
+// pass: a workgroup covers C columns (C = 64, or fewer for short rows) with
+// 256/C threads per column; every thread sums a strided subset of the rows
+// and the subsets are combined in LDS in thread order, so the result does not
+// depend on scheduling.  Several independent sums share a launch: the blocks
+// of segment k are numbered from first[k].
+struct SumPass {
+  int nseg;
+  struct {
+    const float* src;
+    float* dst;
+    int64_t len, first;
+    int rows, C, gx;
+  } seg[kMaxSumSegments];
+};
+
+__global__ void __launch_bounds__(256) sum_partials_multi_kernel(const SumPass p) {
   __shared__ float acc[256];
+  int k = 0;
+  while (k + 1 < p.nseg && (int64_t)blockIdx.x >= p.seg[k + 1].first) ++k;
+  const int64_t b = (int64_t)blockIdx.x - p.seg[k].first;
+  const int C = p.seg[k].C, gx = p.seg[k].gx, rows = p.seg[k].rows;
+  const int64_t len = p.seg[k].len;
+  const int64_t bx = b % gx, by = b / gx;
   const int t = threadIdx.x, c = t % C, g = t / C, G = 256 / C;
-  const int64_t i = (int64_t)blockIdx.x * C + c;
-  const int r0 = blockIdx.y * 64, r1 = min(parts, r0 + 64);
+  const int64_t i = bx * C + c;
+  const int r0 = (int)by * 64, r1 = min(rows, r0 + 64);
+  const float* part = p.seg[k].src;
   float s = 0.0f;
   if (i < len)
 #pragma unroll 4
@@ -400,8 +417,8 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(const float* part, in
   __syncthreads();
   if (g == 0 && i < len) {
     float v = 0.0f;
-    for (int k = 0; k < G; ++k) v += acc[k * C + c];
-    out[(size_t)blockIdx.y * len + i] = v;
+    for (int q = 0; q < G; ++q) v += acc[q * C + c];
+    p.seg[k].dst[(size_t)by * len + i] = v;
   }
 }
 
@@ -458,32 +475,57 @@ hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Reduce in passes of 64 parts per row until at most 64 rows are left, then
-// once more into out.  tmp: 2 · len · ceil(parts/64) floats (two halves used
-// alternately), needed only when parts > 64.
-hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, float* tmp,
-                               hipStream_t s) {
-  if (len <= 0) return hipSuccess;
-  int C = 64;
-  while (C > 1 && C / 2 >= len) C /= 2;
-  const dim3 block(256);
-  const unsigned gx = (unsigned)((len + C - 1) / C);
-  const size_t half = (size_t)len * (size_t)((parts + 63) / 64);
-  const float* src = part;
-  int rows = parts, k = 0;
-  while (rows > 64) {
-    float* dst = tmp + (k & 1) * half;
-    const int next = (rows + 63) / 64;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(gx, (unsigned)next), block, 0, s, src, len, rows, C,
-                       dst);
+size_t sum_partials_tmp(int64_t len, int parts) {
+  return parts > 64 ? 2 * (size_t)len * (size_t)((parts + 63) / 64) : 0;
+}
+
+hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tmp, hipStream_t s) {
+  if (nseg < 0 || nseg > kMaxSumSegments) return hipErrorInvalidValue;
+  struct State { const float* src; int rows; float* tmp; size_t half; int C; int gx; bool done; };
+  State st[kMaxSumSegments];
+  size_t off = 0;
+  for (int k = 0; k < nseg; ++k) {
+    const SumSegment& g = segs[k];
+    int C = 64;
+    while (C > 1 && C / 2 >= g.len) C /= 2;
+    st[k] = {g.part, g.parts, tmp + off, sum_partials_tmp(g.len, g.parts) / 2, C,
+             (int)((g.len + C - 1) / C), g.len <= 0};
+    off += sum_partials_tmp(g.len, g.parts);
+  }
+  for (int pass = 0;; ++pass) {
+    SumPass p;
+    p.nseg = 0;
+    int64_t blocks = 0;
+    int idx[kMaxSumSegments];
+    for (int k = 0; k < nseg; ++k) {
+      if (st[k].done) continue;
+      const bool last = st[k].rows <= 64;
+      const int next = last ? 1 : (st[k].rows + 63) / 64;
+      auto& q = p.seg[p.nseg];
+      q.src = st[k].src;
+      q.dst = last ? segs[k].out : st[k].tmp + (pass & 1) * st[k].half;
+      q.len = segs[k].len;
+      q.first = blocks;
+      q.rows = st[k].rows;
+      q.C = st[k].C;
+      q.gx = st[k].gx;
+      idx[p.nseg++] = k;
+      blocks += (int64_t)st[k].gx * next;
+    }
+    if (p.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(sum_partials_multi_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    src = dst;
-    rows = next;
-    ++k;
+    for (int j = 0; j < p.nseg; ++j) {
+      State& x = st[idx[j]];
+      if (x.rows <= 64) {
+        x.done = true;
+      } else {
+        x.src = p.seg[j].dst;
+        x.rows = (x.rows + 63) / 64;
+      }
+    }
   }
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(gx, 1u), block, 0, s, src, len, rows, C, out);
-  return hipGetLastError();
 }
 
 hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s) {

@@ -92,9 +92,15 @@ st_status ensure_scratch(st_mlp* m, int64_t ld) {
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->dzT[l], (size_t)(W * ld));
   if (e == hipSuccess) e = alloc(m, &m->dy, (size_t)(ld * 4));
   if (e == hipSuccess) e = alloc(m, &m->loss_part, (size_t)nb);
-  // two-pass reduction buffer for the per-workgroup partials (largest row: W1)
-  if (e == hipSuccess)
-    e = alloc(m, &m->red_tmp, (size_t)(2 * W * std::max(m->n_in, 4) * ((nb + 63) / 64)));
+  // multi-pass reduction buffers of the per-workgroup partials, one double
+  // buffer per tensor (all reduced together)
+  if (e == hipSuccess) {
+    const int P = (int)nb;
+    const size_t need = st::sum_partials_tmp(W * m->n_in, P) + 3 * st::sum_partials_tmp(W, P) +
+                        st::sum_partials_tmp(4 * W, P) + st::sum_partials_tmp(4, P) +
+                        st::sum_partials_tmp(1, P) + 2 * st::sum_partials_tmp(W * W, kSplits);
+    e = alloc(m, &m->red_tmp, std::max<size_t>(need, 1));
+  }
   if (e == hipSuccess) e = alloc(m, &m->gW1, (size_t)(nb * W * m->n_in));
   if (e == hipSuccess) e = alloc(m, &m->gb1, (size_t)(nb * W));
   if (e == hipSuccess) e = alloc(m, &m->gb2, (size_t)(nb * W));
@@ -163,16 +169,16 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
   if ((e = st::launch_mlp_forward(a, true, s)) != hipSuccess) return hip_fail(m, e, "forward");
   if ((e = st::launch_mlp_backward(a, s)) != hipSuccess) return hip_fail(m, e, "backward");
   const st::MlpOffsets& o = m->off;
-  struct { const float* part; int64_t len; int parts; int64_t off; } red[] = {
-      {m->gW1, W * m->n_in, nb, o.W1}, {m->gb1, W, nb, o.b1}, {m->gW2, W * W, kSplits, o.W2},
-      {m->gb2, W, nb, o.b2}, {m->gW3, W * W, kSplits, o.W3}, {m->gb3, W, nb, o.b3},
-      {m->gW4, 4 * W, nb, o.W4}, {m->gb4, 4, nb, o.b4}};
-  for (auto& r : red)
-    if ((e = st::launch_sum_partials(r.part, r.len, r.parts, m->grad + r.off, m->red_tmp, s)) !=
-        hipSuccess)
-      return hip_fail(m, e, "gradient reduction");
-  if (d_loss && (e = st::launch_sum_partials(m->loss_part, 1, nb, d_loss, m->red_tmp, s)) != hipSuccess)
-    return hip_fail(m, e, "loss reduction");
+  // every tensor's partials (and the loss) reduced together, one launch per pass
+  st::SumSegment red[] = {
+      {m->gW1, W * m->n_in, nb, m->grad + o.W1}, {m->gb1, W, nb, m->grad + o.b1},
+      {m->gW2, W * W, kSplits, m->grad + o.W2},  {m->gb2, W, nb, m->grad + o.b2},
+      {m->gW3, W * W, kSplits, m->grad + o.W3},  {m->gb3, W, nb, m->grad + o.b3},
+      {m->gW4, 4 * W, nb, m->grad + o.W4},       {m->gb4, 4, nb, m->grad + o.b4},
+      {m->loss_part, 1, nb, d_loss}};
+  const int nseg = d_loss ? 9 : 8;
+  if ((e = st::launch_sum_partials_multi(red, nseg, m->red_tmp, s)) != hipSuccess)
+    return hip_fail(m, e, "gradient reduction");
   return ST_OK;
 }
 

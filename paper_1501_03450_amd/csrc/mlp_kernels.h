@@ -88,8 +88,19 @@ hipError_t launch_features(const double* z, int64_t n, const FeatureMap& f, int 
 hipError_t launch_targets(const double* q, int64_t n, const double* ref, float* t, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s);
 hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s);
-hipError_t launch_sum_partials(const float* part, int64_t len, int parts, float* out, float* tmp,
-                               hipStream_t s);
+// Several independent column sums of row-major partials part[parts][len] into
+// out[len], reduced 64 rows per pass until one row is left; the segments
+// share one launch per pass.  tmp: the sum over segments of
+// sum_partials_tmp(len, parts) floats (a double buffer per segment).
+struct SumSegment {
+  const float* part;
+  int64_t len;
+  int parts;
+  float* out;
+};
+constexpr int kMaxSumSegments = 12;
+size_t sum_partials_tmp(int64_t len, int parts);
+hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tmp, hipStream_t s);
 hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s);
 hipError_t launch_refresh_bf16(const MlpArgs& a, hipStream_t s);
 
