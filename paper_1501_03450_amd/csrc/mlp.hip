@@ -259,20 +259,31 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
     const float w0 = P[a.off.W4 + 0 * W + k], w1 = P[a.off.W4 + 1 * W + k];
     const float w2 = P[a.off.W4 + 2 * W + k], w3 = P[a.off.W4 + 3 * W + k];
     float gw[4] = {0.f, 0.f, 0.f, 0.f}, gb = 0.0f;
-    for (int m = 0; m < TM; ++m) {
-      float dz = 0.0f;
-      if (m < rows) {
-        const float z = a.zS3[(size_t)(b0 + m) * W + k];
-        const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
-        dz = dh * dsilu(z);
-        const float h = silu(z);
-        gw[0] = fmaf(dys[m][0], h, gw[0]);
-        gw[1] = fmaf(dys[m][1], h, gw[1]);
-        gw[2] = fmaf(dys[m][2], h, gw[2]);
-        gw[3] = fmaf(dys[m][3], h, gw[3]);
-        gb += dz;
+    // the pre-activations of 16 samples are loaded together, so that one
+    // memory latency covers them (the sums still run in sample order)
+    constexpr int kChunk = 16;
+    for (int m0 = 0; m0 < TM; m0 += kChunk) {
+      float zv[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u)
+        zv[u] = m0 + u < rows ? a.zS3[(size_t)(b0 + m0 + u) * W + k] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        const int m = m0 + u;
+        float dz = 0.0f;
+        if (m < rows) {
+          const float z = zv[u];
+          const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
+          dz = dh * dsilu(z);
+          const float h = silu(z);
+          gw[0] = fmaf(dys[m][0], h, gw[0]);
+          gw[1] = fmaf(dys[m][1], h, gw[1]);
+          gw[2] = fmaf(dys[m][2], h, gw[2]);
+          gw[3] = fmaf(dys[m][3], h, gw[3]);
+          gb += dz;
+        }
+        bufA[m * LDA + k] = (__bf16)dz;
       }
-      bufA[m * LDA + k] = (__bf16)dz;
     }
     for (int j = 0; j < 4; ++j) a.gpart_W4[((size_t)blk * 4 + j) * W + k] = gw[j];
     a.gpart_b3[(size_t)blk * W + k] = gb;
@@ -341,12 +352,18 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
   }
 }
 
-// dW[n][k] = Σ_b dzT[n][b] hT[k][b] for a 64×64 tile and one batch chunk.
-// blockIdx.x: tile (16 per matrix), blockIdx.y: matrix (0: W2, 1: W3),
-// blockIdx.z: batch split.
+// Weight gradients of the two 256×256 layers: gW[n][k] = Σ_b dzT[n][b] hT[k][b]
+// over one split (a contiguous range of samples) per workgroup group, each
+// workgroup a 64×64 tile of it, each wave a 32×32 quarter.  The 16 tiles of a
+// (layer, split) group read the same 1 MB of operands, so the launch keeps a
+// group on one XCD (workgroups are dealt to the 8 XCDs in turn) where those
+// reads share the XCD's L2.  Four 32-sample steps of operands are loaded
+// before their MFMAs, so one memory latency covers sixteen of them.
 __global__ void __launch_bounds__(NT) mlp_weight_grad_kernel(const MlpArgs a) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int tile = blockIdx.x, which = blockIdx.y, split = blockIdx.z;
+  const int id = blockIdx.x, xcd = id % 8, slot = id / 8;
+  const int group = xcd + 8 * (slot / 16), tile = slot % 16;
+  const int which = group & 1, split = group >> 1;
   const __bf16* dzT = which == 0 ? a.dzT2 : a.dzT3;
   const __bf16* hT = which == 0 ? a.hT1 : a.hT2;
   float* out = (which == 0 ? a.gpart_W2 : a.gpart_W3) + (size_t)split * W * W;
@@ -355,15 +372,36 @@ __global__ void __launch_bounds__(NT) mlp_weight_grad_kernel(const MlpArgs a) {
   const int64_t chunk = a.split_chunk;
   const int64_t bs = (int64_t)split * chunk, be = min(ld, bs + chunk);
   const int r = lane & 15, kb = 8 * (lane >> 4);
+  const __bf16* pa[2] = {dzT + (size_t)(n0 + r) * ld + kb, dzT + (size_t)(n0 + 16 + r) * ld + kb};
+  const __bf16* pb[2] = {hT + (size_t)(k0 + r) * ld + kb, hT + (size_t)(k0 + 16 + r) * ld + kb};
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t b = bs; b < be; b += 32) {
+  constexpr int kSteps = 4;
+  int64_t b = bs;
+  for (; b + 32 * kSteps <= be; b += 32 * kSteps) {
+    bf16x8 av[kSteps][2], bv[kSteps][2];
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[u][i] = *reinterpret_cast<const bf16x8*>(pa[i] + b + 32 * u);
+        bv[u][i] = *reinterpret_cast<const bf16x8*>(pb[i] + b + 32 * u);
+      }
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
+  }
+  for (; b < be; b += 32) {
     bf16x8 av[2], bv[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      av[i] = *reinterpret_cast<const bf16x8*>(dzT + (size_t)(n0 + i * 16 + r) * ld + b + kb);
-      bv[i] = *reinterpret_cast<const bf16x8*>(hT + (size_t)(k0 + i * 16 + r) * ld + b + kb);
+      av[i] = *reinterpret_cast<const bf16x8*>(pa[i] + b);
+      bv[i] = *reinterpret_cast<const bf16x8*>(pb[i] + b);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -471,7 +509,10 @@ hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(mlp_backward_data_kernel, dim3(nb), dim3(NT), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(16, 2, (unsigned)a.n_splits), dim3(NT), 0, s, a);
+  // 16 tiles × 2 layers × n_splits splits; the kernel maps the linear block
+  // index to (group, tile) so that each group stays on one XCD
+  if (a.n_splits % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(16u * 2u * (unsigned)a.n_splits), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
