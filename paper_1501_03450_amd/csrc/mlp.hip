@@ -353,70 +353,89 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
 }
 
 // Weight gradients of the two 256×256 layers: gW[n][k] = Σ_b dzT[n][b] hT[k][b]
-// over one split (a contiguous range of samples) per workgroup group, each
-// workgroup a 64×64 tile of it, each wave a 32×32 quarter.  The 16 tiles of a
-// (layer, split) group read the same 1 MB of operands, so the launch keeps a
-// group on one XCD (workgroups are dealt to the 8 XCDs in turn) where those
-// reads share the XCD's L2.  Four 32-sample steps of operands are loaded
-// before their MFMAs, so one memory latency covers sixteen of them.
+// over one split (a contiguous range of samples).  A workgroup computes a
+// 128×128 tile of one split, each wave a 64×64 quarter of it; every 32-sample
+// step stages the tile's 128 rows of both operands in LDS (double-buffered,
+// rows padded to 40 elements so that the fragment reads hit distinct banks),
+// and the next step's global loads are in flight during the current step's
+// sixteen MFMAs.  The four tiles of a (layer, split) group read the same
+// operands, so the launch keeps a group on one XCD (workgroups are dealt to
+// the 8 XCDs in turn), where they share the XCD's L2.
+constexpr int kWgTile = 128, kWgRow = 40;
 __global__ void __launch_bounds__(NT) mlp_weight_grad_kernel(const MlpArgs a) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ __align__(16) __bf16 As[2][kWgTile * kWgRow];
+  __shared__ __align__(16) __bf16 Bs[2][kWgTile * kWgRow];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int id = blockIdx.x, xcd = id % 8, slot = id / 8;
-  const int group = xcd + 8 * (slot / 16), tile = slot % 16;
+  const int group = xcd + 8 * (slot / 4), tile = slot % 4;
   const int which = group & 1, split = group >> 1;
   const __bf16* dzT = which == 0 ? a.dzT2 : a.dzT3;
   const __bf16* hT = which == 0 ? a.hT1 : a.hT2;
   float* out = (which == 0 ? a.gpart_W2 : a.gpart_W3) + (size_t)split * W * W;
-  const int n0 = (tile / 4) * 64 + (wv >> 1) * 32, k0 = (tile % 4) * 64 + (wv & 1) * 32;
+  const int n0 = (tile >> 1) * kWgTile, k0 = (tile & 1) * kWgTile;
+  const int wn = (wv >> 1) * 64, wk = (wv & 1) * 64;
   const int64_t ld = a.ld;
-  const int64_t chunk = a.split_chunk;
-  const int64_t bs = (int64_t)split * chunk, be = min(ld, bs + chunk);
-  const int r = lane & 15, kb = 8 * (lane >> 4);
-  const __bf16* pa[2] = {dzT + (size_t)(n0 + r) * ld + kb, dzT + (size_t)(n0 + 16 + r) * ld + kb};
-  const __bf16* pb[2] = {hT + (size_t)(k0 + r) * ld + kb, hT + (size_t)(k0 + 16 + r) * ld + kb};
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  constexpr int kSteps = 4;
-  int64_t b = bs;
-  for (; b + 32 * kSteps <= be; b += 32 * kSteps) {
-    bf16x8 av[kSteps][2], bv[kSteps][2];
-#pragma unroll
-    for (int u = 0; u < kSteps; ++u)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        av[u][i] = *reinterpret_cast<const bf16x8*>(pa[i] + b + 32 * u);
-        bv[u][i] = *reinterpret_cast<const bf16x8*>(pb[i] + b + 32 * u);
-      }
-#pragma unroll
-    for (int u = 0; u < kSteps; ++u)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
+  const int64_t bs = (int64_t)split * a.split_chunk, be = min(ld, bs + a.split_chunk);
+  const int nsteps = be > bs ? (int)((be - bs) / 32) : 0;
+  // staging: thread t moves 16 bytes of rows t/4 and 64 + t/4, chunk t%4
+  const int sr = tid >> 2, sc = (tid & 3) * 8;
+  const __bf16* ga0 = dzT + (size_t)(n0 + sr) * ld + bs + sc;
+  const __bf16* ga1 = dzT + (size_t)(n0 + 64 + sr) * ld + bs + sc;
+  const __bf16* gb0 = hT + (size_t)(k0 + sr) * ld + bs + sc;
+  const __bf16* gb1 = hT + (size_t)(k0 + 64 + sr) * ld + bs + sc;
+  const int so0 = sr * kWgRow + sc, so1 = (64 + sr) * kWgRow + sc;
+  const int r = lane & 15, kq = 8 * (lane >> 4);
+  f32x4 acc[4][4];
+  zero_acc(acc);
+  bf16x8 xa0, xa1, xb0, xb1;
+  if (nsteps > 0) {
+    xa0 = *reinterpret_cast<const bf16x8*>(ga0);
+    xa1 = *reinterpret_cast<const bf16x8*>(ga1);
+    xb0 = *reinterpret_cast<const bf16x8*>(gb0);
+    xb1 = *reinterpret_cast<const bf16x8*>(gb1);
+    *reinterpret_cast<bf16x8*>(&As[0][so0]) = xa0;
+    *reinterpret_cast<bf16x8*>(&As[0][so1]) = xa1;
+    *reinterpret_cast<bf16x8*>(&Bs[0][so0]) = xb0;
+    *reinterpret_cast<bf16x8*>(&Bs[0][so1]) = xb1;
   }
-  for (; b < be; b += 32) {
-    bf16x8 av[2], bv[2];
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const int cur = st & 1;
+    const bool more = st + 1 < nsteps;
+    if (more) {
+      const int64_t off = (int64_t)(st + 1) * 32;
+      xa0 = *reinterpret_cast<const bf16x8*>(ga0 + off);
+      xa1 = *reinterpret_cast<const bf16x8*>(ga1 + off);
+      xb0 = *reinterpret_cast<const bf16x8*>(gb0 + off);
+      xb1 = *reinterpret_cast<const bf16x8*>(gb1 + off);
+    }
+    bf16x8 av[4], bv[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      av[i] = *reinterpret_cast<const bf16x8*>(pa[i] + b);
-      bv[i] = *reinterpret_cast<const bf16x8*>(pb[i] + b);
+    for (int i = 0; i < 4; ++i) {
+      av[i] = *reinterpret_cast<const bf16x8*>(&As[cur][(wn + i * 16 + r) * kWgRow + kq]);
+      bv[i] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wk + i * 16 + r) * kWgRow + kq]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      *reinterpret_cast<bf16x8*>(&As[cur ^ 1][so0]) = xa0;
+      *reinterpret_cast<bf16x8*>(&As[cur ^ 1][so1]) = xa1;
+      *reinterpret_cast<bf16x8*>(&Bs[cur ^ 1][so0]) = xb0;
+      *reinterpret_cast<bf16x8*>(&Bs[cur ^ 1][so1]) = xb1;
+    }
+    __syncthreads();
   }
   const int c = lane & 15, rq = 4 * (lane >> 4);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        out[(size_t)(n0 + i * 16 + rq + e) * W + k0 + j * 16 + c] = acc[i][j][e];
+        out[(size_t)(n0 + wn + i * 16 + rq + e) * W + k0 + wk + j * 16 + c] = acc[i][j][e];
 }
 
 // Column sums of row-major partials [rows][len], 64 rows per workgroup and
@@ -509,10 +528,10 @@ hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(mlp_backward_data_kernel, dim3(nb), dim3(NT), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // 16 tiles × 2 layers × n_splits splits; the kernel maps the linear block
+  // 4 tiles × 2 layers × n_splits splits; the kernel maps the linear block
   // index to (group, tile) so that each group stays on one XCD
   if (a.n_splits % 4 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(16u * 2u * (unsigned)a.n_splits), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(4u * 2u * (unsigned)a.n_splits), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
