@@ -129,10 +129,12 @@ __device__ __forceinline__ void store_feature_major(const __bf16* lds, __bf16* o
   }
 }
 
+// One activation buffer per workgroup (34 KB of LDS, so four workgroups fit
+// on a CU): each layer's GEMM reads it, a barrier, then the epilogue
+// overwrites it with the layer's output.
 template <bool TRAIN>
 __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
   __shared__ __align__(16) __bf16 bufA[TM * LDA];
-  __shared__ __align__(16) __bf16 bufB[TM * LDA];
   __shared__ float xs[TM][kMlpMaxIn];
   __shared__ float ys[TM][4];
   __shared__ float red[NT / 64];
@@ -170,12 +172,14 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
   // layer 2 (MFMA)
   zero_acc(acc);
   gemm_64x64(bufA, a.W2b, wv * 64, acc, lane);
-  hidden_epilogue<TRAIN>(acc, P + a.off.b2, bufB, a.zS2, b0, rows, wv * 64, lane);
   __syncthreads();
-  if (TRAIN) store_feature_major(bufB, a.hT2, a.ld, b0, tid);
+  hidden_epilogue<TRAIN>(acc, P + a.off.b2, bufA, a.zS2, b0, rows, wv * 64, lane);
+  __syncthreads();
+  if (TRAIN) store_feature_major(bufA, a.hT2, a.ld, b0, tid);
   // layer 3 (MFMA)
   zero_acc(acc);
-  gemm_64x64(bufB, a.W3b, wv * 64, acc, lane);
+  gemm_64x64(bufA, a.W3b, wv * 64, acc, lane);
+  __syncthreads();
   hidden_epilogue<TRAIN>(acc, P + a.off.b3, bufA, a.zS3, b0, rows, wv * 64, lane);
   __syncthreads();
 
@@ -227,8 +231,7 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
 
 // Backward through the layers for one tile of samples.
 __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) {
-  __shared__ __align__(16) __bf16 bufA[TM * LDA];
-  __shared__ __align__(16) __bf16 bufB[TM * LDA];
+  __shared__ __align__(16) __bf16 bufA[TM * LDA];   // one buffer, as in the forward pass
   __shared__ float xs[TM][kMlpMaxIn];
   __shared__ float dys[TM][4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -296,6 +299,7 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
   // dz2 = (dz3 W3) ⊙ silu'(z2)
   zero_acc(acc);
   gemm_64x64(bufA, a.W3Tb, wv * 64, acc, lane);
+  __syncthreads();   // bufA is overwritten below
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     const int n = wv * 64 + nt * 16 + c;
@@ -306,20 +310,20 @@ __global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) 
       for (int i = 0; i < 4; ++i) {
         float dz = 0.0f;
         if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zS2[(size_t)(b0 + m0 + i) * W + n]);
-        bufB[(m0 + i) * LDA + n] = (__bf16)dz;
+        bufA[(m0 + i) * LDA + n] = (__bf16)dz;
       }
     }
   }
   __syncthreads();
-  store_feature_major(bufB, a.dzT2, a.ld, b0, tid);
+  store_feature_major(bufA, a.dzT2, a.ld, b0, tid);
   {
     float s = 0.0f;
-    for (int m = 0; m < rows; ++m) s += (float)bufB[m * LDA + tid];
+    for (int m = 0; m < rows; ++m) s += (float)bufA[m * LDA + tid];
     a.gpart_b2[(size_t)blk * W + tid] = s;
   }
   // dz1 = (dz2 W2) ⊙ silu'(z1)
   zero_acc(acc);
-  gemm_64x64(bufB, a.W2Tb, wv * 64, acc, lane);
+  gemm_64x64(bufA, a.W2Tb, wv * 64, acc, lane);
   __syncthreads();   // bufA is reused below
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
