@@ -475,6 +475,13 @@ def main():
             "traffic": recorded_traffic(n, T),
         },
     }
+    # the rates reported next to the headline: element passes, and the HBM
+    # rate of the recorded per-launch traffic over the measured launch time
+    traffic = out["roofline"]["traffic"]
+    out["rates"] = {
+        "particle_element_passes_per_s": rate * summ["n_elements"],
+        "hbm_GB_per_s": (traffic / (np.mean(step_ms) / 1e3) / 1e9) if traffic else None,
+    }
     if not args.no_mixed:
         out["mixed"] = mixed_leg(ring, beam, args.mixed_particles, args.mixed_turns, stream)
     if not args.no_surrogate:
