@@ -770,7 +770,7 @@ __global__ void __launch_bounds__(256) reduce_polarization_kernel(const double* 
   for (int c = 0; c < 4; ++c) acc[threadIdx.x][c] = s[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
+    if ((int)threadIdx.x < w)
       for (int c = 0; c < 4; ++c) acc[threadIdx.x][c] += acc[threadIdx.x + w][c];
     __syncthreads();
   }
