@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--scan-turns", type=int, default=100)
     ap.add_argument("--audit-every", type=int, default=50)
     ap.add_argument("--threshold", type=float, default=1e-6)
+    ap.add_argument("--scan-thresholds", type=str, default=None,
+                    help="comma-separated audit thresholds of the surrogate scans "
+                         "(default: --threshold, 1e-4 and 1e-2)")
     ap.add_argument("--band-train-per-energy", type=int, default=65536)
     ap.add_argument("--band-epochs", type=int, default=60)
     ap.add_argument("--c3", action="store_true",
@@ -248,7 +251,7 @@ def c3_leg(ring, beam, n_samples, epochs, batch, lr):
 
 
 def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_energy, epochs,
-             lr, n_bands):
+             lr, n_bands, thresholds=None):
     """Energy scan with surrogate + fallback against plain double precision on
     the same bunches, plus the fallback fraction at looser thresholds."""
     from paper_1501_03450_amd import surrogate as S
@@ -269,7 +272,7 @@ def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_e
     t_train = time.perf_counter() - t0
     f = S.energy_scan(ring, bunches, turns, None, log=lambda m: log(f"[bench] fp64 scan {m}"))
     res = {}
-    for thr in sorted({threshold, 1e-4, 1e-2}):
+    for thr in sorted(thresholds if thresholds else {threshold, 1e-4, 1e-2}):
         r = S.energy_scan(ring, bunches, turns, per, audit_every, thr,
                           log=lambda m: log(f"[bench] surrogate scan (threshold {thr:g}) {m}"))
         dp = np.abs(r["polarization"][:, :3] - f["polarization"][:, :3]).max()
@@ -482,18 +485,21 @@ def main():
         "particle_element_passes_per_s": rate * summ["n_elements"],
         "hbm_GB_per_s": (traffic / (np.mean(step_ms) / 1e3) / 1e9) if traffic else None,
     }
+    thresholds = ({float(v) for v in args.scan_thresholds.split(",")}
+                  if args.scan_thresholds else None)
     if not args.no_mixed:
         out["mixed"] = mixed_leg(ring, beam, args.mixed_particles, args.mixed_turns, stream)
     if not args.no_surrogate:
         out["surrogate"] = scan_leg(ring, args.band_energies, args.scan_particles, args.scan_turns,
                                     args.audit_every, args.threshold, args.band_train_per_energy,
-                                    args.band_epochs, args.lr, 1)
+                                    args.band_epochs, args.lr, 1, thresholds)
     if args.c3:
         out["c3_training"] = c3_leg(ring, beam, args.c3_samples, args.c3_epochs, 65536, args.lr)
     if args.c4:
         out["c4_scan"] = scan_leg(ring, args.c4_energies, args.scan_particles, args.scan_turns,
                                   args.audit_every, args.threshold, args.band_train_per_energy,
-                                  args.band_epochs, args.lr, max(1, args.c4_energies // 16))
+                                  args.band_epochs, args.lr, max(1, args.c4_energies // 16),
+                                  thresholds)
     if args.compare_integrators:
         out["integrators"] = integrator_leg(beam)
     if not args.no_cpu_baseline:
