@@ -267,9 +267,11 @@ st_status st_mlp_targets(st_mlp* m, const double* d_q, int64_t n, const double* 
  * Each turn a particle with d_fallback[j] == 0 gets the orbit push and a spin
  * rotation by the network's quaternion for its turn-start coordinates
  * (inputs as in st_mlp_features); a particle with d_fallback[j] != 0 gets the
- * full double-precision turn.  Every audit_every-th turn (>= 1) every particle
- * gets the full double-precision turn and its network quaternion is compared
- * with the tracked one.  When the largest component difference (after
+ * full double-precision turn.  On the first turn of the call and on every
+ * audit_every-th turn (>= 1) every particle gets the full double-precision
+ * turn and its network quaternion is compared with the tracked one (the early
+ * audit finds the particles the network cannot follow before they cost a
+ * long replay).  When the largest component difference (after
  * aligning the sign) exceeds `threshold`, the particle falls back: d_fallback[j]
  * is set to the turn number (1-based), its state is rolled back to the
  * previous audit (or the start) and the turns since then are replayed in

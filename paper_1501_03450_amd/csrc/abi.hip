@@ -634,7 +634,9 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
     st_status ms = st_mlp_features(m, c->z, n, center, inv_scale, extra, c->d_feat, stream);
     if (ms == ST_OK) ms = st_mlp_infer(m, c->d_feat, c->d_qnn, n, stream);
     if (ms != ST_OK) return fail(c, ms, std::string("network: ") + st_mlp_last_error(m));
-    const bool audit = t % audit_every == 0;
+    // audits: after the first turn, so that particles the network cannot
+    // follow are found before a long replay, then every audit_every-th turn
+    const bool audit = t % audit_every == 0 || t == 1;
     st::TrackArgs a = track_args(c);
     a.turns = 1;
     if (audit) {

@@ -299,27 +299,28 @@ def test_auditing_every_turn_is_exactly_the_double_precision_tracker():
 
 
 def test_threshold_zero_sends_every_particle_to_the_fallback_at_the_first_audit():
+    # the first audit comes after the first turn
     z, s, a = gaussian_bunch(700, 202, BEAM)
     (zs, ss, as_), fb = _surrogate_run(rhic_like_ring(), z, s, a, 5, 3, 0.0)
-    assert (fb[as_ == 1] == 3).all()
+    assert (fb[as_ == 1] == 1).all()
 
 
 def test_a_particle_that_fails_its_audit_is_replayed_in_double_precision():
-    # threshold 0 and one audit at the last turn: every particle is rolled back
-    # to the start and replayed in one double-precision launch, so the result
-    # is the plain tracker's bit for bit
+    # threshold 0 over one turn: every particle fails the audit after it, is
+    # rolled back to the start and replayed in one double-precision launch,
+    # so the result is the plain tracker's bit for bit
     z, s, a = gaussian_bunch(700, 204, BEAM)
-    (zs, ss, as_), fb = _surrogate_run(small_ring(), z, s, a, 4, 4, 0.0)
-    z64, s64, a64 = _fp64_run(small_ring(), z, s, a, 4)
-    assert (fb == 4).all()
+    (zs, ss, as_), fb = _surrogate_run(small_ring(), z, s, a, 1, 4, 0.0)
+    z64, s64, a64 = _fp64_run(small_ring(), z, s, a, 1)
+    assert (fb == 1).all()
     np.testing.assert_array_equal(zs, z64)
     np.testing.assert_array_equal(ss, s64)
     np.testing.assert_array_equal(as_, a64)
 
 
 def test_after_a_rollback_the_spin_stays_the_double_precision_spin():
-    # threshold 0, audits at turns 3 and 6 of 7: rollback and replay at turn
-    # 3, full double-precision turns afterwards
+    # threshold 0, audits at turns 1, 3 and 6 of 7: rollback and replay at
+    # turn 1, double-precision turns on the fallback path afterwards
     z, s, a = gaussian_bunch(700, 205, BEAM)
     (zs, ss, as_), fb = _surrogate_run(rhic_like_ring(), z, s, a, 7, 3, 0.0)
     z64, s64, a64 = _fp64_run(rhic_like_ring(), z, s, a, 7)
