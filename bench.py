@@ -30,6 +30,16 @@ import time
 
 import numpy as np
 
+# The surrogate scans run many small bunches at once, each on its own stream;
+# HIP maps streams onto at most GPU_MAX_HW_QUEUES hardware queues (4 by
+# default), so raise that to 16 before the runtime starts.
+try:
+    _queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _queues = 4
+if _queues < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -100,6 +110,10 @@ def parse():
     ap.add_argument("--scan-turns", type=int, default=100)
     ap.add_argument("--audit-every", type=int, default=50)
     ap.add_argument("--threshold", type=float, default=1e-6)
+    ap.add_argument("--scan-streams", type=int, default=4,
+                    help="streams the double-precision energy scans spread their bunches over")
+    ap.add_argument("--surrogate-streams", type=int, default=16,
+                    help="streams the surrogate energy scans spread their bunches over")
     ap.add_argument("--scan-thresholds", type=str, default=None,
                     help="comma-separated audit thresholds of the surrogate scans "
                          "(default: --threshold, 1e-4 and 1e-2)")
@@ -251,7 +265,7 @@ def c3_leg(ring, beam, n_samples, epochs, batch, lr):
 
 
 def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_energy, epochs,
-             lr, n_bands, thresholds=None):
+             lr, n_bands, thresholds=None, n_streams=4, surrogate_streams=16):
     """Energy scan with surrogate + fallback against plain double precision on
     the same bunches, plus the fallback fraction at looser thresholds."""
     from paper_1501_03450_amd import surrogate as S
@@ -270,10 +284,11 @@ def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_e
         nets.append(sur)
         per += [sur] * len(rng_)
     t_train = time.perf_counter() - t0
-    f = S.energy_scan(ring, bunches, turns, None, log=lambda m: log(f"[bench] fp64 scan {m}"))
+    f = S.energy_scan(ring, bunches, turns, None, n_streams=n_streams,
+                      log=lambda m: log(f"[bench] fp64 scan {m}"))
     res = {}
     for thr in sorted(thresholds if thresholds else {threshold, 1e-4, 1e-2}):
-        r = S.energy_scan(ring, bunches, turns, per, audit_every, thr,
+        r = S.energy_scan(ring, bunches, turns, per, audit_every, thr, n_streams=surrogate_streams,
                           log=lambda m: log(f"[bench] surrogate scan (threshold {thr:g}) {m}"))
         dp = np.abs(r["polarization"][:, :3] - f["polarization"][:, :3]).max()
         res[f"{thr:g}"] = {"value": r["rate"], "speedup_vs_fp64": r["rate"] / f["rate"],
@@ -286,7 +301,9 @@ def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_e
     return {
         "workload": f"{n_energies} energies (G*gamma0 from {gam[0] * beams[0].G:.4f} to "
                     f"{gam[-1] * beams[0].G:.4f}) x {n_per} particles x {turns} turns on "
-                    f"rhic_like_ring; {n_bands} band networks (7 inputs), audit every {audit_every}",
+                    f"rhic_like_ring; {n_bands} band networks (7 inputs), audit after the first "
+                    f"turn and every {audit_every}; bunches over {n_streams} streams (FP64) and "
+                    f"{surrogate_streams} streams (surrogate)",
         "unit": "particle-turns/s",
         "fp64_value": f["rate"],
         "surrogate_by_threshold": res,
@@ -492,14 +509,15 @@ def main():
     if not args.no_surrogate:
         out["surrogate"] = scan_leg(ring, args.band_energies, args.scan_particles, args.scan_turns,
                                     args.audit_every, args.threshold, args.band_train_per_energy,
-                                    args.band_epochs, args.lr, 1, thresholds)
+                                    args.band_epochs, args.lr, 1, thresholds, args.scan_streams,
+                                    args.surrogate_streams)
     if args.c3:
         out["c3_training"] = c3_leg(ring, beam, args.c3_samples, args.c3_epochs, 65536, args.lr)
     if args.c4:
         out["c4_scan"] = scan_leg(ring, args.c4_energies, args.scan_particles, args.scan_turns,
                                   args.audit_every, args.threshold, args.band_train_per_energy,
                                   args.band_epochs, args.lr, max(1, args.c4_energies // 16),
-                                  thresholds)
+                                  thresholds, args.scan_streams, args.surrogate_streams)
     if args.compare_integrators:
         out["integrators"] = integrator_leg(beam)
     if not args.no_cpu_baseline:
