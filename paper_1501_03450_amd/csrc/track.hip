@@ -543,6 +543,8 @@ __device__ __forceinline__ Quat thick_body_ext(const DevElem& el, double& X, dou
   return thick_element<NT, KIND, false, Y4>(el, X, Px, Y, Py, T, p, a);
 }
 
+// The body between the fringe spin kicks of its faces (elements flagged
+// F_FRINGE): q_exit · Q_body · q_entrance.
 template <int NT, int KIND, bool Y4>
 __device__ __forceinline__ Quat thick_ext_y(const DevElem& el, double& X, double& Px, double& Y,
                                          double& Py, double& T, const Particle& p,
