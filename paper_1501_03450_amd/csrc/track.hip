@@ -137,19 +137,8 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
           teapot_slice(el.tp, X, Px, Y, Py, T, p);
         } else if (Y4) {
           quad_slice4<KIND>(el.q4, mc, mc0, X, Px, Y, Py, T, p, a);
-        } else if (KIND == 1) {
-          mk_linear(mc, X, Px, Y, Py, T, p);
-          mk_nonlinear(ds, X, Px, Y, Py, T, p);
-          mk_linear(mc, X, Px, Y, Py, T, p);
-        } else if (KIND == 3) {
-          mk_linear(mc, Y, Py, X, Px, T, p);
-          mk_nonlinear(ds, X, Px, Y, Py, T, p);
-          mk_linear(mc, Y, Py, X, Px, T, p);
         } else {
-          drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
-          Px = fma(-el.q.k1ds, X, Px);
-          Py = fma(el.q.k1ds, Y, Py);
-          drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+          quad_step2<KIND>(el.q, mc, X, Px, Y, Py, T, p, a);
         }
         ps2 = p.P2() - fma(Px, Px, Py * Py);
         r = rsqrt_nr(ps2);
@@ -251,22 +240,8 @@ __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double
   MKConst mc;
   if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
   for (int j = 0; j < el.nsl; ++j) {
-    if (KIND == 4) {
-      teapot_slice(el.tp, X, Px, Y, Py, T, p);
-    } else if (KIND == 1) {
-      mk_linear(mc, X, Px, Y, Py, T, p);
-      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
-      mk_linear(mc, X, Px, Y, Py, T, p);
-    } else if (KIND == 3) {
-      mk_linear(mc, Y, Py, X, Px, T, p);
-      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
-      mk_linear(mc, Y, Py, X, Px, T, p);
-    } else {
-      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
-      Px = fma(-el.q.k1ds, X, Px);
-      Py = fma(el.q.k1ds, Y, Py);
-      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
-    }
+    if (KIND == 4) teapot_slice(el.tp, X, Px, Y, Py, T, p);
+    else           quad_step2<KIND>(el.q, mc, X, Px, Y, Py, T, p, a);
   }
 }
 
@@ -313,19 +288,8 @@ __device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double
       teapot_slice(el.tp, X, Px, Y, Py, T, p);
     } else if (Y4) {
       quad_slice4<KIND>(el.q4, mc, mc0, X, Px, Y, Py, T, p, a);
-    } else if (KIND == 1) {
-      mk_linear(mc, X, Px, Y, Py, T, p);
-      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
-      mk_linear(mc, X, Px, Y, Py, T, p);
-    } else if (KIND == 3) {
-      mk_linear(mc, Y, Py, X, Px, T, p);
-      mk_nonlinear(el.q.ds, X, Px, Y, Py, T, p);
-      mk_linear(mc, Y, Py, X, Px, T, p);
     } else {
-      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
-      Px = fma(-el.q.k1ds, X, Px);
-      Py = fma(el.q.k1ds, Y, Py);
-      drift(el.q.hds, X, Px, Y, Py, T, p, a.inv_beta0);
+      quad_step2<KIND>(el.q, mc, X, Px, Y, Py, T, p, a);
     }
     if (PLACE == P_KICK || (j & 1)) {
       if (KIND != 0) r = rsqrt_nr(p.P2() - fma(Px, Px, Py * Py));
