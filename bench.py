@@ -123,7 +123,7 @@ def parse():
                     help="full surrogate training run: 2^24 widened samples labelled by one "
                          "double-precision turn, batch 65536")
     ap.add_argument("--c3-samples", type=int, default=1 << 24)
-    ap.add_argument("--c3-epochs", type=int, default=20)
+    ap.add_argument("--c3-epochs", type=int, default=200)
     ap.add_argument("--c4", action="store_true",
                     help="full energy scan: 256 energies x 65536 particles, 16 bands")
     ap.add_argument("--c4-energies", type=int, default=256)
