@@ -112,6 +112,9 @@ std::string validate(const st_element& e, int64_t i) {
   if (e.fringe != 0 && e.kind != ST_SBEND && e.kind != ST_QUAD)
     return at + "fringe spin kicks apply to sector bends and quadrupoles";
   if (e.L < 0.0) return at + "negative length";
+  const bool sliced = e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID ||
+                      e.kind == ST_RBEND;
+  if (sliced && e.n_slices < 1) return at + "n_slices must be >= 1";
   switch (e.kind) {
     case ST_DRIFT:
       if (e.orbit != ST_ORB_EXACT) return at + "drifts use the exact method";
@@ -148,8 +151,7 @@ std::string validate(const st_element& e, int64_t i) {
       break;
   }
   if (e.kind != ST_SOLENOID && e.ks != 0.0) return at + "ks applies to solenoids only";
-  if (e.kind == ST_SBEND || e.kind == ST_QUAD || e.kind == ST_SOLENOID || e.kind == ST_RBEND) {
-    if (e.n_slices < 1) return at + "n_slices must be >= 1";
+  if (sliced) {
     if (e.romberg_rows < 1 || e.romberg_rows > st::kMaxRows)
       return at + "romberg_rows must be in 1.." + std::to_string(st::kMaxRows);
     if (e.spin_place != ST_SPIN_EDGES && e.romberg_rows != 1)

@@ -262,6 +262,11 @@ def test_invalid_lattices_are_rejected_before_device_work():
     for arr in bad_cases:
         assert B.st_load_lattice_raw(ctx, arr, 1, beam) == B.ST_EINVAL
         assert B.st_last_error(ctx)
+    for n_slices in (0, -2):
+        arr = B.element_array([sbend(10.0, 0.2, 8, 3)])
+        arr[0].n_slices = n_slices
+        assert B.st_load_lattice_raw(ctx, arr, 1, beam) == B.ST_EINVAL
+        assert "n_slices" in B.st_last_error(ctx)
     for bf, bv in [("gamma0", 1.0), ("aperture", 0.0), ("precision", 3), ("report_every", -1)]:
         b2 = B.st_beam(G=1.79, gamma0=25.0, aperture=0.1, precision=0, report_every=0)
         setattr(b2, bf, bv)
