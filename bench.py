@@ -244,6 +244,16 @@ def c3_leg(ring, beam, n_samples, epochs, batch, lr):
     steps = epochs * (x.shape[0] // batch)
     sps = steps * batch / t_train
     tflops = sps * S.flops_per_sample(6, True) / 1e12
+    # inference over the whole training set: one warm-up pass, then a timed one
+    from paper_1501_03450_amd import binding as B
+    q = torch.empty((x.shape[0], 4), dtype=torch.float32, device=x.device)
+    B.st_mlp_infer(sur.net, x.data_ptr(), q.data_ptr(), x.shape[0], None)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    B.st_mlp_infer(sur.net, x.data_ptr(), q.data_ptr(), x.shape[0], None)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t2
+    del q
     zv, _, _ = gaussian_bunch(65536, SEED_BASE + 33, beam)
     xv, tv = S.label_bunch(sur, ring, beam, zv)
     out = {
@@ -255,6 +265,8 @@ def c3_leg(ring, beam, n_samples, epochs, batch, lr):
         "train_tflops": tflops,
         "train_mfma_frac_of_bf16_peak": tflops / MFMA_BF16_PEAK_TFLOPS,
         "train_seconds": t_train,
+        "infer_samples_per_s": x.shape[0] / t_infer,
+        "infer_tflops": x.shape[0] / t_infer * S.flops_per_sample(6, False) / 1e12,
         "final_loss": sur.losses[-1],
         "output_frame_scale": [float(v) for v in sur.scale],
         "err_train_sample": quantiles(S.component_errors(sur, x[:65536], t[:65536])),

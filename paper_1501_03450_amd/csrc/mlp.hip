@@ -48,24 +48,20 @@ __device__ __forceinline__ float dsilu(float z) {
 }
 
 // acc[mt][nt] += A[64 x 256] (LDS, row stride LDA) · B'[n_base + 16 nt + j][k]
-// (global, row-major [256][256]) for the wave's 64 output columns.  The B
-// fragments of the next 32-wide k step are loaded before the current step's
-// sixteen MFMAs, so the L2 latency overlaps the matrix work.
+// (global, row-major [256][256]) for the wave's 64 output columns.  The
+// loop is unrolled, so the compiler issues the B loads of later k steps
+// ahead of the MFMAs; the L2 latency that remains is covered by the other
+// waves on the SIMD (four per SIMD: the kernels that call this are compiled
+// for that occupancy).
 __device__ __forceinline__ void gemm_64x64(const __bf16* A, const __bf16* Bg, int n_base,
                                            f32x4 acc[4][4], int lane) {
   const int r = lane & 15, kb = 8 * (lane >> 4);
   const __bf16* brow = Bg + (size_t)(n_base + r) * W + kb;
-  bf16x8 b[4], bn[4];
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) b[nt] = *reinterpret_cast<const bf16x8*>(brow + nt * 16 * W);
 #pragma unroll
   for (int k0 = 0; k0 < W; k0 += 32) {
-    if (k0 + 32 < W) {
+    bf16x8 a[4], b[4];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        bn[nt] = *reinterpret_cast<const bf16x8*>(brow + nt * 16 * W + k0 + 32);
-    }
-    bf16x8 a[4];
+    for (int nt = 0; nt < 4; ++nt) b[nt] = *reinterpret_cast<const bf16x8*>(brow + nt * 16 * W + k0);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
       a[mt] = *reinterpret_cast<const bf16x8*>(A + (mt * 16 + r) * LDA + k0 + kb);
@@ -74,10 +70,6 @@ __device__ __forceinline__ void gemm_64x64(const __bf16* A, const __bf16* Bg, in
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
         acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
-    if (k0 + 32 < W) {
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) b[nt] = bn[nt];
-    }
   }
 }
 
@@ -131,9 +123,13 @@ __device__ __forceinline__ void store_feature_major(const __bf16* lds, __bf16* o
 
 // One activation buffer per workgroup (34 KB of LDS, so four workgroups fit
 // on a CU): each layer's GEMM reads it, a barrier, then the epilogue
-// overwrites it with the layer's output.
+// overwrites it with the layer's output.  Compiled for four waves per SIMD
+// (128 registers, a few spilled outside the MFMA loops), so that four
+// workgroups are resident per CU and the whole batch of 1024 tiles of a
+// 65536-sample batch is on the chip at once.
 template <bool TRAIN>
-__global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
+mlp_forward_kernel(const MlpArgs a) {
   __shared__ __align__(16) __bf16 bufA[TM * LDA];
   __shared__ float xs[TM][kMlpMaxIn];
   __shared__ float ys[TM][4];
@@ -229,8 +225,10 @@ __global__ void __launch_bounds__(NT) mlp_forward_kernel(const MlpArgs a) {
   }
 }
 
-// Backward through the layers for one tile of samples.
-__global__ void __launch_bounds__(NT) mlp_backward_data_kernel(const MlpArgs a) {
+// Backward through the layers for one tile of samples (four waves per SIMD,
+// as the forward kernel).
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
+mlp_backward_data_kernel(const MlpArgs a) {
   __shared__ __align__(16) __bf16 bufA[TM * LDA];   // one buffer, as in the forward pass
   __shared__ float xs[TM][kMlpMaxIn];
   __shared__ float dys[TM][4];
