@@ -42,7 +42,8 @@ class _Elem(ctypes.Structure):
                 ("spin", ctypes.c_int32), ("fringe", ctypes.c_int32),
                 ("L", ctypes.c_double), ("angle", ctypes.c_double), ("eta", ctypes.c_double),
                 ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
-                ("phi", ctypes.c_double), ("mu", ctypes.c_double), ("ks", ctypes.c_double)]
+                ("phi", ctypes.c_double), ("mu", ctypes.c_double), ("ks", ctypes.c_double),
+                ("asym", ctypes.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -94,6 +95,9 @@ def _elems(elements):
         a.phi, a.mu = e.snake_phi, e.snake_mu
         a.ks = getattr(e, "ks", 0.0)
         a.fringe = int(bool(getattr(e, "fringe", False)))
+        a.asym = float(getattr(e, "asym", 0.0))
+        if a.asym != 0.0 and e.kind != "rbend":
+            raise ValueError("asym applies to rectangular bends")
         if a.fringe and e.kind not in ("sbend", "quad"):
             raise ValueError("fringe spin kicks apply to sector bends and quadrupoles")
         if e.kind == "sbend" and e.method not in ("exact", "teapot"):
@@ -109,6 +113,8 @@ def _elems(elements):
                 raise ValueError("the kick spin placement needs drift-kick slices")
             if a.spin != SPIN_CODES["edges"] and e.rows != 1:
                 raise ValueError("piece-wise constant spin placements take rows = 1")
+            if not (abs(e.angle / 2 + a.asym) < 1.5 and abs(a.asym - e.angle / 2) < 1.5):
+                raise ValueError("rectangular bends need |phi_entr|, |phi_exit| < 1.5")
         if e.kind == "solenoid":
             if e.method != "exact" or e.n_slices < 1 or e.rows < 1 or e.L <= 0 or e.ks == 0:
                 raise ValueError("solenoids: exact body, L > 0, ks != 0, n_slices, rows >= 1")

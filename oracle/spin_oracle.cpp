@@ -133,6 +133,9 @@ struct Elem {             // the oracle's own element record
   int32_t fringe;         // sector bend or quadrupole: 1 adds the fringe spin kicks
   double L, angle, eta, k1, k1l, k2l, phi, mu;
   double ks;              // solenoid field b0/(Bρ)0 [1/m]
+  double asym;            // rectangular bend: the faces turned by asym from the
+                          // symmetric placement, φ^entr = θ/2 + asym and
+                          // φ^exit = asym - θ/2 (§3.2)
 };
 
 enum { X = 0, PX = 1, Y = 2, PY = 3, TT = 4, PT = 5 };
@@ -326,9 +329,11 @@ template <class T> Quat<T> solenoid_fringe(const T z[6], T ks, T sign, const Ref
   return qrot(f * (a1 * z[X] - a2 * d * kx), f * (a1 * z[Y] - a2 * d * ky), f * (-a2 * d * ps));
 }
 
-// ---- Rectangular bend (§3.2), symmetric: the design orbit enters and leaves
-// at half the bend angle θ to the magnet faces; field b1/(Bρ)0 = 1/ρb =
-// η 2 sin(θ/2)/L in the magnet's Cartesian frame.
+// ---- Rectangular bend (§3.2): in the magnet's Cartesian frame the design
+// orbit enters at the angle φ^entr to the magnet's axis and leaves at φ^exit,
+// turning by θ = φ^entr - φ^exit on a circle of radius ρ with
+// L = ρ (sin φ^entr - sin φ^exit); the field is b1/(Bρ)0 = η/ρ.  The
+// symmetric magnet has φ^exit = -φ^entr = -θ/2.
 
 // Dynamic rotation of the frame by φ: the flow of eq. Hprot, H = -X Ps,
 // over the angle φ (eq. prot).  T follows that flow, dT/dφ = -X (1/β0 +
@@ -539,9 +544,13 @@ void dk_kick(const Elem& e, T z[6], T s) {
   else                 kick(z, T(e.k1) * s, T(0));
 }
 
+// Entrance and exit angles of the design orbit in a rectangular bend.
+template <class T> T rbend_phi_entr(const Elem& e) { return T(e.angle) / T(2) + T(e.asym); }
+template <class T> T rbend_phi_exit(const Elem& e) { return T(e.asym) - T(e.angle) / T(2); }
+
 template <class T> T rbend_fb(const Elem& e) {
   using std::sin;
-  return T(e.eta) * T(2) * sin(T(e.angle) / T(2)) / T(e.L);
+  return T(e.eta) * (sin(rbend_phi_entr<T>(e)) - sin(rbend_phi_exit<T>(e))) / T(e.L);
 }
 
 // One second-order quadrupole slice: drift-kick-drift (§3.4 applied to
@@ -594,13 +603,14 @@ Quat<T> element(const Elem& e, T z[6], const Ref<T>& r) {
       drift(z, T(e.L), r);
       return qident<T>();
     case RBEND: {
-      // frame rotation into the magnet, fringe, body, fringe, rotation out;
-      // the rotations turn the spin components with the frame about ŷ
-      using std::sin;
-      T half = T(e.angle) / T(2);
+      // frame rotation by φ^entr into the magnet, fringe, body, the design
+      // orbit's horizontal offset (eq. Xoffset), fringe, rotation by
+      // -φ^exit out; the rotations turn the spin components with the frame
+      // about ŷ
+      using std::sin; using std::cos;
+      T phe = rbend_phi_entr<T>(e), phx = rbend_phi_exit<T>(e);
       T fb = rbend_fb<T>(e);
-      Quat<T> qf = qrot(T(0), half, T(0));
-      prot(z, half, r);
+      prot(z, phe, r);
       dipole_fringe(z, fb, T(1), r);
       Quat<T> qin = rbend_fringe_spin(z, fb, T(1), r);
       int N = e.nsl;
@@ -626,13 +636,18 @@ Quat<T> element(const Elem& e, T z[6], const Ref<T>& r) {
         }
         Qb = romberg_spin(om, N, ds, e.rows);
       }
+      // the design orbit leaves the body displaced by X^offset from where it
+      // entered (zero for the symmetric magnet): refer X to it again
+      T sdiff = sin(phe) - sin(phx);
+      z[X] = z[X] - (-T(e.L) * (cos(phe) - cos(phx)) / sdiff);
       Quat<T> qout = rbend_fringe_spin(z, fb, T(-1), r);
       dipole_fringe(z, fb, T(-1), r);
-      prot(z, half, r);
+      prot(z, -phx, r);
       // T as a deviation from the design particle's flight time over the arc
-      T larc = T(e.angle) * T(e.L) / (T(2) * sin(half));
+      // (eq. Toffset)
+      T larc = T(e.L) * (phe - phx) / sdiff;
       z[TT] = z[TT] + larc / r.beta0;
-      return qmul(qf, qmul(qout, qmul(Qb, qmul(qin, qf))));
+      return qmul(qrot(T(0), -phx, T(0)), qmul(qout, qmul(Qb, qmul(qin, qrot(T(0), phe, T(0))))));
     }
     case SOLENOID: {
       // entrance fringe, body (edge Ω with Romberg, or midpoint PWC), exit fringe

@@ -210,20 +210,24 @@ def _rhs_rect_dipole(fb, profile, beam):
     return f
 
 
-def track_rbend(L, angle, eta, eps, beam, z, s, rtol=1e-13, atol=1e-16):
-    """Symmetric rectangular bend: frame rotation by angle/2, a dipole field
-    rising linearly over [0, eps], flat to L, falling over [L, L + eps], frame
-    rotation by angle/2; spin components turned with each frame rotation; T
-    referred to the design arc."""
-    fb = eta * 2.0 * math.sin(angle / 2) / L
-    half = angle / 2
-    zz = track_prot(half, beam, z, rtol, atol)
+def track_rbend(L, angle, eta, eps, beam, z, s, rtol=1e-13, atol=1e-16, asym=0.0):
+    """Rectangular bend whose faces meet the design orbit at phe = angle/2 +
+    asym (entrance) and phx = asym - angle/2 (exit): frame rotation by phe, a
+    dipole field rising linearly over [0, eps], flat to L, falling over
+    [L, L + eps], X referred to the exit point of the hard-edge design circle
+    (radius rho = L/(sin phe - sin phx), exit X = rho (cos phx - cos phe)),
+    frame rotation by -phx; spin components turned with each frame rotation;
+    T referred to the design arc rho·angle."""
+    phe, phx = angle / 2 + asym, asym - angle / 2
+    rho = L / (math.sin(phe) - math.sin(phx))
+    fb = eta / rho
+    zz = track_prot(phe, beam, z, rtol, atol)
     S = np.asarray(s, float)
 
     def roty(S, a):          # active rotation about ŷ by a
         c, sn = math.cos(a), math.sin(a)
         return np.array([c * S[0] + sn * S[2], S[1], -sn * S[0] + c * S[2]])
-    S = roty(S, half)
+    S = roty(S, phe)
     y = np.concatenate([zz, S])
     pieces = [(0.0, eps, lambda t: (t / eps, 1.0 / eps)),
               (eps, L, lambda t: (1.0, 0.0)),
@@ -232,9 +236,11 @@ def track_rbend(L, angle, eta, eps, beam, z, s, rtol=1e-13, atol=1e-16):
         sol = solve_ivp(_rhs_rect_dipole(fb, prof, beam), (a, b), y, method="DOP853",
                         rtol=rtol, atol=atol)
         y = sol.y[:, -1]
-    zz = track_prot(half, beam, y[:6], rtol, atol)
-    S = roty(y[6:], half)
-    larc = angle * L / (2 * math.sin(half))
+    y = y.copy()
+    y[0] -= rho * (math.cos(phx) - math.cos(phe))
+    zz = track_prot(-phx, beam, y[:6], rtol, atol)
+    S = roty(y[6:], -phx)
+    larc = rho * angle
     zz[4] += (larc - (L + eps)) / beam.beta0
     return zz, S
 

@@ -71,6 +71,7 @@ class Element:
     spin: str = "edges"
     ks: float = 0.0
     fringe: bool = False
+    asym: float = 0.0          # rectangular bend: φ^entr = angle/2 + asym, φ^exit = asym - angle/2
 
     def __post_init__(self):
         if self.kind not in KINDS:
@@ -81,6 +82,8 @@ class Element:
             raise ValueError(f"unknown spin placement {self.spin!r}")
         if self.fringe and self.kind not in ("sbend", "quad"):
             raise ValueError("fringe spin kicks apply to sector bends and quadrupoles")
+        if self.asym != 0.0 and self.kind != "rbend":
+            raise ValueError("asym applies to rectangular bends")
 
 
 def drift(L: float, name: str = "D") -> Element:
@@ -109,8 +112,9 @@ def solenoid(L: float, ks: float, n: int, rows: int, name: str = "SOL",
 
 
 def rbend(L: float, angle: float, n: int, rows: int, eta: float = 1.0, name: str = "RB",
-          spin: str = "edges") -> Element:
-    return Element("rbend", L=L, angle=angle, eta=eta, n_slices=n, rows=rows, name=name, spin=spin)
+          spin: str = "edges", asym: float = 0.0) -> Element:
+    return Element("rbend", L=L, angle=angle, eta=eta, n_slices=n, rows=rows, name=name, spin=spin,
+                   asym=asym)
 
 
 def thin(k1l: float = 0.0, k2l: float = 0.0, name: str = "M") -> Element:
