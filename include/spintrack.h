@@ -62,11 +62,14 @@ typedef enum {
   ST_SOLENOID = 6,  /* solenoid: L, ks = b0/(Bρ)0, exact body map (§3.7 eq.
                        solenoid) between thin-pancake fringes whose spin kicks
                        follow §4.4 eq. solFringe; spin_place EDGES or MIDPOINT */
-  ST_RBEND = 7      /* symmetric rectangular bend: straight length L, design
-                       bend `angle` (half at each face), powering eta != 0;
-                       frame rotations (eq. prot), thin dipole fringes (eq.
-                       dipolefringe), exact body (§3.2 eq. rbend), fringe
-                       spin kicks (§4.5); spin_place EDGES or MIDPOINT        */
+  ST_RBEND = 7      /* rectangular bend: straight length L, design bend
+                       `angle`, faces at φ^entr = angle/2 + asym and
+                       φ^exit = asym - angle/2 to the design orbit, powering
+                       eta != 0; frame rotations by φ^entr and -φ^exit (eq.
+                       prot), thin dipole fringes (eq. dipolefringe), exact
+                       body (§3.2 eq. rbend), the design orbit's horizontal
+                       offset (eq. Xoffset) and flight time (eq. Toffset),
+                       fringe spin kicks (§4.5); spin_place EDGES or MIDPOINT */
 } st_kind;
 
 typedef enum {
@@ -125,10 +128,16 @@ typedef enum {
  *                entrance and the opposite expression at the exit; the orbit
  *                is unchanged.  0 for every other kind
  *   ks           solenoid longitudinal field b0/(Bρ)0 [m^-1] (0 otherwise)
+ *   asym         rectangular bends: the turn of both faces away from the
+ *                symmetric placement [rad]; the design orbit meets the
+ *                entrance face at φ^entr = angle/2 + asym and the exit face at
+ *                φ^exit = asym - angle/2 to the magnet's axis (§3.2), so the
+ *                field is b1/(Bρ)0 = eta (sin φ^entr - sin φ^exit)/L.  0 is
+ *                the symmetric magnet, and 0 for every other kind
  */
 typedef struct {
   int32_t kind, orbit, n_slices, romberg_rows, spin_place, fringe;
-  double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks;
+  double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks, asym;
 } st_element;
 
 /* Beam and run parameters.
@@ -156,7 +165,8 @@ st_status st_destroy(st_ctx* ctx);
  * sbends need L > 0, angle ≠ 0, the exact or TEAPOT method and, with the
  * exact method, eta > 0; quadrupoles need L > 0 and the DKD, MK, DKD4 or MK4
  * method; solenoids need L > 0 and ks ≠ 0; rectangular bends need L > 0,
- * 0 < |angle| < 3 and eta ≠ 0; thick elements need n_slices ≥ 1 and
+ * angle ≠ 0, |φ^entr| < 1.5, |φ^exit| < 1.5 and eta ≠ 0 (asym ≠ 0 only
+ * for them); thick elements need n_slices ≥ 1 and
  * romberg_rows in 1..4 (1 with a piece-wise constant placement); the kick
  * placement needs DKD or TEAPOT slices; fringe is 0 or 1 and only on sbends
  * and quadrupoles; gamma0 > 1; aperture > 0; report_every ≥ 0.

@@ -44,7 +44,7 @@ class st_element(ctypes.Structure):
                 ("L", ctypes.c_double), ("angle", ctypes.c_double), ("eta", ctypes.c_double),
                 ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
                 ("snake_phi", ctypes.c_double), ("snake_mu", ctypes.c_double),
-                ("ks", ctypes.c_double)]
+                ("ks", ctypes.c_double), ("asym", ctypes.c_double)]
 
 
 class st_beam(ctypes.Structure):
@@ -137,6 +137,7 @@ def element_array(elements):
         a.snake_phi, a.snake_mu = float(e.snake_phi), float(e.snake_mu)
         a.ks = float(getattr(e, "ks", 0.0))
         a.fringe = int(getattr(e, "fringe", 0))
+        a.asym = float(getattr(e, "asym", 0.0))
     return arr
 
 

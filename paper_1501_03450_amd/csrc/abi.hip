@@ -82,7 +82,8 @@ st_status hip_fail(st_ctx* c, hipError_t e, const char* what) {
 }
 
 bool finite_all(const st_element& e) {
-  const double v[] = {e.L, e.angle, e.eta, e.k1, e.k1l, e.k2l, e.snake_phi, e.snake_mu, e.ks};
+  const double v[] = {e.L,         e.angle,    e.eta, e.k1, e.k1l, e.k2l,
+                      e.snake_phi, e.snake_mu, e.ks,  e.asym};
   for (double x : v)
     if (!std::isfinite(x)) return false;
   return true;
@@ -137,7 +138,9 @@ std::string validate(const st_element& e, int64_t i) {
     case ST_RBEND:
       if (e.orbit != ST_ORB_EXACT) return at + "rectangular bends use the exact body map";
       if (!(e.L > 0.0)) return at + "rectangular bend needs L > 0";
-      if (e.angle == 0.0 || !(std::fabs(e.angle) < 3.0)) return at + "rectangular bend needs 0 < |angle| < 3";
+      if (e.angle == 0.0) return at + "rectangular bend needs angle != 0";
+      if (!(std::fabs(0.5 * e.angle + e.asym) < 1.5) || !(std::fabs(e.asym - 0.5 * e.angle) < 1.5))
+        return at + "rectangular bend needs |phi_entr| and |phi_exit| < 1.5";
       if (e.eta == 0.0) return at + "rectangular bend needs eta != 0";
       if (e.spin_place == ST_SPIN_KICK) return at + "the kick spin placement needs drift-kick slices";
       break;
@@ -151,6 +154,7 @@ std::string validate(const st_element& e, int64_t i) {
       break;
   }
   if (e.kind != ST_SOLENOID && e.ks != 0.0) return at + "ks applies to solenoids only";
+  if (e.kind != ST_RBEND && e.asym != 0.0) return at + "asym applies to rectangular bends only";
   if (sliced) {
     if (e.romberg_rows < 1 || e.romberg_rows > st::kMaxRows)
       return at + "romberg_rows must be in 1.." + std::to_string(st::kMaxRows);
@@ -255,19 +259,28 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
       fill(d.q4.s0, (double)(x0 * ds));
     }
   } else if (e.kind == ST_RBEND) {
+    // faces at φ^entr = θ/2 + asym and φ^exit = asym - θ/2; with
+    // sin φ^entr - sin φ^exit = 2 cos(asym) sin(θ/2) and cos φ^entr -
+    // cos φ^exit = -2 sin(asym) sin(θ/2), eq. Xoffset is L tan(asym), free
+    // of the cancellation in the difference of cosines
     st::RbendParams& rb = d.rb;
     const double half = 0.5 * e.angle;
+    const double sdiff = 2.0 * std::cos(e.asym) * std::sin(half);   // sin φ^entr - sin φ^exit
     rb.ds = e.L / n_orb;
     rb.L = e.L;
-    rb.fb = e.eta * 2.0 * std::sin(half) / e.L;
+    rb.fb = e.eta * sdiff / e.L;
     rb.rhob = 1.0 / rb.fb;
-    rb.c = std::cos(half);
-    rb.sn = std::sin(half);
-    rb.tn = rb.sn / rb.c;
-    rb.sec = 1.0 / rb.c;
-    rb.qf_w = std::cos(0.5 * half);
-    rb.qf_y = std::sin(0.5 * half);
-    rb.larc_ib0 = e.angle * e.L / (2.0 * std::sin(half)) / beta0;
+    rb.xoff = e.L * std::tan(e.asym);
+    rb.larc_ib0 = e.angle * e.L / sdiff / beta0;
+    auto face = [](st::RbendFace& f, double phi) {
+      f.c = std::cos(phi);
+      f.tn = std::sin(phi) / f.c;
+      f.sec = 1.0 / f.c;
+      f.qw = std::cos(0.5 * phi);
+      f.qy = std::sin(0.5 * phi);
+    };
+    face(rb.in, half + e.asym);
+    face(rb.out, half - e.asym);                                      // -φ^exit
   } else if (e.kind == ST_SOLENOID) {
     st::SolenoidParams& sp = d.sol;
     sp.ds = e.L / n_orb;
@@ -311,7 +324,7 @@ double design_angle(const st_element& e, const st_beam& b, double r_ref) {
   if (e.kind == ST_RBEND) {
     const double ds = e.L / e.n_slices;
     const double f = (e.n_slices > 1 || e.spin_place != ST_SPIN_EDGES) ? ds : 0.5 * ds;
-    return a1 * std::fabs(e.eta * 2.0 * std::sin(0.5 * e.angle) / e.L) * f;
+    return a1 * std::fabs(e.eta * 2.0 * std::cos(e.asym) * std::sin(0.5 * e.angle) / e.L) * f;
   }
   if (e.kind == ST_SOLENOID) {
     const double ds = e.L / e.n_slices;

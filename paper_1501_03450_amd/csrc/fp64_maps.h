@@ -239,9 +239,9 @@ __device__ __forceinline__ void solenoid_fringe(const SolenoidParams& sp, double
   wz = -f * d * ps;
 }
 
-// Rectangular bend (§3.2).  Frame rotation by the face angle (the flow of
+// Rectangular bend (§3.2).  Frame rotation by a face angle (the flow of
 // eq. Hprot; T decreases for X > 0, which reaches the rotated face later).
-__device__ __forceinline__ void rbend_rotate(const RbendParams& rb, double& X, double& Px, double& Y,
+__device__ __forceinline__ void rbend_rotate(const RbendFace& rb, double& X, double& Px, double& Y,
                                              double Py, double& T, const Particle& p) {
   const double ps2 = p.P2() - fma(Px, Px, Py * Py);
   const double r = rsqrt_nr(ps2);
@@ -251,7 +251,7 @@ __device__ __forceinline__ void rbend_rotate(const RbendParams& rb, double& X, d
   Y = fma(Py * r, xt, Y);
   T = fma(-p.ib() * r, xt, T);
   X = X * rb.sec * inv_den;
-  Px = fma(Px, rb.c, ps * rb.sn);
+  Px = fma(Px, rb.c, ps * (rb.tn * rb.c));
 }
 
 // Thin dipole fringe without gap correction (eq. dipolefringe), sign +1 at

@@ -59,13 +59,17 @@ struct SolenoidParams {     // solenoid (§3.7, §4.4)
   double eta, inv_eta;      // ks/2 and its inverse
   double eta_q;             // ks/4: half the vector potential at a fringe
 };
-struct RbendParams {        // symmetric rectangular bend (§3.2, §4.5)
+struct RbendFace {          // frame rotation by φ at a rectangular-bend face
+  double c, tn, sec;        // cos φ, tan φ, 1/cos φ
+  double qw, qy;            // the spin's frame rotation (cos φ/2, sin φ/2 ŷ)
+};
+struct RbendParams {        // rectangular bend (§3.2, §4.5)
   double ds;                // orbit slice length along the magnet
   double L;                 // straight length (one-step orbit)
   double fb, rhob;          // b1/(Bρ)0 and its inverse
-  double c, sn, tn, sec;    // of the face angle θ/2
-  double qf_w, qf_y;        // frame rotation of the spin: (cos θ/4, sin θ/4 ŷ)
-  double larc_ib0;          // design arc length / β0
+  double xoff;              // the design orbit's exit X in the magnet (eq. Xoffset)
+  double larc_ib0;          // design arc length / β0 (eq. Toffset)
+  RbendFace in, out;        // rotations by φ^entr and by -φ^exit
 };
 struct DriftParams { double L; };
 struct ThinParams { double k1l, k2l; };             // thin multipole (§3.5)

@@ -391,10 +391,12 @@ __device__ __forceinline__ Quat solenoid_element(const DevElem& el, double& X, d
   return qmul(rot(wx, wy, wz), qmul(Q, qin));
 }
 
-// Symmetric rectangular bend (§3.2, §4.5): frame rotation into the magnet
+// Rectangular bend (§3.2, §4.5): frame rotation by φ^entr into the magnet
 // (the spin components turn with the frame about ŷ), entrance fringe and its
 // spin kick, body slices with Romberg over the edges or midpoint rotations,
-// exit fringe and kick, frame rotation out; T referred to the design arc.
+// X referred to the design orbit's exit point (eq. Xoffset), exit fringe and
+// kick, frame rotation by -φ^exit out; T referred to the design arc (eq.
+// Toffset).
 template <int NT, int PLACE>
 __device__ __forceinline__ Quat rbend_element(const DevElem& el, double& X, double& Px, double& Y,
                                               double& Py, double& T, const Particle& p,
@@ -410,8 +412,7 @@ __device__ __forceinline__ Quat rbend_element(const DevElem& el, double& X, doub
     const double f = sign * rb.fb * Y;
     return rot(f * p.a2() * Px, 0.0, -f * (1.0 + a.G));
   };
-  const Quat qf = {rb.qf_w, 0.0, rb.qf_y, 0.0};
-  rbend_rotate(rb, X, Px, Y, Py, T, p);
+  rbend_rotate(rb.in, X, Px, Y, Py, T, p);
   rbend_fringe(rb, 1.0, X, Px, Y, Py, T, p);
   const Quat qin = fringe_spin(1.0);
   Quat Q;
@@ -469,11 +470,13 @@ __device__ __forceinline__ Quat rbend_element(const DevElem& el, double& X, doub
   }
   const double inv = rsqrt_nr(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
   Q = {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
+  X -= rb.xoff;
   const Quat qout = fringe_spin(-1.0);
   rbend_fringe(rb, -1.0, X, Px, Y, Py, T, p);
-  rbend_rotate(rb, X, Px, Y, Py, T, p);
+  rbend_rotate(rb.out, X, Px, Y, Py, T, p);
   T += rb.larc_ib0;
-  return qmul(qf, qmul(qout, qmul(Q, qmul(qin, qf))));
+  const Quat qfi = {rb.in.qw, 0.0, rb.in.qy, 0.0}, qfo = {rb.out.qw, 0.0, rb.out.qy, 0.0};
+  return qmul(qfo, qmul(qout, qmul(Q, qmul(qin, qfi))));
 }
 
 // Spin kick across the thin fringe of a normal 2m-pole face crossed about
@@ -629,11 +632,12 @@ track_kernel(const TrackArgs a) {
           else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a);
           else                    thick_orbit<3>(e, X, Px, Y, Py, T, p, a);
         } else if (EXT && e.kind == K_RBEND) {
-          rbend_rotate(e.rb, X, Px, Y, Py, T, p);
+          rbend_rotate(e.rb.in, X, Px, Y, Py, T, p);
           rbend_fringe(e.rb, 1.0, X, Px, Y, Py, T, p);
           rbend_body(e.rb, e.rb.L, X, Px, Y, Py, T, p);
+          X -= e.rb.xoff;
           rbend_fringe(e.rb, -1.0, X, Px, Y, Py, T, p);
-          rbend_rotate(e.rb, X, Px, Y, Py, T, p);
+          rbend_rotate(e.rb.out, X, Px, Y, Py, T, p);
           T += e.rb.larc_ib0;
         } else if (EXT && e.kind == K_SOLENOID) {
           const SolState st = sol_state<NT>(e.sol, X, Px, Y, Py, p, a.ymax, a.inv_beta0);

@@ -37,13 +37,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_the_header():
     from paper_1501_03450_amd import binding
-    # st_element: 6 int32 then 9 doubles; st_beam: 3 doubles then 2 int32
-    assert ctypes.sizeof(binding.st_element) == 6 * 4 + 9 * 8
+    # st_element: 6 int32 then 10 doubles; st_beam: 3 doubles then 2 int32
+    assert ctypes.sizeof(binding.st_element) == 6 * 4 + 10 * 8
     assert binding.st_element.L.offset == 24
     assert ctypes.sizeof(binding.st_beam) == 3 * 8 + 2 * 4
     text = open(HEADER).read()
     assert "int32_t kind, orbit, n_slices, romberg_rows, spin_place, fringe;" in text
-    assert "double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks;" in text
+    assert "double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks, asym;" in text
     assert "double G, gamma0, aperture;" in text
     assert "int32_t precision, report_every;" in text
 

@@ -42,6 +42,11 @@ ELEMENTS = {
     "rbend_mispowered": [rbend(3.0, 0.12, 4, 2, eta=0.98)],
     "rbend_negative": [rbend(2.0, -0.1, 6, 2)],
     "rbend_midpoint": [rbend(3.0, 0.12, 5, 1, spin="midpoint")],
+    # faces turned from the symmetric placement (eq. Xoffset, eq. Toffset)
+    "rbend_asym_R3": [rbend(3.0, 0.12, 8, 3, asym=0.03)],
+    "rbend_asym_strong": [rbend(3.0, 0.6, 16, 4, asym=0.2)],
+    "rbend_asym_negative_midpoint": [rbend(2.0, -0.1, 5, 1, spin="midpoint", asym=-0.04)],
+    "rbend_asym_one_face_square": [rbend(3.0, 0.12, 4, 2, eta=0.98, asym=-0.06)],
     "fringe_bend_R3": [sbend(10.0, TH, 8, 3, fringe=True)],
     "fringe_bend_teapot_kick": [sbend(10.0, TH, 8, 1, method="teapot", spin="kick", fringe=True)],
     "fringe_quad_mk_R3": [quad(1.1, 0.08, "mk", 4, 3, fringe=True)],
@@ -133,6 +138,36 @@ def test_small_ring_with_rectangular_bends():
     assert err <= 0.25 * plain
 
 
+def test_small_ring_with_turned_rectangular_bends():
+    # as above, with the faces of successive magnets turned by +0.01 and
+    # -0.01 from the symmetric placement: each magnet still hands the design
+    # orbit on at the reference, so the ring stays closed
+    rho = 10.0 / TH
+    ring, k = [], 0
+    for e in pwc_ring(N=4):
+        if e.kind == "sbend":
+            asym = 0.01 if k % 2 == 0 else -0.01
+            sdiff = 2 * math.cos(asym) * math.sin(TH / 2)
+            ring.append(rbend(rho * sdiff, TH, 8, 3, asym=asym))
+            k += 1
+        elif e.kind == "quad":
+            ring.append(quad(e.L, e.k1, "mk", 4, 3))
+        else:
+            ring.append(e)
+    # Px now reaches sin(θ/2 + 0.01) = 0.108 inside the magnets: the one-turn
+    # bound is 3e-12 (the GPU measured 2.2e-12), with the same test against a
+    # plain double evaluation of the printed maps (1.5e-11 here) as above
+    z, s, a = gaussian_bunch(700, 1501034520, BEAM)
+    g, o = both(ring, BEAM, z, s, a, turns=1, want_q=True)
+    assert_parity(g, o, "turned rbend ring", orbit_tol=3e-12)
+    plain, _ = orbit_rel_err(oracle.track(ring, BEAM, z, s, a, turns=1, extended=False), o)
+    err, _ = orbit_rel_err(g, o)
+    print(f"turned rbend ring: GPU orbit rel err {err:.3e}, plain FP64 {plain:.3e}")
+    assert err <= 0.25 * plain
+    g, o = both(ring, BEAM, z, s, a, turns=8)
+    assert_parity(g, o, "turned rbend ring, 8 turns", orbit_tol=3e-12 * 8)
+
+
 def test_low_energy_solenoid():
     # 1.2 GeV protons through the 2.1 m, 1.3 T solenoid: a large spin rotation
     beam = Beam(gamma0=1.2 / 0.938272)
@@ -218,7 +253,11 @@ def test_invalid_placements_are_rejected_before_device_work():
         [solenoid(2.0, 0.0, 4, 1)],                                # ks must be non-zero
         [rbend(3.0, 0.12, 4, 1, eta=0.0)],                         # rbend needs a field
         [rbend(3.0, 0.12, 4, 1, spin="kick")],                     # no kick placement
+        [rbend(3.0, 0.12, 4, 1, asym=1.5)],                        # |phi_entr| >= 1.5
     ]
+    # asym only on rectangular bends
+    bad.append([types.SimpleNamespace(**{**dataclasses.asdict(sbend(10.0, TH, 4, 1)),
+                                         "asym": 0.01})])
     # fringe kicks only on sector bends and quadrupoles, flag 0 or 1
     bad.append([types.SimpleNamespace(**{**dataclasses.asdict(drift(1.0)), "fringe": 1})])
     bad.append([types.SimpleNamespace(**{**dataclasses.asdict(rbend(3.0, 0.12, 4, 1)),
