@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--turns-per-step", type=int, default=100)
     ap.add_argument("--particles", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the FP64 FMA / bf16 MFMA / HBM copy microbenchmarks")
     ap.add_argument("--cpu-sample-particles", type=int, default=32768)
     ap.add_argument("--cpu-sample-turns", type=int, default=10)
     ap.add_argument("--mixed-particles", type=int, default=4 << 20)
@@ -514,6 +516,13 @@ def main():
         "particle_element_passes_per_s": rate * summ["n_elements"],
         "hbm_GB_per_s": (traffic / (np.mean(step_ms) / 1e3) / 1e9) if traffic else None,
     }
+    if not args.no_peaks:
+        # measured denominators next to the published ones (outside the timed region)
+        from paper_1501_03450_amd import binding as B
+        pk = B.st_measure_peaks(0)
+        pk["track_frac_of_measured_fp64"] = achieved / pk["fp64_fma_tflops"]
+        out["peaks_measured"] = pk
+        log(f"[bench] measured peaks: {pk}")
     thresholds = ({float(v) for v in args.scan_thresholds.split(",")}
                   if args.scan_thresholds else None)
     if not args.no_mixed:

@@ -298,6 +298,25 @@ st_status st_track_surrogate(st_ctx* ctx, st_mlp* m, int64_t turns, int32_t audi
                              double threshold, const double* center, const double* inv_scale,
                              double extra, int32_t* d_fallback, void* stream);
 
+/* Measured peaks of the device: the denominators of the roofline fractions
+ * (not a step of the method).
+ *   fp64_fma_tflops   FP64 vector FMA rate, eight independent v_fma_f64 chains
+ *                     per lane, 16 workgroups of 256 lanes per compute unit
+ *   bf16_mfma_tflops  dense bf16 matrix rate, four independent chains of
+ *                     v_mfma_f32_16x16x32_bf16 per wave
+ *   copy_gbps         HBM bandwidth of a 16-byte copy of 1 GiB into 1 GiB,
+ *                     read plus written bytes
+ * Each is timed with HIP events over 10 launches after a warm-up launch. */
+typedef struct {
+  double fp64_fma_tflops, bf16_mfma_tflops, copy_gbps;
+} st_peaks;
+
+/* Run the three microbenchmarks on HIP device `device` and fill *out.
+ * Synchronous; allocates and frees 2 GiB of device memory.  ST_EINVAL for a
+ * NULL out or an unknown device, ST_EDEVICE if an allocation, launch or timing
+ * call fails (out is then incomplete). */
+st_status st_measure_peaks(int device, st_peaks* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,7 @@ EXPORTS = ("st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
            "st_bind_quaternions", "st_track", "st_polarization", "st_read_particles",
            "st_last_error", "st_mlp_create", "st_mlp_destroy", "st_mlp_last_error",
            "st_mlp_params", "st_mlp_set_frame", "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
-           "st_mlp_features", "st_mlp_targets", "st_track_surrogate")
+           "st_mlp_features", "st_mlp_targets", "st_track_surrogate", "st_measure_peaks")
 
 
 class st_element(ctypes.Structure):
@@ -45,6 +45,11 @@ class st_element(ctypes.Structure):
                 ("k1", ctypes.c_double), ("k1l", ctypes.c_double), ("k2l", ctypes.c_double),
                 ("snake_phi", ctypes.c_double), ("snake_mu", ctypes.c_double),
                 ("ks", ctypes.c_double), ("asym", ctypes.c_double)]
+
+
+class st_peaks(ctypes.Structure):
+    _fields_ = [("fp64_fma_tflops", ctypes.c_double), ("bf16_mfma_tflops", ctypes.c_double),
+                ("copy_gbps", ctypes.c_double)]
 
 
 class st_beam(ctypes.Structure):
@@ -88,6 +93,7 @@ def _load():
     lib.st_mlp_features.argtypes = [vp, vp, i64, P(f64), P(f64), f64, vp, vp]
     lib.st_mlp_targets.argtypes = [vp, vp, i64, P(f64), vp, vp]
     lib.st_track_surrogate.argtypes = [vp, vp, i64, ctypes.c_int32, f64, P(f64), P(f64), f64, vp, vp]
+    lib.st_measure_peaks.argtypes = [i32, P(st_peaks)]
     for name in EXPORTS:
         if name not in ("st_last_error", "st_mlp_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -113,6 +119,17 @@ def st_create(device: int = 0):
     if st != ST_OK:
         raise SpinTrackError(st, f"cannot create a context on device {device}")
     return h
+
+
+def st_measure_peaks(device: int = 0) -> dict:
+    """FP64 FMA and bf16 MFMA rates [TFLOP/s] and HBM copy bandwidth [GB/s]
+    measured on `device`."""
+    p = st_peaks()
+    st = LIB.st_measure_peaks(int(device), ctypes.byref(p))
+    if st != ST_OK:
+        raise SpinTrackError(st, f"peak microbenchmarks failed on device {device}")
+    return {"fp64_fma_tflops": p.fp64_fma_tflops, "bf16_mfma_tflops": p.bf16_mfma_tflops,
+            "copy_gbps": p.copy_gbps}
 
 
 def st_destroy(ctx) -> None:

@@ -24,7 +24,8 @@ def test_header_declares_the_boundary():
                             "st_read_particles", "st_last_error", "st_mlp_create",
                             "st_mlp_destroy", "st_mlp_last_error", "st_mlp_params", "st_mlp_set_frame",
                             "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
-                            "st_mlp_features", "st_mlp_targets", "st_track_surrogate"])
+                            "st_mlp_features", "st_mlp_targets", "st_track_surrogate",
+                            "st_measure_peaks"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -41,11 +42,13 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(binding.st_element) == 6 * 4 + 10 * 8
     assert binding.st_element.L.offset == 24
     assert ctypes.sizeof(binding.st_beam) == 3 * 8 + 2 * 4
+    assert ctypes.sizeof(binding.st_peaks) == 3 * 8
     text = open(HEADER).read()
     assert "int32_t kind, orbit, n_slices, romberg_rows, spin_place, fringe;" in text
     assert "double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks, asym;" in text
     assert "double G, gamma0, aperture;" in text
     assert "int32_t precision, report_every;" in text
+    assert "double fp64_fma_tflops, bf16_mfma_tflops, copy_gbps;" in text
 
 
 def test_null_context_and_bad_device_are_rejected_without_device_work():
@@ -62,6 +65,7 @@ def test_null_context_and_bad_device_are_rejected_without_device_work():
     assert lib.st_mlp_destroy(None) == B.ST_OK
     assert lib.st_mlp_set_frame(None, None, None) == B.ST_EINVAL
     assert lib.st_track_surrogate(None, None, 1, 1, 0.0, None, None, 0.0, None, None) == B.ST_EINVAL
+    assert lib.st_measure_peaks(0, None) == B.ST_EINVAL
     with pytest.raises(B.SpinTrackError):
         B.st_create(-1)
 
