@@ -6,6 +6,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "lattice_table.h"
@@ -429,8 +430,12 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   }
   const double beta0 = std::sqrt(1.0 - 1.0 / (b->gamma0 * b->gamma0));
 
-  // compress: unique elements + index sequence
+  // compress: unique elements (equal bytes: st_element has no padding) and
+  // the index sequence
+  static_assert(sizeof(st_element) == 6 * sizeof(int32_t) + 10 * sizeof(double),
+                "st_element must have no padding bytes");
   std::vector<st_element> uniq;
+  std::unordered_map<std::string, uint32_t> index;
   std::vector<uint32_t> seq((size_t)n);
   double theta = 0.0;
   bool ext = false;
@@ -438,15 +443,18 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
     ext = ext || els[i].orbit == ST_ORB_TEAPOT || els[i].orbit == ST_ORB_DKD4 ||
           els[i].orbit == ST_ORB_MK4 || els[i].spin_place != ST_SPIN_EDGES ||
           els[i].kind == ST_SOLENOID || els[i].kind == ST_RBEND || els[i].fringe != 0;
-    int k = -1;
-    for (size_t u = 0; u < uniq.size(); ++u)
-      if (std::memcmp(&uniq[u], &els[i], sizeof(st_element)) == 0) { k = (int)u; break; }
-    if (k < 0) {
+    const std::string key(reinterpret_cast<const char*>(&els[i]), sizeof(st_element));
+    auto it = index.find(key);
+    uint32_t k;
+    if (it != index.end()) {
+      k = it->second;
+    } else {
       if (uniq.size() >= 65535) return fail(c, ST_EINVAL, "more than 65535 distinct elements");
+      k = (uint32_t)uniq.size();
       uniq.push_back(els[i]);
-      k = (int)uniq.size() - 1;
+      index.emplace(key, k);
     }
-    seq[(size_t)i] = (uint32_t)k;
+    seq[(size_t)i] = k;
     theta = std::max(theta, design_angle(els[i], *b, 0.02));
   }
   std::vector<st::DevElem> tab(std::max<size_t>(uniq.size(), 1));

@@ -204,6 +204,36 @@ def test_empty_and_single_particle():
     assert_parity(g, o, "n=1")
 
 
+def test_empty_and_drift_only_lattices():
+    # no elements: every turn is the identity and the polarization is the
+    # mean spin; drifts alone move the orbit and leave the spin exactly as it
+    # was (no field, Ω = 0)
+    z, s, a = gaussian_bunch(100, 5, BEAM)
+    g, o = both([], BEAM, z, s, a, turns=3, report_every=1)
+    np.testing.assert_array_equal(g["z"], z)
+    np.testing.assert_array_equal(g["spin"], s)
+    np.testing.assert_allclose(g["pol"], o["pol"], rtol=0, atol=SPIN_TOL)
+    g, o = both([drift(2.0), drift(3.5)], BEAM, z, s, a, turns=3)
+    assert_parity(g, o, "drifts")
+    np.testing.assert_array_equal(g["spin"], s)
+
+
+def test_distinct_element_limit():
+    # the element table holds up to 65535 distinct records; a ring of that
+    # many distinct drifts loads, one more is rejected before device work
+    from paper_1501_03450_amd import binding as B
+    beam = B.st_beam(G=1.79, gamma0=25.0, aperture=0.1, precision=0, report_every=0)
+    ctx = B.st_create(0)
+    elems = [drift(1.0 + 1e-6 * i) for i in range(65536)]
+    assert B.st_load_lattice_raw(ctx, B.element_array(elems[:65535]), 65535, beam) == B.ST_OK
+    assert B.st_load_lattice_raw(ctx, B.element_array(elems), 65536, beam) == B.ST_EINVAL
+    assert "65535" in B.st_last_error(ctx)
+    # repeats of the same records do not count against the limit
+    arr = B.element_array(elems[:1000] * 70)
+    assert B.st_load_lattice_raw(ctx, arr, 70000, beam) == B.ST_OK
+    B.st_destroy(ctx)
+
+
 def test_losses_flag_the_same_element_and_freeze_the_state():
     z, s, a = gaussian_bunch(300, 31, BEAM)
     beam = Beam(aperture=0.02)
