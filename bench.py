@@ -119,8 +119,8 @@ def parse():
     ap.add_argument("--scan-thresholds", type=str, default=None,
                     help="comma-separated audit thresholds of the surrogate scans "
                          "(default: --threshold, 1e-4 and 1e-2)")
-    ap.add_argument("--band-train-per-energy", type=int, default=65536)
-    ap.add_argument("--band-epochs", type=int, default=600)
+    ap.add_argument("--band-train-per-energy", type=int, default=262144)
+    ap.add_argument("--band-epochs", type=int, default=300)
     ap.add_argument("--c3", action="store_true",
                     help="full surrogate training run: 2^24 widened samples labelled by one "
                          "double-precision turn, batch 65536")
