@@ -1,6 +1,6 @@
 """The mixed-precision modes: single-precision edge quaternions and level
 products with compensated sums, double-precision orbit, tableau and
-composition.  Judged against the double-precision run from identical states
+composition.  Measured against the double-precision run from identical states
 (there is no paper pin for it): the orbit is unchanged bit for bit, and in
 ST_MIXED (single precision where the finest-slice rotation is small) the
 spin error per turn stays below 1e-6.  ST_MIXED_ALL (single precision in

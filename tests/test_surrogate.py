@@ -4,7 +4,7 @@ update, training on tracked one-turn quaternions, and surrogate tracking
 with audits and fallback through the C ABI.
 
 There is no paper pin for the surrogate (it is not part of the method); the
-plain double-precision tracker is the judge of its spin error."""
+plain double-precision tracker is what its spin error is measured against."""
 
 import numpy as np
 import pytest
