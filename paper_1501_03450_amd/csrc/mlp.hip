@@ -107,6 +107,35 @@ __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const flo
   }
 }
 
+// Backward epilogue of a hidden layer: dz = acc ⊙ silu'(z) into LDS (bf16,
+// row-major), z read from HBM sample-major.  The pre-activations of one
+// 16-sample block are loaded together, the four 16-feature pieces of a row
+// back to back, so that both halves of each 128-byte line are requested at
+// once (requested apart, a line can leave the L2 in between and be fetched
+// twice).
+__device__ __forceinline__ void backward_epilogue(const f32x4 acc[4][4], const float* zS,
+                                                  __bf16* out_lds, int64_t b0, int rows,
+                                                  int n_base, int lane) {
+  const int c = lane & 15, rq = 4 * (lane >> 4);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int m0 = mt * 16 + rq;
+    float zv[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        zv[i][nt] = m0 + i < rows ? zS[(size_t)(b0 + m0 + i) * W + n_base + nt * 16 + c] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const float dz = m0 + i < rows ? acc[mt][nt][i] * dsilu(zv[i][nt]) : 0.0f;
+        out_lds[(m0 + i) * LDA + n_base + nt * 16 + c] = (__bf16)dz;
+      }
+  }
+}
+
 // Copy a 64-sample × 256-feature bf16 tile from LDS (sample-major, pitch
 // LDA) to HBM feature-major [256][ld] at column b0: eight lanes write the 128
 // contiguous bytes of one feature.
@@ -293,25 +322,11 @@ mlp_backward_data_kernel(const MlpArgs a) {
   store_feature_major(bufA, a.dzT3, a.ld, b0, tid);
 
   f32x4 acc[4][4];
-  const int c = lane & 15, rq = 4 * (lane >> 4);
   // dz2 = (dz3 W3) ⊙ silu'(z2)
   zero_acc(acc);
   gemm_64x64(bufA, a.W3Tb, wv * 64, acc, lane);
   __syncthreads();   // bufA is overwritten below
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const int n = wv * 64 + nt * 16 + c;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      const int m0 = mt * 16 + rq;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float dz = 0.0f;
-        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zS2[(size_t)(b0 + m0 + i) * W + n]);
-        bufA[(m0 + i) * LDA + n] = (__bf16)dz;
-      }
-    }
-  }
+  backward_epilogue(acc, a.zS2, bufA, b0, rows, wv * 64, lane);
   __syncthreads();
   store_feature_major(bufA, a.dzT2, a.ld, b0, tid);
   {
@@ -323,20 +338,7 @@ mlp_backward_data_kernel(const MlpArgs a) {
   zero_acc(acc);
   gemm_64x64(bufA, a.W2Tb, wv * 64, acc, lane);
   __syncthreads();   // bufA is reused below
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const int n = wv * 64 + nt * 16 + c;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      const int m0 = mt * 16 + rq;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float dz = 0.0f;
-        if (m0 + i < rows) dz = acc[mt][nt][i] * dsilu(a.zS1[(size_t)(b0 + m0 + i) * W + n]);
-        bufA[(m0 + i) * LDA + n] = (__bf16)dz;
-      }
-    }
-  }
+  backward_epilogue(acc, a.zS1, bufA, b0, rows, wv * 64, lane);
   __syncthreads();
   {
     const int n = tid;
