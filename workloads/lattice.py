@@ -15,8 +15,9 @@ Element kinds
           axis (sin mu, 0, cos mu) in (x, y, s); transparent to the orbit
   solenoid  longitudinal field ks = b0/(Bρ)0 over L with thin-pancake fringes
   rbend   rectangular bend of straight length L bending the design orbit by
-          `angle`, entered and left symmetrically (half the angle at each
-          face); eta is the powering ratio
+          `angle`; the design orbit meets the entrance face at angle/2 + asym
+          and the exit face at asym - angle/2 (asym = 0: symmetric); eta is
+          the powering ratio
   marker  does nothing
 
 Orbit integration methods
@@ -209,18 +210,24 @@ def lattice_summary(elements: Sequence[Element]) -> dict:
     counts = {}
     for e in elements:
         counts[e.kind] = counts.get(e.kind, 0) + 1
+    def path_length(e):
+        # a rectangular bend's straight length L spans the design arc of
+        # radius L/(2 cos(asym) sin(angle/2))
+        if e.kind == "rbend":
+            return e.L * e.angle / (2.0 * math.cos(e.asym) * math.sin(e.angle / 2.0))
+        return e.L
     return {
         "n_elements": len(elements),
-        "circumference_m": float(sum(e.L for e in elements)),
+        "circumference_m": float(sum(path_length(e) for e in elements)),
         "total_bend_angle": float(sum(e.angle for e in elements)),
         "counts": counts,
     }
 
 
 ELEMENT_DTYPE = np.dtype([
-    ("kind", "U8"), ("method", "U8"), ("n_slices", "i4"), ("rows", "i4"),
-    ("L", "f8"), ("angle", "f8"), ("eta", "f8"), ("k1", "f8"), ("k1l", "f8"),
-    ("k2l", "f8"), ("snake_phi", "f8"), ("snake_mu", "f8"),
+    ("kind", "U8"), ("method", "U8"), ("spin", "U8"), ("n_slices", "i4"), ("rows", "i4"),
+    ("fringe", "i4"), ("L", "f8"), ("angle", "f8"), ("eta", "f8"), ("k1", "f8"), ("k1l", "f8"),
+    ("k2l", "f8"), ("snake_phi", "f8"), ("snake_mu", "f8"), ("ks", "f8"), ("asym", "f8"),
 ])
 
 
@@ -228,6 +235,6 @@ def element_table(elements: Sequence[Element]) -> np.ndarray:
     """Elements as a numpy structured array (names for kind and method)."""
     out = np.zeros(len(elements), dtype=ELEMENT_DTYPE)
     for i, e in enumerate(elements):
-        out[i] = (e.kind, e.method, e.n_slices, e.rows, e.L, e.angle, e.eta,
-                  e.k1, e.k1l, e.k2l, e.snake_phi, e.snake_mu)
+        out[i] = (e.kind, e.method, e.spin, e.n_slices, e.rows, int(e.fringe), e.L, e.angle,
+                  e.eta, e.k1, e.k1l, e.k2l, e.snake_phi, e.snake_mu, e.ks, e.asym)
     return out
