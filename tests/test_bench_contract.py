@@ -14,3 +14,17 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""        # no JSON line for a refused run
+
+
+def test_committed_traffic_record_is_for_the_committed_tracking_kernel():
+    # The bench line's roofline.traffic comes from the rocprofv3 record under
+    # profiles/, keyed by a hash of the tracking kernel's sources: it must be
+    # the record of this kernel (else the bench reports null), and of the
+    # right size, above the 2 x 76 B of state per particle and within the
+    # spilled registers' share of it.
+    sys.path.insert(0, ROOT)
+    import bench
+    traffic = bench.recorded_traffic(1 << 20, 100)
+    assert traffic is not None
+    algorithmic = 2 * 76 * (1 << 20)
+    assert algorithmic < traffic < 2.5 * algorithmic
