@@ -153,14 +153,22 @@ typedef struct {
   int32_t precision, report_every;
 } st_beam;
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * Passage: §6 — the bunch is moved to the GPU's global memory and tracked
+ * there; a context is that device plus the lattice tables and scratch the
+ * tracking needs. */
 st_status st_create(st_ctx** out, int device);
 
 /* Release the context and everything the library allocated for it.
- * Caller-owned particle memory is not touched.  NULL is accepted. */
+ * Caller-owned particle memory is not touched.  NULL is accepted.
+ * Passage: not in the paper (resource management). */
 st_status st_destroy(st_ctx* ctx);
 
-/* Copy n elements (host memory) and the beam into the context.  Validation:
+/* Copy n elements (host memory) and the beam into the context.
+ * Passage: the element maps of §3 (§3.1 eq. sbend, §3.2 eq. rbend, §3.3
+ * eq. quadL/quadNL/quadConcat, §3.4 eq. HmultD, §3.5, §3.6 eq. teapotD, §3.7
+ * eq. solenoid), the spin placements of §4.1 and §4.3, the fringe kicks of
+ * §4.4 and §4.5; units of §2.1.  Validation:
  * known kind, orbit method and spin placement; finite parameters; L ≥ 0;
  * sbends need L > 0, angle ≠ 0, the exact or TEAPOT method and, with the
  * exact method, eta > 0; quadrupoles need L > 0 and the DKD, MK, DKD4 or MK4
@@ -175,23 +183,35 @@ st_status st_load_lattice(st_ctx* ctx, const st_element* host_elems, int64_t n,
                           const st_beam* beam);
 
 /* Bind n particles held in caller-owned device memory (layout above).
- * n may be 0.  Pointers must be non-NULL when n > 0. */
+ * n may be 0.  Pointers must be non-NULL when n > 0.
+ * Passage: §6 — one GPU thread per particle, whose 6-D orbit (§2.1 eq.
+ * psvars) and 3-D spin (§2.2) stay in global memory for the whole run. */
 st_status st_bind_particles(st_ctx* ctx, int64_t n, double* d_z, double* d_spin,
                             int32_t* d_alive);
 
-/* Optionally bind a device array q (4 rows of n doubles: w, x, y, z) that
+/* Passage: §6 (the quaternions that accumulate spin rotations belong to the
+ * resident state) and §4.1 (the element rotations compose as quaternions).
+ * Optionally bind a device array q (4 rows of n doubles: w, x, y, z) that
  * st_track fills with each particle's one-turn spin quaternion of the last
  * turn it tracked (the product of the element quaternions, later elements on
  * the left).  NULL unbinds.  Must follow st_bind_particles. */
 st_status st_bind_quaternions(st_ctx* ctx, double* d_q);
 
-/* Track the bound particles for `turns` turns (≥ 0), asynchronously on
+/* Passage: §6 (the push of every particle through each element: orbit by
+ * the element's integrator, Ω recorded at every slice edge, the quaternion
+ * updated by piece-wise constant spin integration plus Romberg steps, then
+ * the spin), with the orbit maps of §3, Ω of §2.2 eq. t-bmt.so, the slice
+ * rotations of §4.1 and the tableau of §4.3 eq. romberg.
+ * Track the bound particles for `turns` turns (≥ 0), asynchronously on
  * `stream`.  Updates z, spin, alive (and q if bound) in place and records
  * the polarization history of this call.  Each call starts at the lattice
  * start, so track(a + b) equals track(a) followed by track(b). */
 st_status st_track(st_ctx* ctx, int64_t turns, void* stream);
 
-/* Polarization history of the last st_track: for each report k, four doubles
+/* Passage: not a formula of the paper.  §6 copies particle data back to the
+ * host for analysis such as the invariant spin field (§1); this call gives
+ * the plain bunch-mean spin of that analysis on the device instead.
+ * Polarization history of the last st_track: for each report k, four doubles
  * (Px, Py, Pz, N_alive) with P = Σ_alive S_j / N_alive (0 if none alive).
  * Writes min(capacity, n_reports) reports to caller-owned DEVICE memory
  * d_out, queued on `stream`; *n_reports (host) receives the number of
@@ -200,12 +220,14 @@ st_status st_polarization(st_ctx* ctx, double* d_out, int64_t capacity,
                           int64_t* n_reports, void* stream);
 
 /* Copy the bound particles to HOST memory (any pointer may be NULL to skip
- * that array).  Synchronises `stream` before returning. */
+ * that array).  Synchronises `stream` before returning.
+ * Passage: §6 — particle data is copied back to the host for analysis. */
 st_status st_read_particles(st_ctx* ctx, double* h_z, double* h_spin, int32_t* h_alive,
                             void* stream);
 
 /* Human-readable description of the last error on this context (owned by
- * the context; valid until the next call).  Never NULL. */
+ * the context; valid until the next call).  Never NULL.
+ * Passage: not in the paper (error reporting). */
 const char* st_last_error(const st_ctx* ctx);
 
 /* ------------------------------------------------------------------------
@@ -222,23 +244,28 @@ const char* st_last_error(const st_ctx* ctx);
  * ------------------------------------------------------------------------ */
 typedef struct st_mlp st_mlp;
 
-/* Create a network on HIP device `device` with n_in inputs (1..8) and hidden
+/* Passage: not in the paper (learned spin surrogate).
+ * Create a network on HIP device `device` with n_in inputs (1..8) and hidden
  * width 256 (the only width supported).  Weights are uniform in
  * ±1/sqrt(fan_in) from a counter-based generator keyed by `seed`; biases 0. */
 st_status st_mlp_create(st_mlp** out, int device, int32_t n_in, int32_t width, uint64_t seed);
 
-/* Release the network.  NULL is accepted. */
+/* Release the network.  NULL is accepted.
+ * Passage: not in the paper (learned spin surrogate). */
 st_status st_mlp_destroy(st_mlp* m);
 
-/* Last error on this network (owned by it; never NULL). */
+/* Last error on this network (owned by it; never NULL).
+ * Passage: not in the paper (learned spin surrogate). */
 const char* st_mlp_last_error(const st_mlp* m);
 
-/* Copy the fp32 master parameters to h_get and/or replace them from h_set
+/* Passage: not in the paper (learned spin surrogate).
+ * Copy the fp32 master parameters to h_get and/or replace them from h_set
  * (host memory, *n_params floats; either pointer may be NULL).  *n_params
  * (host, may be NULL) receives the count.  Synchronous. */
 st_status st_mlp_params(st_mlp* m, float* h_get, const float* h_set, int64_t* n_params);
 
-/* Output frame of the network: with the last layer's output y, the
+/* Passage: not in the paper (learned spin surrogate).
+ * Output frame of the network: with the last layer's output y, the
  * prediction is q = u/|u| for u = ref + scale ⊙ y (ref, scale: host, 4
  * doubles each, finite, scale > 0; stored as floats).  A reference
  * quaternion close to the targets and a scale of their spread around it let
@@ -247,45 +274,57 @@ st_status st_mlp_params(st_mlp* m, float* h_get, const float* h_set, int64_t* n_
  * gradients, inference and surrogate tracking alike. */
 st_status st_mlp_set_frame(st_mlp* m, const double* ref, const double* scale);
 
-/* One Adam step (learning rate lr > 0) on `batch` samples: inputs d_x, unit
+/* Passage: not in the paper (learned spin surrogate).
+ * One Adam step (learning rate lr > 0) on `batch` samples: inputs d_x, unit
  * quaternion targets d_t (device).  d_loss (device, 1 float, may be NULL)
  * receives the batch's mean loss before the step.  Queued on `stream`. */
 st_status st_mlp_train_step(st_mlp* m, const float* d_x, const float* d_t, int64_t batch,
                             float lr, float* d_loss, void* stream);
 
-/* Gradient of the batch's mean loss into d_grad (device, n_params floats)
+/* Passage: not in the paper (learned spin surrogate).
+ * Gradient of the batch's mean loss into d_grad (device, n_params floats)
  * without updating the weights; d_loss as in st_mlp_train_step. */
 st_status st_mlp_gradient(st_mlp* m, const float* d_x, const float* d_t, int64_t batch,
                           float* d_grad, float* d_loss, void* stream);
 
-/* Inference: d_q [n][4] (device) from d_x [n][n_in] (device). */
+/* Inference: d_q [n][4] (device) from d_x [n][n_in] (device).
+ * Passage: not in the paper (learned spin surrogate). */
 st_status st_mlp_infer(st_mlp* m, const float* d_x, float* d_q, int64_t n, void* stream);
 
-/* Network inputs from particle coordinates (d_z: device 6×n SoA doubles):
+/* Passage: not in the paper (learned spin surrogate).
+ * Network inputs from particle coordinates (d_z: device 6×n SoA doubles):
  * x[j][i] = (z[i][j] - center[i]) * inv_scale[i] for i < 6 and, when
  * n_in == 7, x[j][6] = extra.  center, inv_scale: host, 6 doubles. */
 st_status st_mlp_features(st_mlp* m, const double* d_z, int64_t n, const double* center,
                           const double* inv_scale, double extra, float* d_x, void* stream);
 
-/* Training targets from tracked one-turn quaternions (d_q: device 4×n SoA
+/* Passage: not in the paper (learned spin surrogate); the targets are the
+ * one-turn quaternions of §4.1 composed by st_track.
+ * Training targets from tracked one-turn quaternions (d_q: device 4×n SoA
  * doubles, as filled by st_track with st_bind_quaternions): t[j] = ±q_j
  * with the sign that makes t·ref >= 0 (ref: host, 4 doubles), as floats. */
 st_status st_mlp_targets(st_mlp* m, const double* d_q, int64_t n, const double* ref, float* d_t,
                          void* stream);
 
-/* Track the bound particles for `turns` turns with the surrogate for spin.
+/* Passage: not in the paper (learned spin surrogate with audits); its
+ * audit and fallback turns are the method of st_track.
+ * Track the bound particles for `turns` turns with the surrogate for spin.
  * Each turn a particle with d_fallback[j] == 0 gets the orbit push and a spin
  * rotation by the network's quaternion for its turn-start coordinates
  * (inputs as in st_mlp_features); a particle with d_fallback[j] != 0 gets the
- * full double-precision turn.  On the first turn of the call and on every
- * audit_every-th turn (>= 1) every particle gets the full double-precision
- * turn and its network quaternion is compared with the tracked one (the early
- * audit finds the particles the network cannot follow before they cost a
- * long replay).  When the largest component difference (after
- * aligning the sign) exceeds `threshold`, the particle falls back: d_fallback[j]
- * is set to the turn number (1-based), its state is rolled back to the
- * previous audit (or the start) and the turns since then are replayed in
- * double precision, so its spin carries no network error; it stays on the
+ * full double-precision turn.  On the first turn of the call, on every
+ * audit_every-th turn (>= 1) and on the call's last turn, every particle gets
+ * the full double-precision turn and its network quaternion is compared with
+ * the tracked one (the early audit finds the particles the network cannot
+ * follow before they cost a long replay; the closing one leaves no network
+ * turn unchecked).  When the largest component difference (after aligning
+ * the sign) exceeds `threshold`, the particle falls back: d_fallback[j] is
+ * set to the turn number (1-based, counted within this call), its state is
+ * rolled back to the previous audit (or the start) and the turns since then
+ * are replayed in double precision, so its spin carries no network error.
+ * Only particles with d_fallback[j] == 0 are audited, so a non-zero value
+ * left by an earlier call or set by the caller is never rolled back again:
+ * such a particle runs every turn in double precision.  It stays on the
  * double-precision path afterwards.  The orbit is the double-precision orbit
  * throughout.  d_fallback: device int32 [n], initialised by the caller (0 =
  * start on the network).  Polarization is recorded as in st_track; the
@@ -311,7 +350,8 @@ typedef struct {
   double fp64_fma_tflops, bf16_mfma_tflops, copy_gbps;
 } st_peaks;
 
-/* Run the three microbenchmarks on HIP device `device` and fill *out.
+/* Passage: not in the paper (measurement).
+ * Run the three microbenchmarks on HIP device `device` and fill *out.
  * Synchronous; allocates and frees 2 GiB of device memory.  ST_EINVAL for a
  * NULL out or an unknown device, ST_EDEVICE if an allocation, launch or timing
  * call fails (out is then incomplete). */

@@ -76,15 +76,23 @@ def _frame(y, ref, scale):
     return ref + scale * y
 
 
-def loss(params, x, t, ref=None, scale=None):
-    q, _ = forward(params, x, ref=ref, scale=scale)
+def loss(params, x, t, ref=None, scale=None, round_act=None):
+    q, _ = forward(params, x, round_act=round_act, ref=ref, scale=scale)
     return float(np.mean(np.sum((q - t) ** 2, axis=1)))
 
 
-def backward(params, x, t, ref=None, scale=None):
-    """Gradients of L with respect to every parameter (same order)."""
+def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None):
+    """Gradients of L with respect to every parameter (same order).
+
+    With round_act and round_dz (both None: plain float64) the gradient
+    follows the GPU kernels' rounding points: the hidden activations rounded
+    as in forward(); the back-propagated dz of each hidden layer rounded
+    before it enters the next product (dz3 after its bias gradient is
+    summed, dz2 and dz1 before theirs), as the kernels hold them in bf16."""
     W1, b1, W2, b2, W3, b3, W4, b4 = params
-    q, (x, z1, h1, z2, h2, z3, h3, u) = forward(params, x, ref=ref, scale=scale)
+    rd = round_dz if round_dz is not None else (lambda v: v)
+    q, (x, z1, h1, z2, h2, z3, h3, u) = forward(params, x, round_act=round_act, ref=ref,
+                                                scale=scale)
     B = x.shape[0]
     dq = 2.0 * (q - t) / B
     nu = np.linalg.norm(u, axis=1, keepdims=True)
@@ -93,12 +101,13 @@ def backward(params, x, t, ref=None, scale=None):
     gW4 = dy.T @ h3
     gb4 = dy.sum(0)
     dz3 = (dy @ W4) * dsilu(z3)
-    gW3 = dz3.T @ h2
     gb3 = dz3.sum(0)
-    dz2 = (dz3 @ W3) * dsilu(z2)
+    dz3 = rd(dz3)
+    gW3 = dz3.T @ h2
+    dz2 = rd((dz3 @ W3) * dsilu(z2))
     gW2 = dz2.T @ h1
     gb2 = dz2.sum(0)
-    dz1 = (dz2 @ W2) * dsilu(z1)
+    dz1 = rd((dz2 @ W2) * dsilu(z1))
     gW1 = dz1.T @ x
     gb1 = dz1.sum(0)
     return [gW1, gb1, gW2, gb2, gW3, gb3, gW4, gb4]

@@ -52,6 +52,7 @@ struct st_ctx {
   double* d_ck = nullptr;      // checkpoint of the last audit: z (6 × n) then spin (3 × n)
   int32_t* d_ck_alive = nullptr;
   int32_t* d_ralive = nullptr; // live set of a replay
+  int32_t* d_failed = nullptr; // particles that failed the last audit
   int32_t* d_perm = nullptr;   // lane order of the surrogate turns
   int32_t* d_rperm = nullptr;  // lane order of a replay
   int32_t* d_pcount = nullptr; // partition counts and offsets, 3 per 256 particles
@@ -400,8 +401,8 @@ st_status st_destroy(st_ctx* c) {
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_pol) (void)hipFree(c->d_pol);
     for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
-                    (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_perm, (void*)c->d_rperm,
-                    (void*)c->d_pcount, (void*)c->d_poff})
+                    (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_failed, (void*)c->d_perm,
+                    (void*)c->d_rperm, (void*)c->d_pcount, (void*)c->d_poff})
       if (p) (void)hipFree(p);
   }
   delete c;
@@ -606,11 +607,12 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   const int64_t n = c->n;
   if (n > c->surr_cap) {
     for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
-                    (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_perm, (void*)c->d_rperm,
-                    (void*)c->d_pcount, (void*)c->d_poff})
+                    (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_failed, (void*)c->d_perm,
+                    (void*)c->d_rperm, (void*)c->d_pcount, (void*)c->d_poff})
       if (p) (void)hipFree(p);
     c->d_feat = nullptr; c->d_qnn = nullptr; c->d_q64 = nullptr; c->d_ck = nullptr;
-    c->d_ck_alive = nullptr; c->d_ralive = nullptr; c->d_perm = nullptr; c->d_rperm = nullptr;
+    c->d_ck_alive = nullptr; c->d_ralive = nullptr; c->d_failed = nullptr; c->d_perm = nullptr;
+    c->d_rperm = nullptr;
     c->d_pcount = nullptr; c->d_poff = nullptr; c->surr_cap = 0;
     const size_t nparts = (size_t)((n + 255) / 256) * 3;
     if ((e = hipMalloc(&c->d_feat, (size_t)n * 8 * sizeof(float))) != hipSuccess ||
@@ -619,6 +621,7 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
         (e = hipMalloc(&c->d_ck, (size_t)n * 9 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->d_ck_alive, (size_t)n * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_ralive, (size_t)n * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_failed, (size_t)n * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_perm, (size_t)n * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_rperm, (size_t)n * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_pcount, nparts * sizeof(int32_t))) != hipSuccess ||
@@ -649,7 +652,8 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   // lane order: particles on the network first, then the fallback ones, so
   // that waves take one path or the other
   auto order = [&]() -> hipError_t {
-    return st::launch_partition(0, 0, c->alive, d_fallback, n, c->d_pcount, c->d_poff, c->d_perm, s);
+    return st::launch_partition(0, nullptr, c->alive, d_fallback, n, c->d_pcount, c->d_poff,
+                                c->d_perm, s);
   };
   if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");
   int64_t last_audit = 0;
@@ -658,25 +662,26 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
     if (ms == ST_OK) ms = st_mlp_infer(m, c->d_feat, c->d_qnn, n, stream);
     if (ms != ST_OK) return fail(c, ms, std::string("network: ") + st_mlp_last_error(m));
     // audits: after the first turn, so that particles the network cannot
-    // follow are found before a long replay, then every audit_every-th turn
-    const bool audit = t % audit_every == 0 || t == 1;
+    // follow are found before a long replay, then every audit_every-th turn,
+    // and after the last turn of the call, so that no network turn goes
+    // unchecked
+    const bool audit = t % audit_every == 0 || t == 1 || t == turns;
     st::TrackArgs a = track_args(c);
     a.turns = 1;
     if (audit) {
       a.qout = c->d_q64;
       if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "audit turn");
-      if ((e = st::launch_audit(c->alive, d_fallback, c->d_qnn, c->d_q64, n, threshold, (int32_t)t,
-                                s)) != hipSuccess)
+      if ((e = st::launch_audit(c->alive, d_fallback, c->d_failed, c->d_qnn, c->d_q64, n, threshold,
+                                (int32_t)t, s)) != hipSuccess)
         return hip_fail(c, e, "audit");
       // Roll the particles that failed back to the last checkpoint and replay
       // the turns since then in double precision; the orbit is the same as on
       // the surrogate path, so only their spins change.
-      if ((e = st::launch_replay_prepare(d_fallback, (int32_t)t, c->z, c->spin, c->d_ck,
-                                         c->d_ck + 6 * n, c->d_ck_alive, c->d_ralive, n, s)) !=
-          hipSuccess)
+      if ((e = st::launch_replay_prepare(c->d_failed, c->z, c->spin, c->d_ck, c->d_ck + 6 * n,
+                                         c->d_ck_alive, c->d_ralive, n, s)) != hipSuccess)
         return hip_fail(c, e, "rollback");
-      if ((e = st::launch_partition(1, (int32_t)t, c->alive, d_fallback, n, c->d_pcount, c->d_poff,
-                                    c->d_rperm, s)) != hipSuccess)
+      if ((e = st::launch_partition(1, c->d_failed, c->alive, d_fallback, n, c->d_pcount,
+                                    c->d_poff, c->d_rperm, s)) != hipSuccess)
         return hip_fail(c, e, "replay order");
       st::TrackArgs r = track_args(c);
       r.alive = c->d_ralive;
@@ -685,8 +690,7 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
       r.report_every = 0;
       r.partials = nullptr;
       if ((e = st::launch_track(r, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "replay");
-      if ((e = st::launch_replay_finish(d_fallback, (int32_t)t, c->d_ralive, c->alive, n, s)) !=
-          hipSuccess)
+      if ((e = st::launch_replay_finish(c->d_failed, c->d_ralive, c->alive, n, s)) != hipSuccess)
         return hip_fail(c, e, "replay status");
       if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");
       if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");

@@ -305,7 +305,9 @@ mlp_backward_data_kernel(const MlpArgs a) {
           const float z = zv[u];
           const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
           dz = dh * dsilu(z);
-          const float h = silu(z);
+          // the activation as the forward pass used it (bf16), so that dW4
+          // is the gradient of the loss the forward pass computed
+          const float h = (float)(__bf16)silu(z);
           gw[0] = fmaf(dys[m][0], h, gw[0]);
           gw[1] = fmaf(dys[m][1], h, gw[1]);
           gw[2] = fmaf(dys[m][2], h, gw[2]);

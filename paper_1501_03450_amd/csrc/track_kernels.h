@@ -20,18 +20,24 @@ hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, bool ext, hipStr
 
 hipError_t launch_surrogate_spin(double* spin, const int32_t* alive, const int32_t* fallback,
                                  const float* qnn, int64_t n, hipStream_t s);
-hipError_t launch_audit(const int32_t* alive, int32_t* fallback, const float* qnn, const double* q64,
-                        int64_t n, double threshold, int32_t turn, hipStream_t s);
-hipError_t launch_replay_prepare(const int32_t* fallback, int32_t turn, double* z, double* spin,
+// Audit of the network quaternions against the tracked ones: failures get
+// fallback[j] = turn and failed[j] = 1; every other particle failed[j] = 0.
+hipError_t launch_audit(const int32_t* alive, int32_t* fallback, int32_t* failed, const float* qnn,
+                        const double* q64, int64_t n, double threshold, int32_t turn,
+                        hipStream_t s);
+// Rollback to the checkpoint, and status after the replay, of the particles
+// with failed[j] != 0.
+hipError_t launch_replay_prepare(const int32_t* failed, double* z, double* spin,
                                  const double* ck_z, const double* ck_spin, const int32_t* ck_alive,
                                  int32_t* ralive, int64_t n, hipStream_t s);
-hipError_t launch_replay_finish(const int32_t* fallback, int32_t turn, const int32_t* ralive,
-                                int32_t* alive, int64_t n, hipStream_t s);
+hipError_t launch_replay_finish(const int32_t* failed, const int32_t* ralive, int32_t* alive,
+                                int64_t n, hipStream_t s);
 // Lane order for surrogate tracking: a stable partition of 0..n-1 (see
-// partition_key); counts and offsets hold 3 ints per 256 particles.
-hipError_t launch_partition(int mode, int32_t turn, const int32_t* alive, const int32_t* fallback,
-                            int64_t n, int32_t* counts, int32_t* offsets, int32_t* perm,
-                            hipStream_t s);
+// partition_key; flag is the audit's failed[] array in mode 1); counts and
+// offsets hold 3 ints per 256 particles.
+hipError_t launch_partition(int mode, const int32_t* flag, const int32_t* alive,
+                            const int32_t* fallback, int64_t n, int32_t* counts, int32_t* offsets,
+                            int32_t* perm, hipStream_t s);
 hipError_t launch_polarization_partials(const double* spin, const int32_t* alive, int64_t n,
                                         double* partials, hipStream_t s);
 

@@ -79,3 +79,29 @@ def test_element_marshalling_follows_the_workload_records():
     assert kinds.count(B.ST_SBEND) == 264 and kinds.count(B.ST_QUAD) == 456
     assert kinds.count(B.ST_THIN) == 132 and kinds.count(B.ST_SNAKE) == 2
     assert all(arr[i].orbit == B.ST_ORB_MK for i in range(len(ring)) if arr[i].kind == B.ST_QUAD)
+
+
+def declaration_comments():
+    """Each declared function with the comment block just above its
+    declaration."""
+    text = open(HEADER).read()
+    out = {}
+    for m in re.finditer(r"^\s*(?:st_status|const char\*)\s+(st_\w+)\s*\(", text, re.M):
+        before = text[:m.start()].rstrip()
+        start = before.rfind("/*")
+        block = before[start:] if before.endswith("*/") else ""
+        out[m.group(1)] = block
+    return out
+
+
+def test_every_declaration_cites_its_passage_or_says_it_is_not_in_the_paper():
+    # Each entry point names the passage of the paper that defines what it
+    # does (a section or equation), or states that it is not in the paper.
+    blocks = declaration_comments()
+    assert set(blocks) == set(declared_functions())
+    for name, block in blocks.items():
+        m = re.search(r"Passage:\s*(.*)", block)
+        assert m, f"{name}: no 'Passage:' line in its comment"
+        cite = m.group(1)
+        assert "§" in cite or cite.lower().startswith(("not in the paper", "not a formula")), \
+            f"{name}: {cite!r}"

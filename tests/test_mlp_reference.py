@@ -72,3 +72,39 @@ def test_bf16_rounding_is_round_to_nearest_even():
     assert r[2] == 1.0 + 2 ** -7                            # above half way: rounds up
     assert r[3] == 1.0                                      # below half way: rounds down
     assert abs(r[4] + 3.140625) < 1e-12
+
+
+def test_rounded_backward_is_the_gradient_of_the_rounded_forward_in_the_last_layer():
+    # With the activations rounded (bf16, as the kernels hold them), the
+    # rounded network is still differentiable in W4 and b4 (the rounded h3
+    # does not depend on them): those two gradients must match central
+    # differences of the rounded loss.  Rounding dz changes only the tensors
+    # before the last layer, and by about the bf16 step.
+    params, x, t = _setup(batch=16)
+    frame = ((0.1, -0.3, 0.9, 0.2), (0.05, 0.02, 0.1, 0.03))
+    gr = M.backward(params, x, t, *frame, round_act=M.bf16_round, round_dz=M.bf16_round)
+    h = 1e-6
+    for k in (6, 7):
+        flat = params[k].ravel()
+        for idx in range(0, flat.size, max(1, flat.size // 12)):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = M.loss(params, x, t, *frame, round_act=M.bf16_round)
+            flat[idx] = old - h
+            lm = M.loss(params, x, t, *frame, round_act=M.bf16_round)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - gr[k].ravel()[idx]) <= 1e-6 * max(1e-3, abs(fd)), (k, idx)
+    g = M.backward(params, x, t, *frame)
+    for k in range(8):
+        rel = np.linalg.norm(gr[k] - g[k]) / np.linalg.norm(g[k])
+        assert rel < 2e-2, (k, rel)
+    assert not np.array_equal(gr[0], g[0])          # the rounding does reach dz1
+
+
+def test_identity_rounding_gives_the_plain_gradient():
+    params, x, t = _setup()
+    same = M.backward(params, x, t, round_act=lambda v: v, round_dz=lambda v: v)
+    plain = M.backward(params, x, t)
+    for a, b in zip(same, plain):
+        np.testing.assert_array_equal(a, b)

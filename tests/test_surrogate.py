@@ -108,32 +108,39 @@ def test_gradient_matches_the_cpu_reference_tensor_by_tensor(frame):
     B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), 1000, g.data_ptr(), loss.data_ptr())
     torch.cuda.synchronize()
     p = _cpu_params(_params(m), n_in)
-    g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64), ref, scale)
+    g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64), ref, scale,
+                       round_act=M.bf16_round, round_dz=M.bf16_round)
     g_gpu = M.unflatten(g.cpu().numpy(), n_in)
     for k, (a, b) in enumerate(zip(g_gpu, g_cpu)):
         assert _rel_fro(a, b) <= 1e-2, (k, _rel_fro(a, b))
-    l_cpu = M.loss(p, x.astype(np.float64), t.astype(np.float64), ref, scale)
+    l_cpu = M.loss(p, x.astype(np.float64), t.astype(np.float64), ref, scale,
+                   round_act=M.bf16_round)
     assert abs(loss.item() - l_cpu) <= 1e-3 * max(1.0, l_cpu)
     B.st_mlp_destroy(m)
 
 
-def test_gradient_of_a_large_ragged_batch_matches_the_cpu_reference():
+@pytest.mark.parametrize("targets", ["coherent", "random"])
+def test_gradient_of_a_large_ragged_batch_matches_the_cpu_reference(targets):
     # 70001 samples: 1094 tiles of 64, so the per-tile partials are reduced
-    # in two passes
+    # in two passes.  Coherent targets give a gradient that is a coherent
+    # sum; random unit targets about a fixed output frame give a cancelling
+    # one (the true gradient shrinks as 1/sqrt(B)), the regime near
+    # convergence.  The reference rounds where the kernels do.
     import torch
     from paper_1501_03450_amd import binding as B
     n_in, n = 6, 70001
     m = B.st_mlp_create(0, n_in, 256, seed=14)
     B.st_mlp_set_frame(m, *FRAME)
-    x, t = _coherent_data(n, n_in, 4)
+    x, t = (_coherent_data if targets == "coherent" else _data)(n, n_in, 4)
     dx, dt = _dev(x, np.float32), _dev(t, np.float32)   # keep both alive during the call
     g = torch.zeros(B.st_mlp_params(m), dtype=torch.float32, device="cuda")
     B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), n, g.data_ptr())
     torch.cuda.synchronize()
     p = _cpu_params(_params(m), n_in)
-    g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64), *FRAME)
+    g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64), *FRAME,
+                       round_act=M.bf16_round, round_dz=M.bf16_round)
     errs = [_rel_fro(a, b) for a, b in zip(M.unflatten(g.cpu().numpy(), n_in), g_cpu)]
-    print("per-tensor relative errors", [f"{e:.1e}" for e in errs])
+    print(f"{targets}: per-tensor relative errors", [f"{e:.1e}" for e in errs])
     assert max(errs) <= 1e-2, errs
     B.st_mlp_destroy(m)
 
