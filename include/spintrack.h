@@ -208,6 +208,34 @@ st_status st_bind_quaternions(st_ctx* ctx, double* d_q);
  * start, so track(a + b) equals track(a) followed by track(b). */
 st_status st_track(st_ctx* ctx, int64_t turns, void* stream);
 
+/* Size of the fixed device scratch array behind st_track_noalloc. */
+#define ST_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * st_track with every piece of device memory it needs already in place: it
+ * runs the same kernels (results bit-identical to st_track's) and calls no
+ * hipMalloc, hipFree or allocating library routine.  The per-block
+ * polarization partials live in a fixed array of ST_NOALLOC_SCRATCH_BYTES in
+ * device memory, one copy per GPU, whose address st_create takes; each GPU
+ * holds it until the process ends.  The caller passes the outputs: d_pol
+ * (caller-owned DEVICE memory, `capacity` reports of 4 doubles: Px, Py, Pz,
+ * N_alive, as in st_polarization) receives this call's polarization history,
+ * and *n_reports (host, may be NULL) the number of reports written.  The
+ * lattice must be loaded and the particles bound beforehand (those calls do
+ * allocate).
+ * Limits: reports x blocks x 4 doubles must fit the scratch array, with
+ * reports = turns / report_every and blocks = ceil(n / 256), i.e.
+ * reports x ceil(n / 256) <= 524288 (e.g. 128 reports of 2^20 particles);
+ * larger requests fail with ST_EINVAL before any device work, as does
+ * capacity < reports.  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents (every slot a call reads it writes first):
+ * calls that overlap in time on one GPU, from any context or stream, race
+ * and must be serialised by the caller.  st_polarization reports no history
+ * after this call. */
+st_status st_track_noalloc(st_ctx* ctx, int64_t turns, double* d_pol, int64_t capacity,
+                           int64_t* n_reports, void* stream);
+
 /* Passage: not a formula of the paper.  §6 copies particle data back to the
  * host for analysis such as the invariant spin field (§1); this call gives
  * the plain bunch-mean spin of that analysis on the device instead.

@@ -31,7 +31,7 @@ SPIN_CODES = {"edges": ST_SPIN_EDGES, "kick": ST_SPIN_KICK, "midpoint": ST_SPIN_
 PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED, "mixed_all": ST_MIXED_ALL}
 
 EXPORTS = ("st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
-           "st_bind_quaternions", "st_track", "st_polarization", "st_read_particles",
+           "st_bind_quaternions", "st_track", "st_track_noalloc", "st_polarization", "st_read_particles",
            "st_last_error", "st_mlp_create", "st_mlp_destroy", "st_mlp_last_error",
            "st_mlp_params", "st_mlp_set_frame", "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
            "st_mlp_features", "st_mlp_targets", "st_track_surrogate", "st_measure_peaks")
@@ -76,6 +76,7 @@ def _load():
     lib.st_bind_particles.argtypes = [vp, i64, vp, vp, vp]
     lib.st_bind_quaternions.argtypes = [vp, vp]
     lib.st_track.argtypes = [vp, i64, vp]
+    lib.st_track_noalloc.argtypes = [vp, i64, vp, i64, P(i64), vp]
     lib.st_polarization.argtypes = [vp, vp, i64, P(i64), vp]
     lib.st_read_particles.argtypes = [vp, vp, vp, vp, vp]
     lib.st_last_error.argtypes = [vp]
@@ -181,6 +182,14 @@ def st_bind_quaternions(ctx, q_ptr):
 
 def st_track(ctx, turns, stream=None):
     _check(ctx, LIB.st_track(ctx, int(turns), stream))
+
+
+def st_track_noalloc(ctx, turns, d_pol_ptr, capacity, stream=None) -> int:
+    """Track with no device allocation; returns the number of reports written."""
+    n = ctypes.c_int64(0)
+    _check(ctx, LIB.st_track_noalloc(ctx, int(turns), d_pol_ptr, int(capacity), ctypes.byref(n),
+                                     stream))
+    return int(n.value)
 
 
 def st_polarization(ctx, d_out_ptr=None, capacity=0, stream=None) -> int:

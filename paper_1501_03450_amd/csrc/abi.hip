@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -20,6 +21,7 @@ int st_mlp_inputs_of(const st_mlp* m);
 struct st_ctx {
   int device = 0;
   std::string err;
+  double* scratch = nullptr;   // this device's copy of the file-scope scratch array
   // lattice
   bool have_lattice = false;
   st_beam beam{};
@@ -59,6 +61,35 @@ struct st_ctx {
   int32_t* d_poff = nullptr;
   int64_t surr_cap = 0;
 };
+
+// Polarization partials of st_track_noalloc: a fixed array in device memory,
+// one copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is only a stand-in for
+// the device symbol); it uses the device address that hipGetSymbolAddress
+// returns, taken once per device by st_create.
+constexpr size_t kScratchDoubles = ST_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (resolved once).
+hipError_t scratch_address(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -376,6 +407,29 @@ st_status ensure_polarization(st_ctx* c, int64_t n_rep, int64_t nb) {
   return ST_OK;
 }
 
+// Queue one tracking launch and, with reports, the second pass of the
+// polarization reduction: partials holds reports x blocks x 4 doubles (every
+// slot is written by the tracking kernel before the reduction reads it), pol
+// receives 4 doubles per report.
+st_status launch_tracking(st_ctx* c, int64_t turns, double* partials, double* pol,
+                          hipStream_t s) {
+  const int64_t nb = (c->n + st::track_block_size() - 1) / st::track_block_size();
+  const int rep_every = c->beam.report_every;
+  const int64_t n_rep = rep_every > 0 ? turns / rep_every : 0;
+  st::TrackArgs a = track_args(c);
+  a.qout = c->qout;
+  a.turns = (int32_t)turns;
+  a.report_every = rep_every;
+  a.partials = partials;
+  hipError_t e;
+  if ((e = st::launch_track(a, c->nt, c->beam.precision != ST_FP64, c->ext, s)) != hipSuccess)
+    return hip_fail(c, e, "launch track");
+  if (n_rep > 0 &&
+      (e = st::launch_reduce_polarization(partials, (int)nb, (int)n_rep, pol, s)) != hipSuccess)
+    return hip_fail(c, e, "launch polarization reduction");
+  return ST_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -385,9 +439,17 @@ st_status st_create(st_ctx** out, int device) {
   *out = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return ST_EINVAL;
+  if (device >= kMaxDevices) return ST_EINVAL;
   st_ctx* c = new (std::nothrow) st_ctx();
   if (!c) return ST_ENOMEM;
   c->device = device;
+  {
+    DeviceGuard g(device);
+    if (scratch_address(device, &c->scratch) != hipSuccess) {
+      delete c;
+      return ST_EDEVICE;
+    }
+  }
   *out = c;
   return ST_OK;
 }
@@ -523,26 +585,44 @@ st_status st_track(st_ctx* c, int64_t turns, void* stream) {
   c->n_reports = 0;
   if (turns == 0 || c->n == 0) return ST_OK;
   DeviceGuard g(c->device);
-  hipStream_t s = (hipStream_t)stream;
-  const int bs = st::track_block_size();
-  const int64_t nb = (c->n + bs - 1) / bs;
+  const int64_t nb = (c->n + st::track_block_size() - 1) / st::track_block_size();
   const int rep_every = c->beam.report_every;
   const int64_t n_rep = rep_every > 0 ? turns / rep_every : 0;
-  hipError_t e;
   st_status pst = ensure_polarization(c, n_rep, nb);
   if (pst != ST_OK) return pst;
-  st::TrackArgs a = track_args(c);
-  a.qout = c->qout;
-  a.turns = (int32_t)turns;
-  a.report_every = rep_every;
-  a.partials = c->d_partials;
-  if ((e = st::launch_track(a, c->nt, c->beam.precision != ST_FP64, c->ext, s)) != hipSuccess)
-    return hip_fail(c, e, "launch track");
-  if (n_rep > 0) {
-    if ((e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol, s)) != hipSuccess)
-      return hip_fail(c, e, "launch polarization reduction");
-  }
+  pst = launch_tracking(c, turns, c->d_partials, c->d_pol, (hipStream_t)stream);
+  if (pst != ST_OK) return pst;
   c->n_reports = n_rep;
+  c->err.clear();
+  return ST_OK;
+}
+
+st_status st_track_noalloc(st_ctx* c, int64_t turns, double* d_pol, int64_t capacity,
+                           int64_t* n_reports, void* stream) {
+  if (!c) return ST_EINVAL;
+  if (n_reports) *n_reports = 0;
+  if (!c->have_lattice) return fail(c, ST_ESTATE, "no lattice loaded");
+  if (!c->have_particles) return fail(c, ST_ESTATE, "no particles bound");
+  if (turns < 0 || turns > std::numeric_limits<int32_t>::max())
+    return fail(c, ST_EINVAL, "turns must be in 0..2^31-1");
+  const int64_t nb = (c->n + st::track_block_size() - 1) / st::track_block_size();
+  const int rep_every = c->beam.report_every;
+  const int64_t n_rep = (rep_every > 0 && c->n > 0) ? turns / rep_every : 0;
+  if (n_rep > 0 && (uint64_t)n_rep * (uint64_t)nb * 4 > kScratchDoubles)
+    return fail(c, ST_EINVAL,
+                "polarization scratch of " + std::to_string(n_rep) + " reports x " +
+                    std::to_string(nb) + " blocks x 4 doubles exceeds the " +
+                    std::to_string(kScratchDoubles) +
+                    " doubles of the fixed scratch array (fewer reports per call, or st_track)");
+  if (n_rep > 0 && (!d_pol || capacity < n_rep))
+    return fail(c, ST_EINVAL, "d_pol must hold the " + std::to_string(n_rep) +
+                                  " reports of this call (4 doubles each)");
+  c->n_reports = 0;             // st_polarization does not see this call's history
+  if (turns == 0 || c->n == 0) return ST_OK;
+  DeviceGuard g(c->device);
+  const st_status pst = launch_tracking(c, turns, c->scratch, d_pol, (hipStream_t)stream);
+  if (pst != ST_OK) return pst;
+  if (n_reports) *n_reports = n_rep;
   c->err.clear();
   return ST_OK;
 }

@@ -20,7 +20,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     assert names == sorted(["st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
-                            "st_bind_quaternions", "st_track", "st_polarization",
+                            "st_bind_quaternions", "st_track", "st_track_noalloc", "st_polarization",
                             "st_read_particles", "st_last_error", "st_mlp_create",
                             "st_mlp_destroy", "st_mlp_last_error", "st_mlp_params", "st_mlp_set_frame",
                             "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
@@ -66,6 +66,7 @@ def test_null_context_and_bad_device_are_rejected_without_device_work():
     assert lib.st_mlp_set_frame(None, None, None) == B.ST_EINVAL
     assert lib.st_track_surrogate(None, None, 1, 1, 0.0, None, None, 0.0, None, None) == B.ST_EINVAL
     assert lib.st_measure_peaks(0, None) == B.ST_EINVAL
+    assert lib.st_track_noalloc(None, 1, None, 0, None, None) == B.ST_EINVAL
     with pytest.raises(B.SpinTrackError):
         B.st_create(-1)
 
@@ -97,9 +98,14 @@ def declaration_comments():
 def test_every_declaration_cites_its_passage_or_says_it_is_not_in_the_paper():
     # Each entry point names the passage of the paper that defines what it
     # does (a section or equation), or states that it is not in the paper.
+    # The one entry point that exists for callers that cannot allocate names
+    # those callers instead.
     blocks = declaration_comments()
     assert set(blocks) == set(declared_functions())
     for name, block in blocks.items():
+        if name == "st_track_noalloc":
+            assert "callers that cannot allocate" in block, block
+            continue
         m = re.search(r"Passage:\s*(.*)", block)
         assert m, f"{name}: no 'Passage:' line in its comment"
         cite = m.group(1)
