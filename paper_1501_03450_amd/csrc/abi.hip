@@ -234,6 +234,11 @@ st::DevElem derive(const st_element& e, const st_beam& beam, double beta0) {
     d.nsl = n_orb;
     const int re = std::min(e.romberg_rows, 1 + v2(e.n_slices));
     d.K = re - 1;
+    const double ds = e.L / n_orb;
+    d.hw_end = 0.25 * ds;
+    d.hw_in = 0.5 * ds;
+    d.hw2_end = d.hw_end * d.hw_end;
+    d.hw2_in = d.hw_in * d.hw_in;
   }
   if (e.kind == ST_SBEND && e.orbit == ST_ORB_TEAPOT) {
     st::TeapotParams& t = d.tp;

@@ -55,17 +55,18 @@ __device__ __forceinline__ void cosh_sinhc_series(double t, double& c, double& s
   Series<NT>::eval(t, c, s);
 }
 
-// asin(x) for |x| <= kAsinPolyMax: 8 Taylor terms, truncation < 1e-23 |x|.
-constexpr double kAsinPolyMax = 0.05;
-template <int N = 7>
+// asin(x) for |x| <= kAsinPolyMax: 5 Taylor terms (through x^9); the first
+// omitted term, C(10, 5)/(4^5 11) x^11, stays below 1.4e-17 |x| there.
+constexpr double kAsinPolyMax = 0.03;
+template <int N = 4>
 struct AsinSeries {
   __device__ __forceinline__ static double eval(double t) {
-    return fma(AsinSeries<N - 1>::eval(t), t, AC<7 - N>::v);
+    return fma(AsinSeries<N - 1>::eval(t), t, AC<4 - N>::v);
   }
 };
 template <>
 struct AsinSeries<0> {
-  __device__ __forceinline__ static double eval(double) { return AC<7>::v; }
+  __device__ __forceinline__ static double eval(double) { return AC<4>::v; }
 };
 
 // Beyond the series range the argument is reduced by halving, which keeps
@@ -120,15 +121,21 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 }
 
 // Quaternion terms of a rotation by θ = |ω|, ω = f Ω: with y = (θ/2)²,
-// cos(θ/2) and sin(θ/2)/θ.  NT series terms cover y <= ymax.
+// cos(θ/2) and sin(θ/2)/(θ/2).  NT series terms cover y <= ymax.
 template <int NT>
-__device__ __forceinline__ void rot_half_angle(double y, double ymax, double& c, double& sfac) {
-  double s;
+__device__ __forceinline__ void rot_half_series(double y, double ymax, double& c, double& s) {
   if (y <= ymax) {
     cos_sinc_series<NT>(y, c, s);
   } else {
     halving_series<NT, false>(y, ymax, c, s);
   }
+}
+
+// The same with the vector factor sin(θ/2)/θ.
+template <int NT>
+__device__ __forceinline__ void rot_half_angle(double y, double ymax, double& c, double& sfac) {
+  double s;
+  rot_half_series<NT>(y, ymax, c, s);
   sfac = 0.5 * s;
 }
 

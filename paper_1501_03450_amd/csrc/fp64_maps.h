@@ -299,6 +299,18 @@ __device__ __forceinline__ void teapot_slice(const TeapotParams& t, double& X, d
   teapot_drift(t, X, Px, Y, Py, T, p);
 }
 
+// Constants of one particle for the steps of a sector bend: the flight-time
+// change of a step is c0 - ibh D, with c0 = (1 - 1/η) s/β0 - Pt s/η and
+// ibh = (1/β0 + Pt)/(η h).
+struct BendLane {
+  double c0, ibh;
+};
+
+__device__ __forceinline__ BendLane bend_lane(const BendParams& e, const BendStep& k,
+                                              const Particle& p) {
+  return {fma(-p.Pt, k.s_eta, k.tconst), p.ib() * e.inv_eta_h};
+}
+
 // One step of the exact sector bend over the slice length (§3.1 eq. sbend),
 // from the state (X, Px) with Ps = W0 to the next slice edge.  Pα² = P² - Py²
 // is passed in; W1 = sqrt(Pα² - Px(s)²) is returned through W0/r0 (it is Ps
@@ -308,10 +320,10 @@ __device__ __forceinline__ void teapot_slice(const TeapotParams& t, double& X, d
 // with W1 - W0 = (Px - Px(s))(Px + Px(s))/(W0 + W1), and
 // asin(Px/Pα) - asin(Px(s)/Pα) = asin((Px W1 - Px(s) W0)/Pα²): both
 // algebraically identical to the printed forms and free of cancellation.
-__device__ __forceinline__ void bend_step(const BendParams& e, const BendStep& k, double& X,
-                                          double& Px, double Py, double& Y, double& T,
-                                          double& W0, double& r0, double& wme, double Pa2,
-                                          double invPa2, const Particle& p) {
+__device__ __forceinline__ void bend_step(const BendParams& e, const BendStep& k,
+                                          const BendLane& bl, double& X, double& Px, double Py,
+                                          double& Y, double& T, double& W0, double& r0,
+                                          double& wme, double Pa2, double invPa2) {
   double A = fma(-e.eta_h, X, wme);
   double px1 = fma(Px, k.cs, A * k.sn);
   double ps2n = fma(-px1, px1, Pa2);
@@ -320,8 +332,8 @@ __device__ __forceinline__ void bend_step(const BendParams& e, const BendStep& k
   double dW = (Px - px1) * (Px + px1) * rcp_nr(W0 + W1);
   double X1 = fma(X, k.cs, fma(wme, k.omc, fma(Px, k.sn, dW)) * e.inv_eta_h);
   double D = asin_small(fma(Px, W1, -px1 * W0) * invPa2);
-  Y = fma(Py, k.s_eta, fma(Py * D, e.inv_eta_h, Y));
-  T = T - p.Pt * k.s_eta - p.ib() * D * e.inv_eta_h + k.tconst;
+  Y = fma(Py, fma(D, e.inv_eta_h, k.s_eta), Y);
+  T += fma(-bl.ibh, D, bl.c0);
   wme += dW;
   X = X1;
   Px = px1;
@@ -331,12 +343,16 @@ __device__ __forceinline__ void bend_step(const BendParams& e, const BendStep& k
 
 // Matrix-kick quadrupole constants of one particle (§3.3 eq. quadL over
 // s = ds/2): κ² = |k1|/P; cos, sin(κs)/κ, κP sin(κs) and their hyperbolic
-// twins, all functions of (κs)² = |k1| s²/P.
+// twins, all functions of (κs)² = |k1| s²/P.  The flight-time brace of
+// eq. quadL is a quadratic form in (X, Px, Y, Py) at the entrance of the
+// step; its six coefficients, with the factor -1/β = -(1/β0 + Pt)/P
+// folded in, are constants of the particle in the element.
 struct MKConst {
-  double cf, sf, kf;     // focusing plane:   cos κs, sin κs / κ, κ P sin κs
-  double cd, sd, kd;     // defocusing plane: cosh κs, sinh κs / κ, κ P sinh κs
-  double kap2;           // κ²
-  double A1, A2, A3, A4, A5;   // coefficients of the flight-time formula
+  double cf, sfP, kf;    // focusing plane:   cos κs, sin κs /(κ P), κ P sin κs
+  double cd, sdP, kd;    // defocusing plane: cosh κs, sinh κs /(κ P), κ P sinh κs
+  double tpx, tpy;       // ΔT = Px (tpx Px + txp X) + Py (tpy Py + typ Y)
+  double txx, tyy;       //      + txx X² + tyy Y²
+  double txp, typ;
 };
 
 __device__ __forceinline__ MKConst mk_const(const QuadParams& e, const Particle& p) {
@@ -351,52 +367,67 @@ __device__ __forceinline__ MKConst mk_const(const QuadParams& e, const Particle&
     halving_series<7, false>(t, 0.04, C, Sc);
     halving_series<7, true>(t, 0.04, Ch, Sh);
   }
-  double hs = e.hds;
-  m.cf = C;  m.sf = hs * Sc;  m.kf = kabs * hs * Sc;
-  m.cd = Ch; m.sd = hs * Sh;  m.kd = kabs * hs * Sh;
-  m.kap2 = kabs * p.invP;
-  m.A1 = 0.25 * hs;
-  m.A2 = 0.25 * m.sf * m.cf;
-  m.A3 = 0.25 * m.sd * m.cd;
-  m.A4 = 0.5 * m.kap2 * m.sf * m.sf;
-  m.A5 = 0.5 * m.kap2 * m.sd * m.sd;
+  const double hs = e.hds;
+  const double sf = hs * Sc, sd = hs * Sh;
+  m.cf = C;  m.sfP = sf * p.invP;  m.kf = kabs * sf;
+  m.cd = Ch; m.sdP = sd * p.invP;  m.kd = kabs * sd;
+  const double kap2 = kabs * p.invP;
+  // brace = A1 (px² + py² + κ²X² - κ²Y²) + A2 (px² - κ²X²) + A3 (py² + κ²Y²)
+  //         - A4 X px + A5 Y py,  px = Px/P, py = Py/P,
+  // A1 = s/4, A2 = sf cf/4, A3 = sd cd/4, A4 = κ² sf²/2, A5 = κ² sd²/2
+  const double A1 = 0.25 * hs, A2 = 0.25 * sf * C, A3 = 0.25 * sd * Ch;
+  const double nib = -p.invbeta();       // -1/β
+  const double nibP = nib * p.invP;
+  m.tpx = nibP * p.invP * (A1 + A2);
+  m.tpy = nibP * p.invP * (A1 + A3);
+  m.txx = nib * kap2 * (A1 - A2);
+  m.tyy = nib * kap2 * (A3 - A1);
+  m.txp = -nibP * (0.5 * kap2 * sf * sf);
+  m.typ = nibP * (0.5 * kap2 * sd * sd);
   return m;
 }
 
 // Linear part of the matrix-kick quadrupole over ds/2 in (focusing,
 // defocusing) coordinates.
 __device__ __forceinline__ void mk_linear(const MKConst& m, double& xf, double& pxf, double& yd,
-                                          double& pyd, double& T, const Particle& p) {
-  double px = pxf * p.invP, py = pyd * p.invP;
-  double x0 = xf, y0 = yd;
-  double k2x2 = m.kap2 * x0 * x0, k2y2 = m.kap2 * y0 * y0;
-  double brace = m.A1 * (px * px + py * py + k2x2 - k2y2)
-               + m.A2 * (px * px - k2x2)
-               + m.A3 * (py * py + k2y2)
-               - m.A4 * x0 * px
-               + m.A5 * y0 * py;
-  xf = fma(x0, m.cf, px * m.sf);
-  pxf = fma(pxf, m.cf, -x0 * m.kf);
-  yd = fma(y0, m.cd, py * m.sd);
-  pyd = fma(pyd, m.cd, y0 * m.kd);
-  T = fma(-p.invbeta(), brace, T);
+                                          double& pyd, double& T, const Particle&) {
+  const double x0 = xf, y0 = yd, p0 = pxf, q0 = pyd;
+  const double dT = fma(p0, fma(m.tpx, p0, m.txp * x0),
+                        fma(q0, fma(m.tpy, q0, m.typ * y0), fma(m.txx * x0, x0, m.tyy * y0 * y0)));
+  xf = fma(x0, m.cf, p0 * m.sfP);
+  pxf = fma(p0, m.cf, -x0 * m.kf);
+  yd = fma(y0, m.cd, q0 * m.sdP);
+  pyd = fma(q0, m.cd, y0 * m.kd);
+  T += dT;
 }
 
-// Nonlinear "kick of positions" over ds (§3.3 eq. quadNL).  The flight-time
-// term is written as -ds/β [P/Ps - 1 - u/2] - ds (1/β - 1/β0) with
-// u = (Px² + Py²)/P² and P/Ps - 1 - u/2 = u²(2 + ρ)/(2ρ(1 + ρ)²), ρ = Ps/P.
+// Nonlinear "kick of positions" over ds (§3.3 eq. quadNL).  With
+// u = (Px² + Py²)/P², P/Ps = (1 - u)^(-1/2), so 1/Ps - 1/P = (u/2 + g)/P with
+// g = P/Ps - 1 - u/2 = Σ_{k≥2} C(2k, k) (u/4)^k, and the flight-time term is
+// -ds/β g - ds (1/β - 1/β0).  For u ≤ 2^-8 the series through u^6 leaves
+// less than 3e-18 of g (the binomial series of (1 - u)^(-1/2)); a lane with
+// larger angles takes the closed form g = u²(2 + ρ)/(2ρ(1 + ρ)²), ρ = Ps/P.
+constexpr double kMkSeriesMaxU = 0.00390625;
 __device__ __forceinline__ void mk_nonlinear(double ds, double& X, double Px, double& Y,
                                              double Py, double& T, const Particle& p) {
-  double pp = fma(Px, Px, Py * Py);
-  double ps2 = p.P2() - pp;
-  double r = rsqrt_nr(ps2);
-  double d = r - p.invP;
+  const double pp = fma(Px, Px, Py * Py);
+  const double u = pp * p.invP2();
+  double g, d;
+  if (u <= kMkSeriesMaxU) {
+    constexpr double c2 = 3.0 / 8.0, c3 = 5.0 / 16.0, c4 = 35.0 / 128.0, c5 = 63.0 / 256.0,
+                     c6 = 231.0 / 1024.0;
+    g = (u * u) * fma(u, fma(u, fma(u, fma(u, c6, c5), c4), c3), c2);
+    d = fma(u, 0.5, g) * p.invP;         // 1/Ps - 1/P
+  } else {
+    const double ps2 = p.P2() - pp;
+    const double r = rsqrt_nr(ps2);
+    d = r - p.invP;
+    const double rho = ps2 * r * p.invP;
+    const double opr = 1.0 + rho;
+    g = u * u * (2.0 + rho) * (p.P() * r) * 0.5 * rcp_nr(opr * opr);
+  }
   X = fma(ds * Px, d, X);
   Y = fma(ds * Py, d, Y);
-  double u = pp * p.invP2();
-  double rho = ps2 * r * p.invP;
-  double opr = 1.0 + rho;
-  double g = u * u * (2.0 + rho) * (p.P() * r) * 0.5 * rcp_nr(opr * opr);
   T = T - ds * fma(p.invbeta(), g, p.dib);
 }
 

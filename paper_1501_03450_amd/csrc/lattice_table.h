@@ -89,6 +89,9 @@ struct DevElem {
   int32_t kind, orbit, nsl, K;   // K = R_e - 1: Romberg levels minus one
   int32_t flags, place;          // place: P_EDGES, P_KICK or P_MIDPOINT (nsl = 2N orbit
                                  // half slices for P_MIDPOINT)
+  // Romberg edge rotations of sliced elements: half the step w ds of an end
+  // edge (w = 1/2) and of an interior edge (w = 1), and their squares
+  double hw_end, hw_in, hw2_end, hw2_in;
   union {
     BendParams b;
     TeapotParams tp;

@@ -37,6 +37,10 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
   d.K = p->K;
   d.flags = p->flags;
   d.place = p->place;
+  d.hw_end = p->hw_end;
+  d.hw_in = p->hw_in;
+  d.hw2_end = p->hw2_end;
+  d.hw2_in = p->hw2_in;
 #pragma unroll
   for (int i = 0; i < kElemWords; ++i) d.v[i] = p->v[i];
   return d;
@@ -122,7 +126,9 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   double r = rsqrt_nr(ps2);
   double W = ps2 * r;
   double invPa2 = 0.0, wme = 0.0;
+  BendLane bl{0.0, 0.0};
   if (KIND == 0) {
+    bl = bend_lane(el.b, el.b.slice, p);
     invPa2 = rcp_nr(Pa2);
     // W - η = (W² - η²)/(W + η) with W² - η² = (1 - η²) + (P² - 1) - Py² - Px²
     wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
@@ -131,7 +137,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   for (int j = 0; j <= N; ++j) {
     if (j > 0) {
       if (KIND == 0) {
-        bend_step(el.b, el.b.slice, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
+        bend_step(el.b, el.b.slice, bl, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2);
       } else {
         if (KIND == 4) {
           teapot_slice(el.tp, X, Px, Y, Py, T, p);
@@ -152,8 +158,9 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
     // Level m keeps this edge when 2^m divides j, with step w 2^m ds: the
     // rotation about Ω by 2^m times the finest angle, i.e. the finest
     // quaternion squared m times.
-    const double f = ((j == 0 || j == N) ? 0.5 : 1.0) * ds;
+    const bool end_edge = j == 0 || j == N;
     if (spin32) {
+      const double f = (end_edge ? 0.5 : 1.0) * ds;
       float d, sf;
       rot_deviation_f32(0.25 * f * f * om2, d, sf);
       float vx = sf * (float)(f * ox), vy = sf * (float)(f * oy), vz = sf * (float)(f * oz);
@@ -171,9 +178,10 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
         }
       }
     } else {
-      double c, sfac;
-      rot_half_angle<NT>(0.25 * f * f * om2, a.ymax, c, sfac);
-      const double g = sfac * f;
+      // half angle θ/2 = hw |Ω|: q = (cos θ/2, sin(θ/2)/(θ/2) hw Ω)
+      double c, sc;
+      rot_half_series<NT>((end_edge ? el.hw2_end : el.hw2_in) * om2, a.ymax, c, sc);
+      const double g = sc * (end_edge ? el.hw_end : el.hw_in);
       Quat qb = {c, g * ox, g * oy, g * oz};
       Q0 = qmul(qb, Q0);
       if (K >= 1 && (j & 1) == 0) {
@@ -228,7 +236,8 @@ __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double
     double r = rsqrt_nr(ps2);
     double W = ps2 * r;
     double wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
-    bend_step(el.b, el.b.whole, X, Px, Py, Y, T, W, r, wme, Pa2, rcp_nr(Pa2), p);
+    bend_step(el.b, el.b.whole, bend_lane(el.b, el.b.whole, p), X, Px, Py, Y, T, W, r, wme, Pa2,
+              rcp_nr(Pa2));
     return;
   }
   if constexpr (Y4) {
@@ -264,7 +273,9 @@ __device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double
     if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
   }
   double Pa2 = 0.0, invPa2 = 0.0, W = 0.0, r = 0.0, wme = 0.0;
+  BendLane bl{0.0, 0.0};
   if (KIND == 0) {
+    bl = bend_lane(el.b, el.b.slice, p);
     Pa2 = p.P2() - Py * Py;
     invPa2 = rcp_nr(Pa2);
     const double ps2 = fma(-Px, Px, Pa2);
@@ -283,7 +294,7 @@ __device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double
         Py = fma(0.5 * el.q.k1ds, Y, Py);
       }
     } else if (KIND == 0) {
-      bend_step(el.b, el.b.slice, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2, p);
+      bend_step(el.b, el.b.slice, bl, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2);
     } else if (KIND == 4) {
       teapot_slice(el.tp, X, Px, Y, Py, T, p);
     } else if (Y4) {
