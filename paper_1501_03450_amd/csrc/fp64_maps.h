@@ -90,18 +90,39 @@ __device__ __forceinline__ Particle make_particle(double Pt, const TrackArgs& a)
   return p;
 }
 
-// Exact drift of length L (flow of -Ps + Pt/β0).  The flight-time change
-// L/β0 - L(1/β0 + Pt)/Ps is evaluated as
-// L (c1 - Px² - Py²) / (β0 Ps (Ps + 1 + β0 Pt)), free of cancellation.
+// With u = (Px² + Py²)/P², P/Ps = (1 - u)^(-1/2); g = P/Ps - 1 - u/2 is the
+// binomial series Σ_{k≥2} C(2k, k) (u/4)^k.  For u ≤ 2^-8 its terms through
+// u^6 leave less than 3e-18 of g; callers take a closed form beyond.
+constexpr double kSeriesMaxU = 0.00390625;
+__device__ __forceinline__ double series_g(double u) {
+  constexpr double c2 = 3.0 / 8.0, c3 = 5.0 / 16.0, c4 = 35.0 / 128.0, c5 = 63.0 / 256.0,
+                   c6 = 231.0 / 1024.0;
+  return (u * u) * fma(u, fma(u, fma(u, fma(u, c6, c5), c4), c3), c2);
+}
+
+// Exact drift of length L (flow of -Ps + Pt/β0).  With e = P/Ps - 1 =
+// u/2 + g (series above), X and Y advance by L P(x,y) (1 + e)/P, and the
+// flight-time change L/β0 - L(1/β0 + Pt)/Ps is -L (1/β - 1/β0) - L e/β,
+// free of cancellation.  A lane with u > 2^-8 evaluates it as
+// L (c1 - Px² - Py²) / (β0 Ps (Ps + 1 + β0 Pt)).
 __device__ __forceinline__ void drift(double L, double& X, double Px, double& Y, double Py,
                                       double& T, const Particle& p, double inv_beta0) {
-  double pp = fma(Px, Px, Py * Py);
-  double ps2 = p.P2() - pp;
-  double r = rsqrt_nr(ps2);
-  double ps = ps2 * r;
-  X = fma(L * Px, r, X);
-  Y = fma(L * Py, r, Y);
-  T = fma(L * (p.c1() - pp) * r * inv_beta0, rcp_nr(ps + p.c2()), T);
+  const double pp = fma(Px, Px, Py * Py);
+  const double u = pp * p.invP2();
+  if (u <= kSeriesMaxU) {
+    const double e = fma(u, 0.5, series_g(u));
+    const double r = fma(p.invP, e, p.invP);       // 1/Ps
+    X = fma(L * Px, r, X);
+    Y = fma(L * Py, r, Y);
+    T = fma(-L, fma(p.invbeta(), e, p.dib), T);
+  } else {
+    const double ps2 = p.P2() - pp;
+    const double r = rsqrt_nr(ps2);
+    const double ps = ps2 * r;
+    X = fma(L * Px, r, X);
+    Y = fma(L * Py, r, Y);
+    T = fma(L * (p.c1() - pp) * r * inv_beta0, rcp_nr(ps + p.c2()), T);
+  }
 }
 
 // Precession vector of eq. t-bmt.so for a field b = (bx, by, 0) without
@@ -402,21 +423,17 @@ __device__ __forceinline__ void mk_linear(const MKConst& m, double& xf, double& 
 }
 
 // Nonlinear "kick of positions" over ds (§3.3 eq. quadNL).  With
-// u = (Px² + Py²)/P², P/Ps = (1 - u)^(-1/2), so 1/Ps - 1/P = (u/2 + g)/P with
-// g = P/Ps - 1 - u/2 = Σ_{k≥2} C(2k, k) (u/4)^k, and the flight-time term is
-// -ds/β g - ds (1/β - 1/β0).  For u ≤ 2^-8 the series through u^6 leaves
-// less than 3e-18 of g (the binomial series of (1 - u)^(-1/2)); a lane with
-// larger angles takes the closed form g = u²(2 + ρ)/(2ρ(1 + ρ)²), ρ = Ps/P.
-constexpr double kMkSeriesMaxU = 0.00390625;
+// u = (Px² + Py²)/P², 1/Ps - 1/P = (u/2 + g)/P and the flight-time term is
+// -ds/β g - ds (1/β - 1/β0), g = P/Ps - 1 - u/2 (series_g); a lane
+// with larger angles takes the closed form g = u²(2 + ρ)/(2ρ(1 + ρ)²),
+// ρ = Ps/P.
 __device__ __forceinline__ void mk_nonlinear(double ds, double& X, double Px, double& Y,
                                              double Py, double& T, const Particle& p) {
   const double pp = fma(Px, Px, Py * Py);
   const double u = pp * p.invP2();
   double g, d;
-  if (u <= kMkSeriesMaxU) {
-    constexpr double c2 = 3.0 / 8.0, c3 = 5.0 / 16.0, c4 = 35.0 / 128.0, c5 = 63.0 / 256.0,
-                     c6 = 231.0 / 1024.0;
-    g = (u * u) * fma(u, fma(u, fma(u, fma(u, c6, c5), c4), c3), c2);
+  if (u <= kSeriesMaxU) {
+    g = series_g(u);
     d = fma(u, 0.5, g) * p.invP;         // 1/Ps - 1/P
   } else {
     const double ps2 = p.P2() - pp;

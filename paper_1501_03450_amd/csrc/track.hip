@@ -14,6 +14,8 @@
 // composed into the turn quaternion, which rotates the spin once per turn.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fp64_maps.h"
 #include "mixed_spin.h"
 #include "track_kernels.h"
@@ -99,7 +101,10 @@ __device__ __forceinline__ void quad_slice4(const Quad4Params& q4, const MKConst
 }
 
 // Y4: quadrupoles with the fourth-order slice (extended kernels only).
-template <int NT, int KIND, bool MIXED, bool Y4 = false>
+// PEEL: the entrance edge is folded outside the slice loop, where the level
+// products are set instead of multiplied into the identity (the extended
+// kernels keep one copy of the edge code, which holds their registers down).
+template <int NT, int KIND, bool MIXED, bool Y4 = false, bool PEEL = true>
 __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, double& Px, double& Y,
                                               double& Py, double& T, const Particle& p,
                                               const TrackArgs& a) {
@@ -134,22 +139,11 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
     wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
   }
 
-  for (int j = 0; j <= N; ++j) {
-    if (j > 0) {
-      if (KIND == 0) {
-        bend_step(el.b, el.b.slice, bl, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2);
-      } else {
-        if (KIND == 4) {
-          teapot_slice(el.tp, X, Px, Y, Py, T, p);
-        } else if (Y4) {
-          quad_slice4<KIND>(el.q4, mc, mc0, X, Px, Y, Py, T, p, a);
-        } else {
-          quad_step2<KIND>(el.q, mc, X, Px, Y, Py, T, p, a);
-        }
-        ps2 = p.P2() - fma(Px, Px, Py * Py);
-        r = rsqrt_nr(ps2);
-      }
-    }
+  // Fold the rotation of edge j into the running products of the levels
+  // that keep it.  The entrance edge starts every level (FIRST: the
+  // products are set, not multiplied into the identity).
+  auto fold = [&](int j, auto first_tag) {
+    constexpr bool FIRST = decltype(first_tag)::value;
     double ox, oy, oz;
     if (KIND == 0)      omega_bend(el.b, X, Px, Py, r, p, ox, oy, oz);
     else if (KIND == 4) omega_dipole(el.tp.h, el.tp.eta_h, X, Px, Py, r, p, ox, oy, oz);
@@ -183,20 +177,44 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
       rot_half_series<NT>((end_edge ? el.hw2_end : el.hw2_in) * om2, a.ymax, c, sc);
       const double g = sc * (end_edge ? el.hw_end : el.hw_in);
       Quat qb = {c, g * ox, g * oy, g * oz};
-      Q0 = qmul(qb, Q0);
+      Q0 = FIRST ? qb : qmul(qb, Q0);
       if (K >= 1 && (j & 1) == 0) {
         qb = qsquare(qb);
-        Q1 = qmul(qb, Q1);
+        Q1 = FIRST ? qb : qmul(qb, Q1);
         if (K >= 2 && (j & 3) == 0) {
           qb = qsquare(qb);
-          Q2 = qmul(qb, Q2);
+          Q2 = FIRST ? qb : qmul(qb, Q2);
           if (K >= 3 && (j & 7) == 0) {
             qb = qsquare(qb);
-            Q3 = qmul(qb, Q3);
+            Q3 = FIRST ? qb : qmul(qb, Q3);
           }
         }
       }
     }
+  };
+
+  int j0 = 0;
+  if constexpr (PEEL) {
+    fold(0, std::true_type{});
+    j0 = 1;
+  }
+  for (int j = j0; j <= N; ++j) {
+    if (j > 0) {
+      if (KIND == 0) {
+        bend_step(el.b, el.b.slice, bl, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2);
+      } else {
+        if (KIND == 4) {
+          teapot_slice(el.tp, X, Px, Y, Py, T, p);
+        } else if (Y4) {
+          quad_slice4<KIND>(el.q4, mc, mc0, X, Px, Y, Py, T, p, a);
+        } else {
+          quad_step2<KIND>(el.q, mc, X, Px, Y, Py, T, p, a);
+        }
+        ps2 = p.P2() - fma(Px, Px, Py * Py);
+        r = rsqrt_nr(ps2);
+      }
+    }
+    fold(j, std::false_type{});
   }
   if (spin32) {
     Q0 = qc_to_double(C0);
@@ -518,7 +536,7 @@ __device__ __forceinline__ Quat thick_body_ext(const DevElem& el, double& X, dou
   }
   if (el.place == P_MIDPOINT)
     return pwc_element<NT, KIND, P_MIDPOINT, Y4>(el, X, Px, Y, Py, T, p, a);
-  return thick_element<NT, KIND, false, Y4>(el, X, Px, Y, Py, T, p, a);
+  return thick_element<NT, KIND, false, Y4, false>(el, X, Px, Y, Py, T, p, a);
 }
 
 // The body between the fringe spin kicks of its faces (elements flagged
