@@ -120,6 +120,16 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(y, e, y);
 }
 
+// 1/sqrt(x) where it only scales a precession vector: one Newton step from
+// the hardware estimate (measured within 2^-24.4 of 1/sqrt(x) on gfx950)
+// leaves a relative error below 5e-15, i.e. below 1e-15 rad in the rotation
+// of one slice edge (angles stay under 0.2 rad).  Orbit maps use rsqrt_nr.
+__device__ __forceinline__ double rsqrt_omega(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-0.5 * x * y, y, 0.5);
+  return fma(y, e, y);
+}
+
 // Quaternion terms of a rotation by θ = |ω|, ω = f Ω: with y = (θ/2)²,
 // cos(θ/2) and sin(θ/2)/(θ/2).  NT series terms cover y <= ymax.
 template <int NT>

@@ -100,6 +100,39 @@ __device__ __forceinline__ void quad_slice4(const Quad4Params& q4, const MKConst
   quad_step2<KIND>(q4.s1, m1, X, Px, Y, Py, T, p, a);
 }
 
+// Matrix-kick constants of the last quadrupole a lane crossed, kept in the
+// block's LDS (one column per lane).  They depend only on the particle's P
+// and on the element's |k1| and slice length, so quadrupoles that share
+// those (in a FODO ring the focusing and defocusing ones usually do) reuse
+// them instead of re-evaluating the series.  The key is element data, the
+// same for every lane of a wave.
+constexpr int kMKWords = sizeof(MKConst) / sizeof(double);
+struct MKCache {
+  double (*slot)[kBlock];
+  int tid;
+  double k1abs, hds;       // key of the stored constants (NaN: none yet)
+};
+
+__device__ __forceinline__ MKConst mk_cached(const QuadParams& q, const Particle& p,
+                                             MKCache* c) {
+  MKConst m;
+  double* w = reinterpret_cast<double*>(&m);
+  const double ka = fabs(q.k1);
+  if (c && ka == c->k1abs && q.hds == c->hds) {
+#pragma unroll
+    for (int i = 0; i < kMKWords; ++i) w[i] = c->slot[i][c->tid];
+    return m;
+  }
+  m = mk_const(q, p);
+  if (c) {
+#pragma unroll
+    for (int i = 0; i < kMKWords; ++i) c->slot[i][c->tid] = w[i];
+    c->k1abs = ka;
+    c->hds = q.hds;
+  }
+  return m;
+}
+
 // Y4: quadrupoles with the fourth-order slice (extended kernels only).
 // PEEL: the entrance edge is folded outside the slice loop, where the level
 // products are set instead of multiplied into the identity (the extended
@@ -107,7 +140,7 @@ __device__ __forceinline__ void quad_slice4(const Quad4Params& q4, const MKConst
 template <int NT, int KIND, bool MIXED, bool Y4 = false, bool PEEL = true>
 __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, double& Px, double& Y,
                                               double& Py, double& T, const Particle& p,
-                                              const TrackArgs& a) {
+                                              const TrackArgs& a, MKCache* mkc = nullptr) {
   static_assert(kMaxRows == 4, "the level products below are written out for four rows");
   const int N = el.nsl;
   const int K = el.K;
@@ -123,12 +156,12 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   if constexpr (Y4) {
     if (KIND == 1 || KIND == 3) { mc = mk_const(el.q4.s1, p); mc0 = mk_const(el.q4.s0, p); }
   } else {
-    if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+    if (KIND == 1 || KIND == 3) mc = mk_cached(el.q, p, mkc);
   }
 
-  // Ps and 1/Ps at the entrance edge
+  // Ps and 1/Ps at the entrance edge (outside bends 1/Ps only enters Ω)
   double ps2 = fma(-Px, Px, Pa2);
-  double r = rsqrt_nr(ps2);
+  double r = KIND == 0 ? rsqrt_nr(ps2) : rsqrt_omega(ps2);
   double W = ps2 * r;
   double invPa2 = 0.0, wme = 0.0;
   BendLane bl{0.0, 0.0};
@@ -211,7 +244,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
           quad_step2<KIND>(el.q, mc, X, Px, Y, Py, T, p, a);
         }
         ps2 = p.P2() - fma(Px, Px, Py * Py);
-        r = rsqrt_nr(ps2);
+        r = rsqrt_omega(ps2);
       }
     }
     fold(j, std::false_type{});
@@ -569,7 +602,7 @@ __device__ __forceinline__ Quat thin_element(const DevElem& e, double X, double&
   Px -= fma(hk1, X, 0.5 * hk2 * (X * X - Y * Y));
   Py += fma(hk1, Y, hk2 * X * Y);
   double ps2 = p.P2() - fma(Px, Px, Py * Py);
-  double r = rsqrt_nr(ps2);
+  double r = rsqrt_omega(ps2);
   double bx = fma(e.t.k2l * X, Y, e.t.k1l * Y);
   double by = fma(e.t.k1l, X, 0.5 * e.t.k2l * (X * X - Y * Y));
   double ox, oy, oz;
@@ -602,6 +635,7 @@ track_kernel(const TrackArgs a) {
   // Cold per-lane data in LDS: the spin (touched once per turn) and the
   // orbit at the current element's entrance (read back only on a loss).
   __shared__ double cold[8][kBlock];
+  __shared__ double mk_slot[EXT ? 1 : kMKWords][kBlock];
   const int tid = threadIdx.x;
   const int64_t g = (int64_t)blockIdx.x * kBlock + tid;
   const bool valid = g < a.n;
@@ -621,6 +655,7 @@ track_kernel(const TrackArgs a) {
   // (a replay of a few particles) may leave at once.
   if (a.report_every == 0 && !__any(live)) return;
   const Particle p = make_particle(Pt, a);
+  MKCache mkc{mk_slot, tid, __builtin_nan(""), __builtin_nan("")};
   Quat qturn = qident();
   const bool spin_lane = !SURR || (valid && a.fallback[j] != 0);
   // The lattice is read-only for the whole launch: reading it through the
@@ -699,8 +734,8 @@ track_kernel(const TrackArgs a) {
           break;
         case K_QUAD:
           if (e.orbit != M_MK)   q = thick_element<NT, 2, MIXED>(e, X, Px, Y, Py, T, p, a);
-          else if (e.q.k1 >= 0.0) q = thick_element<NT, 1, MIXED>(e, X, Px, Y, Py, T, p, a);
-          else                   q = thick_element<NT, 3, MIXED>(e, X, Px, Y, Py, T, p, a);
+          else if (e.q.k1 >= 0.0) q = thick_element<NT, 1, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
+          else                   q = thick_element<NT, 3, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
           break;
         case K_THIN:
           q = thin_element<NT>(e, X, Px, Y, Py, p, a);
