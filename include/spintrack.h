@@ -369,17 +369,19 @@ st_status st_track_surrogate(st_ctx* ctx, st_mlp* m, int64_t turns, int32_t audi
  * (not a step of the method).
  *   fp64_fma_tflops   FP64 vector FMA rate, eight independent v_fma_f64 chains
  *                     per lane, 16 workgroups of 256 lanes per compute unit
+ *   fp32_fma_tflops   the same with v_fma_f32, one operation per instruction
+ *                     (the library is built without packed FP32 instructions)
  *   bf16_mfma_tflops  dense bf16 matrix rate, four independent chains of
  *                     v_mfma_f32_16x16x32_bf16 per wave
  *   copy_gbps         HBM bandwidth of a 16-byte copy of 1 GiB into 1 GiB,
  *                     read plus written bytes
  * Each is timed with HIP events over 10 launches after a warm-up launch. */
 typedef struct {
-  double fp64_fma_tflops, bf16_mfma_tflops, copy_gbps;
+  double fp64_fma_tflops, bf16_mfma_tflops, copy_gbps, fp32_fma_tflops;
 } st_peaks;
 
 /* Passage: not in the paper (measurement).
- * Run the three microbenchmarks on HIP device `device` and fill *out.
+ * Run the four microbenchmarks on HIP device `device` and fill *out.
  * Synchronous; allocates and frees 2 GiB of device memory.  ST_EINVAL for a
  * NULL out or an unknown device, ST_EDEVICE if an allocation, launch or timing
  * call fails (out is then incomplete). */

@@ -49,7 +49,7 @@ class st_element(ctypes.Structure):
 
 class st_peaks(ctypes.Structure):
     _fields_ = [("fp64_fma_tflops", ctypes.c_double), ("bf16_mfma_tflops", ctypes.c_double),
-                ("copy_gbps", ctypes.c_double)]
+                ("copy_gbps", ctypes.c_double), ("fp32_fma_tflops", ctypes.c_double)]
 
 
 class st_beam(ctypes.Structure):
@@ -123,14 +123,14 @@ def st_create(device: int = 0):
 
 
 def st_measure_peaks(device: int = 0) -> dict:
-    """FP64 FMA and bf16 MFMA rates [TFLOP/s] and HBM copy bandwidth [GB/s]
-    measured on `device`."""
+    """FP64 and unpacked FP32 FMA and bf16 MFMA rates [TFLOP/s] and HBM copy
+    bandwidth [GB/s] measured on `device`."""
     p = st_peaks()
     st = LIB.st_measure_peaks(int(device), ctypes.byref(p))
     if st != ST_OK:
         raise SpinTrackError(st, f"peak microbenchmarks failed on device {device}")
     return {"fp64_fma_tflops": p.fp64_fma_tflops, "bf16_mfma_tflops": p.bf16_mfma_tflops,
-            "copy_gbps": p.copy_gbps}
+            "copy_gbps": p.copy_gbps, "fp32_fma_tflops": p.fp32_fma_tflops}
 
 
 def st_destroy(ctx) -> None:

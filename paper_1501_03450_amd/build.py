@@ -16,6 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds fused only within one expression, so that every kernel
+    # instantiation rounds the same source the same way (the mixed-precision
+    # kernel reproduces the double-precision orbit bit for bit)
+    "-ffp-contract=on",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,

@@ -53,26 +53,27 @@ __device__ __forceinline__ void qrotate(const Quat& q, double& sx, double& sy, d
 
 // Quantities of one particle that depend on Pt only (eq. pt, eq. ps,
 // eq. quadSclP): P² = 1 + 2Pt/β0 + Pt², γ = γ0 (1 + β0 Pt), and the T-BMT
-// factors a1 = 1 + Gγ, a2 = G(γ - 1).  Four values stay in registers; the
-// others cost one instruction each where they are used, which keeps the
-// register footprint of the persistent loop small.
+// factors a1 = 1 + Gγ, a2 = G(γ - 1).  The factors used at every slice edge
+// stay in registers; the rarer ones cost one instruction each where they are
+// used.
 struct Particle {
   double Pt;
   double c3;       // P² - 1 = 2Pt/β0 + Pt², kept exactly (P² itself rounds it)
   double invP;
   double dib;      // 1/β - 1/β0
+  double invP2_, invbeta_, a1_, a2_;
   // beam constants (kernel arguments, uniform)
-  double ib0, beta0, ig2, Gg0b0, a1_0, a2_0;
+  double ib0, beta0, ig2;
 
   __device__ __forceinline__ double P2() const { return 1.0 + c3; }
   __device__ __forceinline__ double P() const { return (1.0 + c3) * invP; }
-  __device__ __forceinline__ double invP2() const { return invP * invP; }
+  __device__ __forceinline__ double invP2() const { return invP2_; }
   __device__ __forceinline__ double c1() const { return c3 * ig2; }           // P² - (1 + β0 Pt)²
   __device__ __forceinline__ double c2() const { return fma(beta0, Pt, 1.0); }  // 1 + β0 Pt
   __device__ __forceinline__ double ib() const { return ib0 + Pt; }           // 1/β0 + Pt
-  __device__ __forceinline__ double invbeta() const { return (ib0 + Pt) * invP; }
-  __device__ __forceinline__ double a1() const { return fma(Gg0b0, Pt, a1_0); }  // 1 + Gγ
-  __device__ __forceinline__ double a2() const { return fma(Gg0b0, Pt, a2_0); }  // G(γ - 1)
+  __device__ __forceinline__ double invbeta() const { return invbeta_; }      // (1/β0 + Pt)/P
+  __device__ __forceinline__ double a1() const { return a1_; }                // 1 + Gγ
+  __device__ __forceinline__ double a2() const { return a2_; }                // G(γ - 1)
 };
 
 __device__ __forceinline__ Particle make_particle(double Pt, const TrackArgs& a) {
@@ -81,11 +82,13 @@ __device__ __forceinline__ Particle make_particle(double Pt, const TrackArgs& a)
   p.ib0 = a.inv_beta0;
   p.beta0 = a.beta0;
   p.ig2 = a.inv_gamma0_sq;
-  p.Gg0b0 = a.G * a.gamma0 * a.beta0;
-  p.a1_0 = fma(a.G, a.gamma0, 1.0);
-  p.a2_0 = a.G * (a.gamma0 - 1.0);
+  const double Gg0b0 = a.G * a.gamma0 * a.beta0;
+  p.a1_ = fma(Gg0b0, Pt, fma(a.G, a.gamma0, 1.0));
+  p.a2_ = fma(Gg0b0, Pt, a.G * (a.gamma0 - 1.0));
   p.c3 = Pt * fma(2.0, a.inv_beta0, Pt);
   p.invP = rsqrt_nr(p.P2());
+  p.invP2_ = p.invP * p.invP;
+  p.invbeta_ = (a.inv_beta0 + Pt) * p.invP;
   p.dib = -p.c1() * a.inv_beta0 * p.invP * rcp_nr(p.c2() + p.P());
   return p;
 }

@@ -6,7 +6,8 @@
 // cancellation against 1), v = sin(θ/2)/θ · ω.  The running product of a
 // Romberg level is a compensated pair (hi, lo) of single-precision
 // quaternions: each update Q <- q ⊗ Q = Q + Δ with Δ = -d Q + (0, v) ⊗ Q is
-// added with Fast2Sum, so the product keeps about twice the single-precision
+// added with an error-free sum (Fast2Sum for the scalar part, 2Sum for the
+// vector part), so the product keeps about twice the single-precision
 // significand.  The tableau, the normalisation and the composition of
 // element quaternions are done in double precision by the caller.
 #pragma once
@@ -61,10 +62,22 @@ __device__ __forceinline__ void dev_square(float& d, float& vx, float& vy, float
   vz *= two_omd;
 }
 
-// Fast2Sum of the running hi with an increment, error carried into lo.
-__device__ __forceinline__ void comp_add(float& hi, float& lo, float inc) {
+// Fast2Sum of the running hi with an increment, error carried into lo: exact
+// only when |hi| >= |inc|, which holds for the scalar part (it starts at 1
+// and the increments are small rotations).
+__device__ __forceinline__ void comp_add_fast(float& hi, float& lo, float inc) {
   const float s = hi + inc;
   const float e = inc - (s - hi);
+  hi = s;
+  lo += e;
+}
+
+// 2Sum (Knuth): the rounding error of hi + inc for any magnitudes, for the
+// vector part, which starts at 0 and is smaller than the first increments.
+__device__ __forceinline__ void comp_add(float& hi, float& lo, float inc) {
+  const float s = hi + inc;
+  const float b = s - hi;
+  const float e = (hi - (s - b)) + (inc - b);
   hi = s;
   lo += e;
 }
@@ -81,7 +94,7 @@ __device__ __forceinline__ void qc_update(QuatC& Q, float d, float vx, float vy,
   dx = fmaf(-d, h.x, dx);
   dy = fmaf(-d, h.y, dy);
   dz = fmaf(-d, h.z, dz);
-  comp_add(Q.hi.w, Q.lo.w, dw);
+  comp_add_fast(Q.hi.w, Q.lo.w, dw);
   comp_add(Q.hi.x, Q.lo.x, dx);
   comp_add(Q.hi.y, Q.lo.y, dy);
   comp_add(Q.hi.z, Q.lo.z, dz);

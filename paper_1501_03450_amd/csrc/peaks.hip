@@ -3,6 +3,8 @@
 // method.
 //
 //   FP64 vector FMA   every lane runs eight independent v_fma_f64 chains
+//   FP32 vector FMA   the same with v_fma_f32 (unpacked: the library is built
+//                     without packed single-precision instructions)
 //   bf16 MFMA         every wave runs four independent chains of
 //                     v_mfma_f32_16x16x32_bf16 (16·16·32 multiply-adds each)
 //   HBM copy          16-byte loads and stores over two device buffers
@@ -38,6 +40,20 @@ __global__ void __launch_bounds__(kBlock) fp64_fma_kernel(double b, double c, do
 #pragma unroll
   for (int j = 0; j < 8; ++j) s += x[j];
   if (s == 12345.678) out[0] = s;   // never true for the arguments used; keeps the chains live
+}
+
+__global__ void __launch_bounds__(kBlock) fp32_fma_kernel(float b, float c, float* out) {
+  float x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = (float)(threadIdx.x + j) * 1e-3f;
+  for (int i = 0; i < kFmaIters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = fmaf(x[j], b, c);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += x[j];
+  if (s == 12345.678f) out[0] = s;
 }
 
 __global__ void __launch_bounds__(kBlock) mfma_bf16_kernel(float seed, float* out) {
@@ -130,6 +146,11 @@ extern "C" st_status st_measure_peaks(int device, st_peaks* out) {
                                        0.999999, 1e-9, dsink); }, reps, &ms);
   if (e == hipSuccess)
     out->fp64_fma_tflops = 2.0 * 8 * kFmaIters * (double)fma_blocks * kBlock * reps / (ms * 1e-3) / 1e12;
+  if (e == hipSuccess)
+    e = timed([&] { hipLaunchKernelGGL(fp32_fma_kernel, dim3(fma_blocks), dim3(kBlock), 0, nullptr,
+                                       0.999999f, 1e-9f, (float*)dsink); }, reps, &ms);
+  if (e == hipSuccess)
+    out->fp32_fma_tflops = 2.0 * 8 * kFmaIters * (double)fma_blocks * kBlock * reps / (ms * 1e-3) / 1e12;
   // bf16 MFMA: 16 workgroups of four waves per CU
   const int mfma_blocks = 16 * cus;
   if (e == hipSuccess)

@@ -48,11 +48,13 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
   return d;
 }
 
-// Waves per SIMD the register allocation aims at: three for the plain double
-// kernel (168 VGPRs, a few spilled; measured faster than two waves at 209
-// VGPRs), two for the variants with more live state.
+// Waves per SIMD the register allocation aims at: two, for every variant.
+// The plain double kernel fits in 236 VGPRs with no scratch at two waves; at
+// three waves (168 VGPRs) it ran at the same speed, but spilled 70 VGPRs at
+// the element entrances, and with 2^20 lanes those spill slots (228 B each)
+// were written back to memory, about 500 GB per 100-turn launch.
 #ifndef ST_WAVES_PER_EU
-#define ST_WAVES_PER_EU 3
+#define ST_WAVES_PER_EU 2
 #endif
 #ifndef ST_WAVES_PER_EU_WIDE
 #define ST_WAVES_PER_EU_WIDE 2
@@ -137,13 +139,19 @@ __device__ __forceinline__ MKConst mk_cached(const QuadParams& q, const Particle
 // PEEL: the entrance edge is folded outside the slice loop, where the level
 // products are set instead of multiplied into the identity (the extended
 // kernels keep one copy of the edge code, which holds their registers down).
-template <int NT, int KIND, bool MIXED, bool Y4 = false, bool PEEL = true>
+// NS > 0: the element has NS slices and KS + 1 effective Romberg rows, known
+// at compile time, so the edge loop unrolls completely and the choice of the
+// levels each edge feeds is made by the compiler (no loop-carried copies, no
+// branches); NS == 0 reads both from the element.
+template <int NT, int KIND, bool MIXED, bool Y4 = false, bool PEEL = true, int NS = 0, int KS = 0>
 __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, double& Px, double& Y,
                                               double& Py, double& T, const Particle& p,
                                               const TrackArgs& a, MKCache* mkc = nullptr) {
   static_assert(kMaxRows == 4, "the level products below are written out for four rows");
-  const int N = el.nsl;
-  const int K = el.K;
+  static_assert(NS == 0 || (KS >= 0 && KS < kMaxRows && NS % (1 << KS) == 0),
+                "NS slices must be divisible by 2^KS");
+  const int N = NS > 0 ? NS : el.nsl;
+  const int K = NS > 0 ? KS : el.K;
   const double ds = KIND == 0 ? el.b.ds : (KIND == 4 ? el.tp.ds : el.q.ds);
   const bool spin32 = MIXED && (el.flags & F_SPIN32);
   // running products of the Romberg levels: level m keeps every 2^m-th edge
@@ -231,6 +239,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
     fold(0, std::true_type{});
     j0 = 1;
   }
+#pragma unroll
   for (int j = j0; j <= N; ++j) {
     if (j > 0) {
       if (KIND == 0) {
@@ -729,13 +738,34 @@ track_kernel(const TrackArgs a) {
           else                    q = thick_ext<NT, 3>(e, X, Px, Y, Py, T, p, a);
         }
       } else switch (e.kind) {
+        // The slice counts and Romberg depths of the standard rings get
+        // unrolled bodies in the double-precision kernel: sector bends with 8
+        // slices and 3 or 4 rows, MK quadrupoles with 4 slices and 3 rows, DKD
+        // quadrupoles with 8 slices and 3 rows.  Other elements take the loop.
         case K_SBEND:
-          q = thick_element<NT, 0, MIXED>(e, X, Px, Y, Py, T, p, a);
+          if (!MIXED && e.nsl == 8 && e.K == 3)
+            q = thick_element<NT, 0, MIXED, false, true, 8, 3>(e, X, Px, Y, Py, T, p, a);
+          else if (!MIXED && e.nsl == 8 && e.K == 2)
+            q = thick_element<NT, 0, MIXED, false, true, 8, 2>(e, X, Px, Y, Py, T, p, a);
+          else
+            q = thick_element<NT, 0, MIXED>(e, X, Px, Y, Py, T, p, a);
           break;
         case K_QUAD:
-          if (e.orbit != M_MK)   q = thick_element<NT, 2, MIXED>(e, X, Px, Y, Py, T, p, a);
-          else if (e.q.k1 >= 0.0) q = thick_element<NT, 1, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
-          else                   q = thick_element<NT, 3, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
+          if (e.orbit != M_MK) {
+            if (!MIXED && e.nsl == 8 && e.K == 2)
+              q = thick_element<NT, 2, MIXED, false, true, 8, 2>(e, X, Px, Y, Py, T, p, a);
+            else
+              q = thick_element<NT, 2, MIXED>(e, X, Px, Y, Py, T, p, a);
+          } else if (!MIXED && e.nsl == 4 && e.K == 2) {
+            if (e.q.k1 >= 0.0)
+              q = thick_element<NT, 1, MIXED, false, true, 4, 2>(e, X, Px, Y, Py, T, p, a, &mkc);
+            else
+              q = thick_element<NT, 3, MIXED, false, true, 4, 2>(e, X, Px, Y, Py, T, p, a, &mkc);
+          } else if (e.q.k1 >= 0.0) {
+            q = thick_element<NT, 1, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
+          } else {
+            q = thick_element<NT, 3, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
+          }
           break;
         case K_THIN:
           q = thin_element<NT>(e, X, Px, Y, Py, p, a);

@@ -42,13 +42,13 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(binding.st_element) == 6 * 4 + 10 * 8
     assert binding.st_element.L.offset == 24
     assert ctypes.sizeof(binding.st_beam) == 3 * 8 + 2 * 4
-    assert ctypes.sizeof(binding.st_peaks) == 3 * 8
+    assert ctypes.sizeof(binding.st_peaks) == 4 * 8
     text = open(HEADER).read()
     assert "int32_t kind, orbit, n_slices, romberg_rows, spin_place, fringe;" in text
     assert "double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks, asym;" in text
     assert "double G, gamma0, aperture;" in text
     assert "int32_t precision, report_every;" in text
-    assert "double fp64_fma_tflops, bf16_mfma_tflops, copy_gbps;" in text
+    assert "double fp64_fma_tflops, bf16_mfma_tflops, copy_gbps, fp32_fma_tflops;" in text
 
 
 def test_null_context_and_bad_device_are_rejected_without_device_work():
