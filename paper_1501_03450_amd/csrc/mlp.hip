@@ -10,13 +10,17 @@
 //
 // Kernels (one batch, 64 samples per workgroup of four waves):
 //   forward        all four layers fused, activations kept in LDS; when
-//                  training it stores the pre-activations (fp32,
-//                  sample-major) and the activations (bf16, feature-major,
-//                  copied out of LDS in 128-byte rows) for the backward pass
-//                  and fuses the loss and dL/dy of the normalised output
-//   backward_data  dL/dy -> dz3 -> dz2 -> dz1 through the transposed bf16
-//                  weights, with per-workgroup partial sums of the bias and
-//                  vector-layer weight gradients
+//                  training it stores the two hidden activations the weight
+//                  gradients need (bf16, feature-major, copied out of LDS in
+//                  128-byte rows) and fuses the loss and dL/dy of the
+//                  normalised output
+//   backward_data  recomputes the pre-activations z1, z2, z3 of its tile
+//                  from the inputs and the stored bf16 activations with the
+//                  forward pass's own arithmetic (the same MFMA calls in the
+//                  same order, so the same bits), then dL/dy -> dz3 -> dz2 ->
+//                  dz1 through the transposed bf16 weights, with
+//                  per-workgroup partial sums of the bias and vector-layer
+//                  weight gradients
 //   weight_grad    dW2, dW3 = dzᵀ hᵀ as split-K MFMA GEMMs over the batch
 //   reduce         fixed-order sum of the partials (deterministic)
 //   adam           fp32 master weights, then the bf16 copies W and Wᵀ
@@ -47,30 +51,38 @@ __device__ __forceinline__ float dsilu(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
-// acc[mt][nt] += A[64 x 256] (LDS, row stride LDA) · B'[n_base + 16 nt + j][k]
-// (global, row-major [256][256]) for the wave's 64 output columns.  The
-// loop is unrolled, so the compiler issues the B loads of later k steps
-// ahead of the MFMAs; the L2 latency that remains is covered by the other
-// waves on the SIMD (four per SIMD: the kernels that call this are compiled
-// for that occupancy).
-__device__ __forceinline__ void gemm_64x64(const __bf16* A, const __bf16* Bg, int n_base,
-                                           f32x4 acc[4][4], int lane) {
+// acc[mt][nt] += A[16 MT x 256] (LDS, row stride LDA) · B'[n_base + 16 nt + j][k]
+// (global, row-major [256][256]) for the wave's 64 output columns.  Each
+// 16x16 output tile accumulates over k in the same order whatever MT and
+// UNROLL are, so a tile computed in a smaller call has the same bits.  With
+// the loop unrolled (UNROLL = 8) the compiler issues the B loads of later k
+// steps ahead of the MFMAs; the L2 latency that remains is covered by the
+// other waves on the SIMD.  Callers short of registers unroll by 2.
+template <int MT, int UNROLL = 8>
+__device__ __forceinline__ void gemm_tiles(const __bf16* A, const __bf16* Bg, int n_base,
+                                           f32x4 acc[MT][4], int lane) {
   const int r = lane & 15, kb = 8 * (lane >> 4);
   const __bf16* brow = Bg + (size_t)(n_base + r) * W + kb;
-#pragma unroll
+#pragma unroll UNROLL
   for (int k0 = 0; k0 < W; k0 += 32) {
-    bf16x8 a[4], b[4];
+    bf16x8 a[MT], b[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) b[nt] = *reinterpret_cast<const bf16x8*>(brow + nt * 16 * W + k0);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
       a[mt] = *reinterpret_cast<const bf16x8*>(A + (mt * 16 + r) * LDA + k0 + kb);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
         acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
   }
+}
+
+template <int UNROLL = 8>
+__device__ __forceinline__ void gemm_64x64(const __bf16* A, const __bf16* Bg, int n_base,
+                                           f32x4 acc[4][4], int lane) {
+  gemm_tiles<4, UNROLL>(A, Bg, n_base, acc, lane);
 }
 
 __device__ __forceinline__ void zero_acc(f32x4 acc[4][4]) {
@@ -80,13 +92,9 @@ __device__ __forceinline__ void zero_acc(f32x4 acc[4][4]) {
     for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
-// Hidden-layer epilogue: z = acc + b, h = silu(z) into LDS (bf16, row-major)
-// and, when training, z (fp32) sample-major [ld][256] in HBM (16 lanes write
-// 64 contiguous bytes of one sample).
-template <bool TRAIN>
+// Hidden-layer epilogue: z = acc + b, h = silu(z) into LDS (bf16, row-major).
 __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const float* bias,
-                                                __bf16* out_lds, float* zS, int64_t b0, int rows,
-                                                int n_base, int lane) {
+                                                __bf16* out_lds, int rows, int n_base, int lane) {
   const int c = lane & 15, rq = 4 * (lane >> 4);
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -99,40 +107,26 @@ __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const flo
       for (int i = 0; i < 4; ++i) {
         const float z = acc[mt][nt][i] + bn;
         // padded samples (beyond the batch) carry zero activations
-        const bool ok = m0 + i < rows;
-        out_lds[(m0 + i) * LDA + n] = (__bf16)(ok ? silu(z) : 0.0f);
-        if (TRAIN) zS[(size_t)(b0 + m0 + i) * W + n] = ok ? z : 0.0f;
+        out_lds[(m0 + i) * LDA + n] = (__bf16)(m0 + i < rows ? silu(z) : 0.0f);
       }
     }
   }
 }
 
-// Backward epilogue of a hidden layer: dz = acc ⊙ silu'(z) into LDS (bf16,
-// row-major), z read from HBM sample-major.  The pre-activations of one
-// 16-sample block are loaded together, the four 16-feature pieces of a row
-// back to back, so that both halves of each 128-byte line are requested at
-// once (requested apart, a line can leave the L2 in between and be fetched
-// twice).
-__device__ __forceinline__ void backward_epilogue(const f32x4 acc[4][4], const float* zS,
-                                                  __bf16* out_lds, int64_t b0, int rows,
-                                                  int n_base, int lane) {
+// A wave's 64 x 64 block of gradients into LDS (bf16, row-major); samples
+// beyond the batch get zeros.
+__device__ __forceinline__ void store_grad_tile(const f32x4 acc[4][4], __bf16* out_lds, int rows,
+                                                int n_base, int lane) {
   const int c = lane & 15, rq = 4 * (lane >> 4);
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
     const int m0 = mt * 16 + rq;
-    float zv[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
-        zv[i][nt] = m0 + i < rows ? zS[(size_t)(b0 + m0 + i) * W + n_base + nt * 16 + c] : 0.0f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        const float dz = m0 + i < rows ? acc[mt][nt][i] * dsilu(zv[i][nt]) : 0.0f;
-        out_lds[(m0 + i) * LDA + n_base + nt * 16 + c] = (__bf16)dz;
-      }
+        out_lds[(m0 + i) * LDA + n_base + nt * 16 + c] =
+            (__bf16)(m0 + i < rows ? acc[mt][nt][i] : 0.0f);
   }
 }
 
@@ -147,6 +141,18 @@ __device__ __forceinline__ void store_feature_major(const __bf16* lds, __bf16* o
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = lds[(ch * 8 + e) * LDA + n];
     *reinterpret_cast<bf16x8*>(outT + (size_t)n * ld + b0 + ch * 8) = v;
+  }
+}
+
+// The inverse copy: columns b0..b0+63 of a feature-major [256][ld] bf16 array
+// into LDS sample-major (pitch LDA).
+__device__ __forceinline__ void load_feature_major(const __bf16* inT, int64_t ld, int64_t b0,
+                                                   __bf16* lds, int tid) {
+  for (int it = tid; it < W * (TM / 8); it += NT) {
+    const int n = it >> 3, ch = it & 7;
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(inT + (size_t)n * ld + b0 + ch * 8);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lds[(ch * 8 + e) * LDA + n] = v[e];
   }
 }
 
@@ -187,7 +193,6 @@ mlp_forward_kernel(const MlpArgs a) {
 #pragma unroll
       for (int k = 0; k < kMlpMaxIn; ++k) z = fmaf(w[k], xs[m][k], z);
       bufA[m * LDA + n] = (__bf16)(m < rows ? silu(z) : 0.0f);
-      if (TRAIN) a.zS1[(size_t)(b0 + m) * W + n] = m < rows ? z : 0.0f;
     }
   }
   __syncthreads();
@@ -198,14 +203,14 @@ mlp_forward_kernel(const MlpArgs a) {
   zero_acc(acc);
   gemm_64x64(bufA, a.W2b, wv * 64, acc, lane);
   __syncthreads();
-  hidden_epilogue<TRAIN>(acc, P + a.off.b2, bufA, a.zS2, b0, rows, wv * 64, lane);
+  hidden_epilogue(acc, P + a.off.b2, bufA, rows, wv * 64, lane);
   __syncthreads();
   if (TRAIN) store_feature_major(bufA, a.hT2, a.ld, b0, tid);
   // layer 3 (MFMA)
   zero_acc(acc);
   gemm_64x64(bufA, a.W3b, wv * 64, acc, lane);
   __syncthreads();
-  hidden_epilogue<TRAIN>(acc, P + a.off.b3, bufA, a.zS3, b0, rows, wv * 64, lane);
+  hidden_epilogue(acc, P + a.off.b3, bufA, rows, wv * 64, lane);
   __syncthreads();
 
   // layer 4 (vector): thread t -> sample t % 64, output t / 64
@@ -254,11 +259,17 @@ mlp_forward_kernel(const MlpArgs a) {
   }
 }
 
-// Backward through the layers for one tile of samples (four waves per SIMD,
-// as the forward kernel).
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
+// Backward through the layers for one tile of samples.  The pre-activations
+// are recomputed here rather than stored by the forward pass: z2 and z3 by
+// the forward pass's MFMA sums on the bf16 activations it stored for the
+// weight gradients (same operands, same order, so the same bits), z1 by its
+// vector loop.  z3 reaches the per-feature loop of the last layer through a
+// 16-sample chunk of LDS per wave; z2 is recomputed 32 samples at a time
+// while dz3 W3 is held, which keeps the kernel within two waves' registers.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 mlp_backward_data_kernel(const MlpArgs a) {
   __shared__ __align__(16) __bf16 bufA[TM * LDA];   // one buffer, as in the forward pass
+  __shared__ float zc[NT / 64][16][64];             // z3 of 16 samples x a wave's features
   __shared__ float xs[TM][kMlpMaxIn];
   __shared__ float dys[TM][4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -267,6 +278,7 @@ mlp_backward_data_kernel(const MlpArgs a) {
   const int nin = a.n_in;
   const float* P = a.params;
   const int blk = blockIdx.x;
+  const int n_base = wv * 64, c = lane & 15, rq = 4 * (lane >> 4);
 
   for (int i = tid; i < TM * kMlpMaxIn; i += NT) {
     const int m = i / kMlpMaxIn, k = i % kMlpMaxIn;
@@ -276,6 +288,7 @@ mlp_backward_data_kernel(const MlpArgs a) {
     const int m = i / 4, j = i % 4;
     dys[m][j] = m < rows ? a.dy[(b0 + m) * 4 + j] : 0.0f;
   }
+  load_feature_major(a.hT2, a.ld, b0, bufA, tid);
   __syncthreads();
   if (tid < 4) {
     float s = 0.0f;
@@ -283,26 +296,34 @@ mlp_backward_data_kernel(const MlpArgs a) {
     a.gpart_b4[(size_t)blk * 4 + tid] = s;
   }
 
-  // dz3 = (dy W4) ⊙ silu'(z3); dW4 and db3 partials
+  // z3 - b3 = W3 h2, as in the forward pass
+  f32x4 acc[4][4];
+  zero_acc(acc);
+  gemm_64x64<2>(bufA, a.W3b, n_base, acc, lane);
+  __syncthreads();   // bufA: h2 -> dz3
+
+  // dz3 = (dy W4) ⊙ silu'(z3); dW4 and db3 partials.  Thread k = feature k
+  // runs through the samples in order, 16 at a time.
   {
     const int k = tid;
     const float w0 = P[a.off.W4 + 0 * W + k], w1 = P[a.off.W4 + 1 * W + k];
     const float w2 = P[a.off.W4 + 2 * W + k], w3 = P[a.off.W4 + 3 * W + k];
     float gw[4] = {0.f, 0.f, 0.f, 0.f}, gb = 0.0f;
-    // the pre-activations of 16 samples are loaded together, so that one
-    // memory latency covers them (the sums still run in sample order)
-    constexpr int kChunk = 16;
-    for (int m0 = 0; m0 < TM; m0 += kChunk) {
-      float zv[kChunk];
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u)
-        zv[u] = m0 + u < rows ? a.zS3[(size_t)(b0 + m0 + u) * W + k] : 0.0f;
+    for (int mt = 0; mt < 4; ++mt) {   // unrolled: acc is indexed by mt
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        const int m = m0 + u;
+      for (int nt = 0; nt < 4; ++nt) {
+        const float bn = P[a.off.b3 + n_base + nt * 16 + c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) zc[wv][rq + i][nt * 16 + c] = acc[mt][nt][i] + bn;
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int u = 0; u < 16; ++u) {
+        const int m = mt * 16 + u;
         float dz = 0.0f;
         if (m < rows) {
-          const float z = zv[u];
+          const float z = zc[wv][u][lane];
           const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
           dz = dh * dsilu(z);
           // the activation as the forward pass used it (bf16), so that dW4
@@ -316,19 +337,39 @@ mlp_backward_data_kernel(const MlpArgs a) {
         }
         bufA[m * LDA + k] = (__bf16)dz;
       }
+      __syncthreads();   // zc is rewritten by the next chunk
     }
     for (int j = 0; j < 4; ++j) a.gpart_W4[((size_t)blk * 4 + j) * W + k] = gw[j];
     a.gpart_b3[(size_t)blk * W + k] = gb;
   }
-  __syncthreads();
   store_feature_major(bufA, a.dzT3, a.ld, b0, tid);
 
-  f32x4 acc[4][4];
-  // dz2 = (dz3 W3) ⊙ silu'(z2)
+  // dz2 = (dz3 W3) ⊙ silu'(z2), z2 = W2 h1 + b2 as in the forward pass
   zero_acc(acc);
-  gemm_64x64(bufA, a.W3Tb, wv * 64, acc, lane);
-  __syncthreads();   // bufA is overwritten below
-  backward_epilogue(acc, a.zS2, bufA, b0, rows, wv * 64, lane);
+  gemm_64x64<2>(bufA, a.W3Tb, n_base, acc, lane);
+  __syncthreads();   // bufA: dz3 -> h1
+  load_feature_major(a.hT1, a.ld, b0, bufA, tid);
+  __syncthreads();
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    f32x4 z2[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) z2[t][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    gemm_tiles<2, 2>(bufA + half * 32 * LDA, a.W2b, n_base, z2, lane);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const float bn = P[a.off.b2 + n_base + nt * 16 + c];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[2 * half + t][nt][i] = acc[2 * half + t][nt][i] * dsilu(z2[t][nt][i] + bn);
+    }
+  }
+  __syncthreads();   // bufA: h1 -> dz2
+  store_grad_tile(acc, bufA, rows, n_base, lane);
   __syncthreads();
   store_feature_major(bufA, a.dzT2, a.ld, b0, tid);
   {
@@ -336,11 +377,38 @@ mlp_backward_data_kernel(const MlpArgs a) {
     for (int m = 0; m < rows; ++m) s += (float)bufA[m * LDA + tid];
     a.gpart_b2[(size_t)blk * W + tid] = s;
   }
-  // dz1 = (dz2 W2) ⊙ silu'(z1)
+  // dz1 = (dz2 W2) ⊙ silu'(z1), z1 = W1 x + b1 as in the forward pass (the
+  // lane's four feature columns share each sample's inputs)
   zero_acc(acc);
-  gemm_64x64(bufA, a.W2Tb, wv * 64, acc, lane);
-  __syncthreads();   // bufA is reused below
-  backward_epilogue(acc, a.zS1, bufA, b0, rows, wv * 64, lane);
+  gemm_64x64<2>(bufA, a.W2Tb, n_base, acc, lane);
+  {
+    float w[4][kMlpMaxIn], bn[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int n = n_base + nt * 16 + c;
+#pragma unroll
+      for (int k = 0; k < kMlpMaxIn; ++k) w[nt][k] = k < nin ? P[a.off.W1 + n * nin + k] : 0.0f;
+      bn[nt] = P[a.off.b1 + n];
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = mt * 16 + rq + i;
+        float xr[kMlpMaxIn];
+#pragma unroll
+        for (int k = 0; k < kMlpMaxIn; ++k) xr[k] = xs[m][k];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          float z = bn[nt];
+#pragma unroll
+          for (int k = 0; k < kMlpMaxIn; ++k) z = fmaf(w[nt][k], xr[k], z);
+          acc[mt][nt][i] = acc[mt][nt][i] * dsilu(z);
+        }
+      }
+  }
+  __syncthreads();   // bufA: dz2 -> dz1
+  store_grad_tile(acc, bufA, rows, n_base, lane);
   __syncthreads();
   {
     const int n = tid;

@@ -27,7 +27,6 @@ struct st_mlp {
   // training scratch, sized for the largest batch seen
   int64_t cap_ld = 0;
   std::vector<void*> scratch;
-  float *zS[3] = {nullptr, nullptr, nullptr};
   __bf16 *hT[2] = {nullptr, nullptr};
   __bf16 *dzT[2] = {nullptr, nullptr};
   float *dy = nullptr, *loss_part = nullptr, *red_tmp = nullptr;
@@ -87,7 +86,6 @@ st_status ensure_scratch(st_mlp* m, int64_t ld) {
   const int64_t W = st::kMlpWidth;
   const int64_t nb = ld / st::mlp_tile();
   hipError_t e = hipSuccess;
-  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = alloc(m, &m->zS[l], (size_t)(W * ld));
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->hT[l], (size_t)(W * ld));
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->dzT[l], (size_t)(W * ld));
   if (e == hipSuccess) e = alloc(m, &m->dy, (size_t)(ld * 4));
@@ -156,7 +154,6 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
   a.inv_loss_norm = 1.0f / (float)batch;
   a.loss_part = m->loss_part;
   a.dy = m->dy;
-  a.zS1 = m->zS[0]; a.zS2 = m->zS[1]; a.zS3 = m->zS[2];
   a.hT1 = m->hT[0]; a.hT2 = m->hT[1];
   a.dzT2 = m->dzT[0]; a.dzT3 = m->dzT[1];
   a.gpart_W1 = m->gW1; a.gpart_b1 = m->gb1; a.gpart_b2 = m->gb2; a.gpart_b3 = m->gb3;

@@ -55,9 +55,6 @@ struct MlpArgs {
   float out_scale[4];
   float inv_loss_norm;    // 1/batch
   float* loss_part;       // [blocks]
-  float* zS1;             // [ld][256] pre-activations, sample-major
-  float* zS2;
-  float* zS3;
   __bf16* hT1;            // [256][ld] activations, feature-major
   __bf16* hT2;
   __bf16* dzT2;           // [256][ld] gradients at the pre-activations
