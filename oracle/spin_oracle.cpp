@@ -173,7 +173,10 @@ template <class T> Quat<T> qconj(const Quat<T>& a) { return {a.w, -a.x, -a.y, -a
 template <class T> Quat<T> qrot(T wx, T wy, T wz) {
   using std::cos; using std::sin; using std::sqrt;
   T th = sqrt(wx * wx + wy * wy + wz * wz);
-  if (th == T(0)) return qident<T>();
+  // At zero angle the quaternion is the identity, and its first derivative
+  // is (0, ½ dω): sin(θ/2)/θ tends to ½ while cos(θ/2) is flat.  Written
+  // with ω itself so that forward-mode derivatives keep that term.
+  if (th == T(0)) return {T(1), T(0.5) * wx, T(0.5) * wy, T(0.5) * wz};
   T c = cos(th / T(2));
   T f = sin(th / T(2)) / th;
   return {c, f * wx, f * wy, f * wz};

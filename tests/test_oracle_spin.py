@@ -263,3 +263,37 @@ def test_paper_ir_quad_four_slices_two_romberg_steps_gain_four_decades():
     pwc256 = np.abs(run([quad(qd["L"], k1, "mk", 256, 1)], z0, s0, beam=beam)[1] - sb).max()
     pwc512 = np.abs(run([quad(qd["L"], k1, "mk", 512, 1)], z0, s0, beam=beam)[1] - sb).max()
     assert pwc512 < rom4 < pwc256
+
+
+def test_quaternion_derivatives_at_the_design_orbit_match_differences_of_tracked_values():
+    # Forward-mode dQ of the one-turn quaternion at the design orbit, where the
+    # quadrupoles rotate the spin by exactly zero, against central differences
+    # of tracked quaternions (values only, extended precision).
+    from workloads.lattice import drift as _drift
+    ring = small_ring()
+    jac = oracle.jacobian(ring, BEAM, np.zeros(6))
+    h = 1e-9
+    fd = np.zeros((4, 6))
+    for i in range(6):
+        z = np.zeros((6, 2))
+        z[i, 0], z[i, 1] = h, -h
+        s = np.zeros((3, 2))
+        s[1] = 1.0
+        q = oracle.track(ring, BEAM, z, s, turns=1, want_quaternion=True)["q"]
+        fd[:, i] = (q[:, 0] - q[:, 1]) / (2 * h)
+    assert np.abs(fd).max() > 1.0                      # the quadrupoles' share is not small
+    assert np.abs(jac["dQ"] - fd).max() <= 1e-6 * np.abs(fd).max()
+    # a ring of drifts and quadrupoles alone: Ω = 0 on the design orbit, so
+    # every spin derivative there comes from the zero-angle quaternions
+    straight = [quad(1.0, 0.05, "mk", 4, 3), _drift(2.0), quad(1.0, -0.05, "mk", 4, 3), _drift(2.0)]
+    j2 = oracle.jacobian(straight, BEAM, np.zeros(6))
+    fd2 = np.zeros((4, 6))
+    for i in range(6):
+        z = np.zeros((6, 2))
+        z[i, 0], z[i, 1] = h, -h
+        s = np.zeros((3, 2))
+        s[1] = 1.0
+        q = oracle.track(straight, BEAM, z, s, turns=1, want_quaternion=True)["q"]
+        fd2[:, i] = (q[:, 0] - q[:, 1]) / (2 * h)
+    assert np.abs(fd2).max() > 1e-2
+    assert np.abs(j2["dQ"] - fd2).max() <= 1e-6 * np.abs(fd2).max()
