@@ -303,6 +303,39 @@ st_status st_mlp_params(st_mlp* m, float* h_get, const float* h_set, int64_t* n_
 st_status st_mlp_set_frame(st_mlp* m, const double* ref, const double* scale);
 
 /* Passage: not in the paper (learned spin surrogate).
+ * Linear part of the output frame: u = ref + lin x + scale ⊙ y, with x the
+ * network's inputs and lin host row-major [4][n_in] doubles (finite; stored as
+ * floats); NULL clears it (the default).  Applies wherever st_mlp_set_frame's
+ * frame does.  ST_EINVAL for a non-finite value. */
+st_status st_mlp_set_linear_frame(st_mlp* m, const double* lin);
+
+/* Result of st_mlp_fit_frame (host struct; lin rows hold n_in used columns,
+ * the rest zero). */
+typedef struct {
+  double ref[4];         /* intercept of each component */
+  double lin[4][8];      /* slope per input */
+  double scale[4];       /* max(resid_rms, floor) */
+  double resid_rms[4];   /* RMS of the targets about ref + lin x */
+  double resid_max[4];   /* largest residual magnitude */
+} st_frame_fit;
+
+/* Passage: not in the paper (learned spin surrogate).
+ * Double-precision least-squares fit of the targets d_t [n][4] on the inputs
+ * d_x [n][n_in] (device floats) plus a constant: the affine map ref + lin x
+ * that minimises the summed squared residual of every component, from the
+ * normal equations summed on the device in double (fixed order) and solved
+ * on the host by Cholesky, with a ridge of 1e-12 of the mean diagonal on the
+ * input columns.  Then it sets the network's whole frame: ref and lin as
+ * fitted, scale = max(RMS residual, floor) per component, so that the network
+ * learns only what the affine map leaves.  *out (host, may be NULL) receives
+ * the fit.  Synchronous on `stream` (returns after the fit); allocates and
+ * frees about 0.5 MB of device memory.  ST_EINVAL for NULL inputs, n <
+ * n_in + 1, floor <= 0, or inputs whose normal equations are not positive
+ * definite; ST_ENOMEM, ST_EDEVICE on device failures. */
+st_status st_mlp_fit_frame(st_mlp* m, const float* d_x, const float* d_t, int64_t n, double floor,
+                           st_frame_fit* out, void* stream);
+
+/* Passage: not in the paper (learned spin surrogate).
  * One Adam step (learning rate lr > 0) on `batch` samples: inputs d_x, unit
  * quaternion targets d_t (device).  d_loss (device, 1 float, may be NULL)
  * receives the batch's mean loss before the step.  Queued on `stream`. */

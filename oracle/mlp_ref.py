@@ -51,9 +51,9 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(params, x, round_act=None, ref=None, scale=None):
-    """q = u/|u| with u = ref + scale ⊙ y for a batch x [B][n_in] (the output
-    frame; ref = 0, scale = 1 by default).  round_act, when given, is applied
+def forward(params, x, round_act=None, ref=None, scale=None, lin=None):
+    """q = u/|u| with u = ref + lin x + scale ⊙ y for a batch x [B][n_in] (the
+    output frame; ref = 0, lin = 0, scale = 1 by default).  round_act, when given, is applied
     to each hidden activation before it enters the next layer (the GPU
     kernels hold them in bf16)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = params
@@ -66,6 +66,8 @@ def forward(params, x, round_act=None, ref=None, scale=None):
     h3 = r(silu(z3))
     y = h3 @ W4.T + b4
     u = _frame(y, ref, scale)
+    if lin is not None:
+        u = u + x @ np.asarray(lin, dtype=np.float64).T
     q = u / np.linalg.norm(u, axis=1, keepdims=True)
     return q, (x, z1, h1, z2, h2, z3, h3, u)
 
@@ -76,12 +78,12 @@ def _frame(y, ref, scale):
     return ref + scale * y
 
 
-def loss(params, x, t, ref=None, scale=None, round_act=None):
-    q, _ = forward(params, x, round_act=round_act, ref=ref, scale=scale)
+def loss(params, x, t, ref=None, scale=None, round_act=None, lin=None):
+    q, _ = forward(params, x, round_act=round_act, ref=ref, scale=scale, lin=lin)
     return float(np.mean(np.sum((q - t) ** 2, axis=1)))
 
 
-def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None):
+def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None, lin=None):
     """Gradients of L with respect to every parameter (same order).
 
     With round_act and round_dz (both None: plain float64) the gradient
@@ -92,7 +94,7 @@ def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None):
     W1, b1, W2, b2, W3, b3, W4, b4 = params
     rd = round_dz if round_dz is not None else (lambda v: v)
     q, (x, z1, h1, z2, h2, z3, h3, u) = forward(params, x, round_act=round_act, ref=ref,
-                                                scale=scale)
+                                                scale=scale, lin=lin)
     B = x.shape[0]
     dq = 2.0 * (q - t) / B
     nu = np.linalg.norm(u, axis=1, keepdims=True)
@@ -111,6 +113,21 @@ def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None):
     gW1 = dz1.T @ x
     gb1 = dz1.sum(0)
     return [gW1, gb1, gW2, gb2, gW3, gb3, gW4, gb4]
+
+
+def fit_frame(x, t, floor):
+    """Affine frame by least squares: the intercept ref [4] and slopes lin
+    [4][n_in] minimising sum |t - ref - lin x|^2 per component over the
+    samples, the RMS and largest residual per component, and scale =
+    max(RMS, floor).  numpy's least-squares solver in float64."""
+    x = np.asarray(x, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    A = np.concatenate([np.ones((x.shape[0], 1)), x], axis=1)
+    c, *_ = np.linalg.lstsq(A, t, rcond=None)
+    r = t - A @ c
+    rms = np.sqrt(np.mean(r * r, axis=0))
+    return {"ref": c[0], "lin": c[1:].T, "resid_rms": rms, "resid_max": np.abs(r).max(axis=0),
+            "scale": np.maximum(rms, floor)}
 
 
 def adam_step(theta, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

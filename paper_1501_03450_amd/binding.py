@@ -33,7 +33,8 @@ PRECISION_CODES = {"fp64": ST_FP64, "mixed": ST_MIXED, "mixed_all": ST_MIXED_ALL
 EXPORTS = ("st_create", "st_destroy", "st_load_lattice", "st_bind_particles",
            "st_bind_quaternions", "st_track", "st_track_noalloc", "st_polarization", "st_read_particles",
            "st_last_error", "st_mlp_create", "st_mlp_destroy", "st_mlp_last_error",
-           "st_mlp_params", "st_mlp_set_frame", "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
+           "st_mlp_params", "st_mlp_set_frame", "st_mlp_set_linear_frame", "st_mlp_fit_frame",
+           "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
            "st_mlp_features", "st_mlp_targets", "st_track_surrogate", "st_measure_peaks")
 
 
@@ -50,6 +51,12 @@ class st_element(ctypes.Structure):
 class st_peaks(ctypes.Structure):
     _fields_ = [("fp64_fma_tflops", ctypes.c_double), ("bf16_mfma_tflops", ctypes.c_double),
                 ("copy_gbps", ctypes.c_double), ("fp32_fma_tflops", ctypes.c_double)]
+
+
+class st_frame_fit(ctypes.Structure):
+    _fields_ = [("ref", ctypes.c_double * 4), ("lin", (ctypes.c_double * 8) * 4),
+                ("scale", ctypes.c_double * 4), ("resid_rms", ctypes.c_double * 4),
+                ("resid_max", ctypes.c_double * 4)]
 
 
 class st_beam(ctypes.Structure):
@@ -88,6 +95,8 @@ def _load():
     lib.st_mlp_last_error.restype = ctypes.c_char_p
     lib.st_mlp_params.argtypes = [vp, vp, vp, P(i64)]
     lib.st_mlp_set_frame.argtypes = [vp, P(f64), P(f64)]
+    lib.st_mlp_set_linear_frame.argtypes = [vp, P(f64)]
+    lib.st_mlp_fit_frame.argtypes = [vp, vp, vp, i64, f64, P(st_frame_fit), vp]
     lib.st_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp]
     lib.st_mlp_gradient.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.st_mlp_infer.argtypes = [vp, vp, vp, i64, vp]
@@ -236,6 +245,24 @@ def st_mlp_set_frame(m, ref, scale):
     r = (ctypes.c_double * 4)(*[float(x) for x in ref])
     c = (ctypes.c_double * 4)(*[float(x) for x in scale])
     _check_mlp(m, LIB.st_mlp_set_frame(m, r, c))
+
+
+def st_mlp_set_linear_frame(m, lin=None):
+    """lin: [4][n_in] values (None clears the linear part)."""
+    if lin is None:
+        _check_mlp(m, LIB.st_mlp_set_linear_frame(m, None))
+        return
+    flat = [float(v) for row in lin for v in row]
+    _check_mlp(m, LIB.st_mlp_set_linear_frame(m, (ctypes.c_double * len(flat))(*flat)))
+
+
+def st_mlp_fit_frame(m, x_ptr, t_ptr, n, floor, stream=None) -> dict:
+    """The fitted frame as a dict of lists (lin rows with 8 columns)."""
+    f = st_frame_fit()
+    _check_mlp(m, LIB.st_mlp_fit_frame(m, x_ptr, t_ptr, int(n), float(floor), ctypes.byref(f),
+                                       stream))
+    return {"ref": list(f.ref), "lin": [list(r) for r in f.lin], "scale": list(f.scale),
+            "resid_rms": list(f.resid_rms), "resid_max": list(f.resid_max)}
 
 
 def st_mlp_train_step(m, x_ptr, t_ptr, batch, lr, loss_ptr=None, stream=None):

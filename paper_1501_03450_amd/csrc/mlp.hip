@@ -230,10 +230,19 @@ mlp_forward_kernel(const MlpArgs a) {
   float l = 0.0f;
   if (tid < TM && tid < rows) {
     const int m = tid;
-    const float y0 = fmaf(a.out_scale[0], ys[m][0], a.out_ref[0]);
-    const float y1 = fmaf(a.out_scale[1], ys[m][1], a.out_ref[1]);
-    const float y2 = fmaf(a.out_scale[2], ys[m][2], a.out_ref[2]);
-    const float y3 = fmaf(a.out_scale[3], ys[m][3], a.out_ref[3]);
+    // frame base ref + lin x (zero columns past n_in: xs is zero-padded)
+    float base[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float b = a.out_ref[j];
+#pragma unroll
+      for (int k = 0; k < kMlpMaxIn; ++k) b = fmaf(a.out_lin[j][k], xs[m][k], b);
+      base[j] = b;
+    }
+    const float y0 = fmaf(a.out_scale[0], ys[m][0], base[0]);
+    const float y1 = fmaf(a.out_scale[1], ys[m][1], base[1]);
+    const float y2 = fmaf(a.out_scale[2], ys[m][2], base[2]);
+    const float y3 = fmaf(a.out_scale[3], ys[m][3], base[3]);
     const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2 + y3 * y3);
     const float inv = 1.0f / ny;
     const float q[4] = {y0 * inv, y1 * inv, y2 * inv, y3 * inv};
@@ -699,7 +708,81 @@ __global__ void __launch_bounds__(256) targets_kernel(const double* q, int64_t n
   t[j * 4 + 3] = (float)(s * z);
 }
 
+// Normal equations of the frame fit, one block per contiguous range of
+// samples: rows [1, x, t] of 256 samples at a time in LDS, thread v owns one
+// entry of [1,x][1,x]ᵀ (v < D*D) or of [1,x] tᵀ and sums it over the range in
+// sample order.
+__global__ void __launch_bounds__(256) fit_normal_kernel(const float* x, const float* t, int64_t n,
+                                                         int n_in, double* partials) {
+  constexpr int C = kMlpMaxIn + 1 + 4;
+  __shared__ double rows[256][C];
+  const int D = n_in + 1, V = D * D + 4 * D, tid = threadIdx.x;
+  const int64_t per = (n + kFitBlocks - 1) / kFitBlocks;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  const int p = tid < D * D ? tid / D : (tid - D * D) / 4;
+  const int q = tid < D * D ? tid % D : D + (tid - D * D) % 4;
+  double acc = 0.0;
+  for (int64_t c0 = lo; c0 < hi; c0 += 256) {
+    const int64_t j = c0 + tid;
+    const bool in = j < hi;
+    rows[tid][0] = in ? 1.0 : 0.0;
+    for (int k = 0; k < n_in; ++k) rows[tid][1 + k] = in ? (double)x[j * n_in + k] : 0.0;
+    for (int c = 0; c < 4; ++c) rows[tid][D + c] = in ? (double)t[j * 4 + c] : 0.0;
+    __syncthreads();
+    if (tid < V) {
+      const int m = (int)min((int64_t)256, hi - c0);
+      for (int i = 0; i < m; ++i) acc = fma(rows[i][p], rows[i][q], acc);
+    }
+    __syncthreads();
+  }
+  if (tid < V) partials[(int64_t)blockIdx.x * V + tid] = acc;
+}
+
+// Squared residuals of each component and their largest magnitude over one
+// block's range; tree reduction in a fixed order.
+__global__ void __launch_bounds__(256) fit_residual_kernel(const float* x, const float* t, int64_t n,
+                                                           int n_in, FitCoef cf, double* partials) {
+  __shared__ double red[256][8];
+  const int tid = threadIdx.x;
+  const int64_t per = (n + kFitBlocks - 1) / kFitBlocks;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  double ss[4] = {0.0, 0.0, 0.0, 0.0}, mx[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t j = lo + tid; j < hi; j += 256) {
+    for (int c = 0; c < 4; ++c) {
+      double f = cf.c[c][0];
+      for (int k = 0; k < n_in; ++k) f = fma(cf.c[c][1 + k], (double)x[j * n_in + k], f);
+      const double r = (double)t[j * 4 + c] - f;
+      ss[c] = fma(r, r, ss[c]);
+      mx[c] = fmax(mx[c], fabs(r));
+    }
+  }
+  for (int c = 0; c < 4; ++c) { red[tid][c] = ss[c]; red[tid][4 + c] = mx[c]; }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int c = 0; c < 4; ++c) {
+        red[tid][c] += red[tid + w][c];
+        red[tid][4 + c] = fmax(red[tid][4 + c], red[tid + w][4 + c]);
+      }
+    __syncthreads();
+  }
+  if (tid < 8) partials[(int64_t)blockIdx.x * 8 + tid] = red[0][tid];
+}
+
 }  // namespace
+
+hipError_t launch_fit_normal(const float* x, const float* t, int64_t n, int n_in, double* partials,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(fit_normal_kernel, dim3(kFitBlocks), dim3(256), 0, s, x, t, n, n_in, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_residual(const float* x, const float* t, int64_t n, int n_in,
+                               const FitCoef& coef, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(fit_residual_kernel, dim3(kFitBlocks), dim3(256), 0, s, x, t, n, n_in, coef,
+                     partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_features(const double* z, int64_t n, const FeatureMap& f, int n_in, float* x,
                            hipStream_t s) {

@@ -19,6 +19,7 @@ struct st_mlp {
   int64_t step = 0;                 // Adam steps taken
   float frame_ref[4] = {0.0f, 0.0f, 0.0f, 0.0f};    // output frame (st_mlp_set_frame)
   float frame_scale[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+  float frame_lin[4][st::kMlpMaxIn] = {};            // linear part (st_mlp_set_linear_frame)
   float* params = nullptr;          // fp32 master weights
   float* adam_m = nullptr;
   float* adam_v = nullptr;
@@ -135,7 +136,11 @@ st::MlpArgs base_args(st_mlp* m) {
   a.grad = m->grad;
   a.adam_m = m->adam_m;
   a.adam_v = m->adam_v;
-  for (int j = 0; j < 4; ++j) { a.out_ref[j] = m->frame_ref[j]; a.out_scale[j] = m->frame_scale[j]; }
+  for (int j = 0; j < 4; ++j) {
+    a.out_ref[j] = m->frame_ref[j];
+    a.out_scale[j] = m->frame_scale[j];
+    for (int k = 0; k < st::kMlpMaxIn; ++k) a.out_lin[j][k] = m->frame_lin[j][k];
+  }
   return a;
 }
 
@@ -284,6 +289,107 @@ st_status st_mlp_set_frame(st_mlp* m, const double* ref, const double* scale) {
       return fail(m, ST_EINVAL, "frame values must be finite with scale > 0");
   for (int j = 0; j < 4; ++j) { m->frame_ref[j] = (float)ref[j]; m->frame_scale[j] = (float)scale[j]; }
   return ST_OK;
+}
+
+st_status st_mlp_set_linear_frame(st_mlp* m, const double* lin) {
+  if (!m) return ST_EINVAL;
+  if (lin)
+    for (int i = 0; i < 4 * m->n_in; ++i)
+      if (!std::isfinite(lin[i])) return fail(m, ST_EINVAL, "linear frame values must be finite");
+  for (int j = 0; j < 4; ++j)
+    for (int k = 0; k < st::kMlpMaxIn; ++k)
+      m->frame_lin[j][k] = (lin && k < m->n_in) ? (float)lin[j * m->n_in + k] : 0.0f;
+  return ST_OK;
+}
+
+st_status st_mlp_fit_frame(st_mlp* m, const float* d_x, const float* d_t, int64_t n, double floor,
+                           st_frame_fit* out, void* stream) {
+  if (!m) return ST_EINVAL;
+  const int D = m->n_in + 1, V = D * D + 4 * D;
+  if (!d_x || !d_t) return fail(m, ST_EINVAL, "inputs or targets are NULL");
+  if (n < D || n > ((int64_t)1 << 40)) return fail(m, ST_EINVAL, "need at least n_in + 1 samples");
+  if (!(floor > 0.0) || !std::isfinite(floor)) return fail(m, ST_EINVAL, "floor must be > 0");
+  DeviceGuard g(m->device);
+  hipStream_t s = (hipStream_t)stream;
+  double* part = nullptr;
+  const int B = st::kFitBlocks;
+  hipError_t e = hipMalloc((void**)&part, (size_t)B * V * sizeof(double));
+  if (e != hipSuccess) return fail(m, ST_ENOMEM, std::string("fit scratch: ") + hipGetErrorString(e));
+  std::vector<double> h((size_t)B * V);
+  auto done = [&](st_status st) { (void)hipFree(part); return st; };
+  if ((e = st::launch_fit_normal(d_x, d_t, n, m->n_in, part, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess ||
+      (e = hipMemcpy(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+    return done(hip_fail(m, e, "frame fit, normal equations"));
+  // block partials summed in block order
+  std::vector<double> sum((size_t)V, 0.0);
+  for (int b = 0; b < B; ++b)
+    for (int v = 0; v < V; ++v) sum[(size_t)v] += h[(size_t)b * V + v];
+  double G[st::kMlpMaxIn + 1][st::kMlpMaxIn + 1], R[st::kMlpMaxIn + 1][4];
+  double trace = 0.0;
+  for (int p = 0; p < D; ++p) {
+    for (int q = 0; q < D; ++q) G[p][q] = sum[(size_t)(p * D + q)];
+    for (int c = 0; c < 4; ++c) R[p][c] = sum[(size_t)(D * D + p * 4 + c)];
+    trace += G[p][p];
+  }
+  // a ridge of 1e-12 of the mean diagonal on the input columns keeps a
+  // constant-zero input (a band of one energy) solvable, with coefficient 0
+  for (int p = 1; p < D; ++p) G[p][p] += 1e-12 * trace / D;
+  // Cholesky G = L Lᵀ, then L Lᵀ c = R for the four components
+  double L[st::kMlpMaxIn + 1][st::kMlpMaxIn + 1] = {};
+  for (int p = 0; p < D; ++p) {
+    for (int q = 0; q <= p; ++q) {
+      double v = G[p][q];
+      for (int k = 0; k < q; ++k) v -= L[p][k] * L[q][k];
+      if (p == q) {
+        if (!(v > 0.0)) return done(fail(m, ST_EINVAL, "frame fit: inputs are degenerate"));
+        L[p][p] = std::sqrt(v);
+      } else {
+        L[p][q] = v / L[q][q];
+      }
+    }
+  }
+  st::FitCoef cf{};
+  for (int c = 0; c < 4; ++c) {
+    double y[st::kMlpMaxIn + 1];
+    for (int p = 0; p < D; ++p) {
+      double v = R[p][c];
+      for (int k = 0; k < p; ++k) v -= L[p][k] * y[k];
+      y[p] = v / L[p][p];
+    }
+    for (int p = D - 1; p >= 0; --p) {
+      double v = y[p];
+      for (int k = p + 1; k < D; ++k) v -= L[k][p] * cf.c[c][k];
+      cf.c[c][p] = v / L[p][p];
+    }
+  }
+  if ((e = st::launch_fit_residual(d_x, d_t, n, m->n_in, cf, part, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess ||
+      (e = hipMemcpy(h.data(), part, (size_t)B * 8 * sizeof(double), hipMemcpyDeviceToHost)) !=
+          hipSuccess)
+    return done(hip_fail(m, e, "frame fit, residuals"));
+  double ss[4] = {0.0, 0.0, 0.0, 0.0}, mx[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < B; ++b)
+    for (int c = 0; c < 4; ++c) {
+      ss[c] += h[(size_t)b * 8 + c];
+      mx[c] = std::max(mx[c], h[(size_t)b * 8 + 4 + c]);
+    }
+  st_frame_fit f;
+  std::memset(&f, 0, sizeof(f));
+  for (int c = 0; c < 4; ++c) {
+    f.ref[c] = cf.c[c][0];
+    for (int k = 0; k < m->n_in; ++k) f.lin[c][k] = cf.c[c][1 + k];
+    f.resid_rms[c] = std::sqrt(ss[c] / (double)n);
+    f.resid_max[c] = mx[c];
+    f.scale[c] = std::max(f.resid_rms[c], floor);
+  }
+  for (int c = 0; c < 4; ++c) {
+    m->frame_ref[c] = (float)f.ref[c];
+    m->frame_scale[c] = (float)f.scale[c];
+    for (int k = 0; k < st::kMlpMaxIn; ++k) m->frame_lin[c][k] = (float)f.lin[c][k];
+  }
+  if (out) *out = f;
+  return done(ST_OK);
 }
 
 st_status st_mlp_gradient(st_mlp* m, const float* d_x, const float* d_t, int64_t batch,

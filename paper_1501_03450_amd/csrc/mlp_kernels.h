@@ -51,8 +51,9 @@ struct MlpArgs {
   const float* target;    // [batch][4]
   float* q_out;           // [batch][4]
   float* dy;              // [batch][4]
-  float out_ref[4];       // output frame: u = out_ref + out_scale ⊙ y, q = u/|u|
+  float out_ref[4];       // output frame: u = out_ref + out_lin x + out_scale ⊙ y, q = u/|u|
   float out_scale[4];
+  float out_lin[4][kMlpMaxIn];
   float inv_loss_norm;    // 1/batch
   float* loss_part;       // [blocks]
   __bf16* hT1;            // [256][ld] activations, feature-major
@@ -98,6 +99,20 @@ struct SumSegment {
 constexpr int kMaxSumSegments = 12;
 size_t sum_partials_tmp(int64_t len, int parts);
 hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tmp, hipStream_t s);
+// Least-squares fit of targets t [n][4] on the inputs augmented with a
+// constant, [1, x] (D = n_in + 1 columns), in double precision.  Pass 1:
+// per-block partial sums of the normal equations, D*D entries of [1,x][1,x]ᵀ
+// then D*4 of [1,x] tᵀ (row-major), kFitBlocks blocks.  Pass 2: per-block
+// sums of squared residuals of each component and their largest magnitude,
+// for coefficients coef[4][D].
+constexpr int kFitBlocks = 512;
+struct FitCoef {
+  double c[4][kMlpMaxIn + 1];
+};
+hipError_t launch_fit_normal(const float* x, const float* t, int64_t n, int n_in, double* partials,
+                             hipStream_t s);
+hipError_t launch_fit_residual(const float* x, const float* t, int64_t n, int n_in,
+                               const FitCoef& coef, double* partials, hipStream_t s);
 hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s);
 hipError_t launch_refresh_bf16(const MlpArgs& a, hipStream_t s);
 

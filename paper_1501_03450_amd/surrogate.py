@@ -49,11 +49,12 @@ class Surrogate:
     n_in: int
     center: np.ndarray             # feature map: (z - center) * inv_scale
     inv_scale: np.ndarray
-    ref: np.ndarray                # output frame: q = (ref + scale ⊙ y)/|…|
+    ref: np.ndarray                # output frame: q = (ref + lin x + scale ⊙ y)/|…|
     scale: np.ndarray
     gamma_center: float = 0.0      # energy input (n_in == 7): (γ0 - centre)/half-width
     gamma_half_width: float = 1.0
     losses: list = dataclasses.field(default_factory=list)
+    lin: np.ndarray = None         # [4][n_in]; None: no linear part
 
     def extra(self, gamma0: float) -> float:
         if self.n_in < 7:
@@ -124,6 +125,18 @@ def frame_from_targets(t_host: np.ndarray, ref: np.ndarray, floor: float = 1e-5)
     """Output scale: RMS spread of the targets about ref, per component."""
     dev = t_host.astype(np.float64) - ref[None, :]
     return np.maximum(np.sqrt((dev * dev).mean(axis=0)), floor)
+
+
+def fit_frame(sur: Surrogate, x, t, floor: float = 1e-5, stream=None) -> dict:
+    """Affine output frame fitted by the library in double precision (least
+    squares of the targets on the inputs): the network then learns only the
+    residual of ref + lin x, scaled by its RMS."""
+    f = B.st_mlp_fit_frame(sur.net, x.data_ptr(), t.data_ptr(), x.shape[0], floor,
+                           stream.cuda_stream if stream is not None else None)
+    sur.ref = np.array(f["ref"])
+    sur.scale = np.array(f["scale"])
+    sur.lin = np.array([row[:sur.n_in] for row in f["lin"]])
+    return f
 
 
 def train(sur: Surrogate, x, t, epochs: int, batch: int, lr: float, lr_final: float = None,
@@ -204,10 +217,13 @@ def band_slices(n_energies: int, n_bands: int):
 
 
 def train_band(ring, beams, n_per_energy: int, seed: int, epochs: int, batch: int, lr: float,
-               widen: float = 3.0, net_seed: int = 1, device: int = 0, log=None) -> Surrogate:
+               widen: float = 3.0, net_seed: int = 1, device: int = 0, log=None,
+               linear_frame: bool = True) -> Surrogate:
     """A 7-input network for a band of reference energies: inputs are the six
     coordinates and the energy offset within the band; labels are tracked one
-    turn at each energy of the band (widened bunch)."""
+    turn at each energy of the band (widened bunch).  The output frame is the
+    fitted affine map (linear_frame) or the design quaternion with the
+    targets' RMS spread."""
     import torch
     from workloads import gaussian_bunch
     g = np.array([b.gamma0 for b in beams])
@@ -228,7 +244,10 @@ def train_band(ring, beams, n_per_energy: int, seed: int, epochs: int, batch: in
     n = min(x.shape[0] for x in xs)
     x = torch.stack([v[:n] for v in xs], dim=1).reshape(-1, 7).contiguous()
     t = torch.stack([v[:n] for v in ts], dim=1).reshape(-1, 4).contiguous()
-    set_scale(sur, frame_from_targets(t[:65536].cpu().numpy(), ref))
+    if linear_frame:
+        fit_frame(sur, x, t)
+    else:
+        set_scale(sur, frame_from_targets(t[:65536].cpu().numpy(), ref))
     train(sur, x, t, epochs, min(batch, x.shape[0]), lr, log=log)
     return sur
 

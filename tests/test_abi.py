@@ -23,6 +23,7 @@ def test_header_declares_the_boundary():
                             "st_bind_quaternions", "st_track", "st_track_noalloc", "st_polarization",
                             "st_read_particles", "st_last_error", "st_mlp_create",
                             "st_mlp_destroy", "st_mlp_last_error", "st_mlp_params", "st_mlp_set_frame",
+                            "st_mlp_set_linear_frame", "st_mlp_fit_frame",
                             "st_mlp_train_step", "st_mlp_gradient", "st_mlp_infer",
                             "st_mlp_features", "st_mlp_targets", "st_track_surrogate",
                             "st_measure_peaks"])
@@ -43,6 +44,9 @@ def test_struct_layouts_match_the_header():
     assert binding.st_element.L.offset == 24
     assert ctypes.sizeof(binding.st_beam) == 3 * 8 + 2 * 4
     assert ctypes.sizeof(binding.st_peaks) == 4 * 8
+    # st_frame_fit: ref[4], lin[4][8], scale[4], resid_rms[4], resid_max[4]
+    assert ctypes.sizeof(binding.st_frame_fit) == (4 + 32 + 4 + 4 + 4) * 8
+    assert binding.st_frame_fit.scale.offset == 36 * 8
     text = open(HEADER).read()
     assert "int32_t kind, orbit, n_slices, romberg_rows, spin_place, fringe;" in text
     assert "double L, angle, eta, k1, k1l, k2l, snake_phi, snake_mu, ks, asym;" in text

@@ -108,3 +108,53 @@ def test_identity_rounding_gives_the_plain_gradient():
     plain = M.backward(params, x, t)
     for a, b in zip(same, plain):
         np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------------------------------ affine output frame --
+
+def test_fit_frame_recovers_an_exact_affine_map():
+    # targets exactly affine in the inputs: the fit returns that map, with no
+    # residual, and the scale falls to the floor
+    rng = np.random.default_rng(21)
+    x = rng.normal(size=(500, 6))
+    c0 = np.array([0.3, -0.1, 0.9, 0.2])
+    A = rng.normal(size=(4, 6))
+    f = M.fit_frame(x, c0 + x @ A.T, floor=1e-7)
+    assert np.abs(f["ref"] - c0).max() < 1e-13
+    assert np.abs(f["lin"] - A).max() < 1e-13
+    assert f["resid_rms"].max() < 1e-13 and f["resid_max"].max() < 1e-13
+    np.testing.assert_array_equal(f["scale"], np.full(4, 1e-7))
+
+
+def test_fit_frame_residual_is_orthogonal_to_the_inputs_and_minimal():
+    # least squares: the residual of every component is orthogonal to the
+    # constant and to each input, and any perturbation of the fit raises
+    # the summed squared residual
+    rng = np.random.default_rng(22)
+    x = rng.normal(size=(2000, 7))
+    t = np.sin(x[:, :4]) + 0.1 * x[:, 4:5] ** 2
+    f = M.fit_frame(x, t, floor=1e-9)
+    r = t - f["ref"] - x @ f["lin"].T
+    A = np.concatenate([np.ones((2000, 1)), x], axis=1)
+    assert np.abs(A.T @ r).max() < 1e-9 * np.abs(A).sum(axis=0).max()
+    np.testing.assert_allclose(f["resid_rms"], np.sqrt((r * r).mean(axis=0)), rtol=1e-12)
+    base = (r * r).sum()
+    for k in range(20):
+        d = rng.normal(scale=1e-3, size=(4, 7))
+        r2 = t - f["ref"] - x @ (f["lin"] + d).T
+        assert (r2 * r2).sum() > base
+
+
+def test_forward_with_a_linear_frame_adds_it_before_normalising():
+    # with a zero last layer the prediction is the normalised affine map
+    rng = np.random.default_rng(23)
+    n_in = 6
+    p = [rng.normal(scale=0.1, size=s) for s in M.shapes(n_in)]
+    p[6][:] = 0.0
+    p[7][:] = 0.0
+    x = rng.normal(size=(10, n_in))
+    ref = np.array([0.1, 0.2, 0.9, -0.3])
+    lin = rng.normal(scale=0.05, size=(4, n_in))
+    q, _ = M.forward(p, x, ref=ref, scale=np.ones(4), lin=lin)
+    u = ref + x @ lin.T
+    np.testing.assert_allclose(q, u / np.linalg.norm(u, axis=1, keepdims=True), rtol=1e-14)
