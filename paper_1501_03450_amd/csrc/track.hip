@@ -153,7 +153,9 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   const int N = NS > 0 ? NS : el.nsl;
   const int K = NS > 0 ? KS : el.K;
   const double ds = KIND == 0 ? el.b.ds : (KIND == 4 ? el.tp.ds : el.q.ds);
-  const bool spin32 = MIXED && (el.flags & F_SPIN32);
+  // MIXED: this element's edges are built and multiplied in single
+  // precision (the caller picks this instantiation for flagged elements)
+  constexpr bool spin32 = MIXED;
   // running products of the Romberg levels: level m keeps every 2^m-th edge
   Quat Q0 = qident(), Q1 = qident(), Q2 = qident(), Q3 = qident();
   QuatC C0 = qc_ident(), C1 = qc_ident(), C2 = qc_ident(), C3 = qc_ident();
@@ -194,7 +196,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
     // rotation about Ω by 2^m times the finest angle, i.e. the finest
     // quaternion squared m times.
     const bool end_edge = j == 0 || j == N;
-    if (spin32) {
+    if constexpr (spin32) {
       const double f = (end_edge ? 0.5 : 1.0) * ds;
       float d, sf;
       rot_deviation_f32(0.25 * f * f * om2, d, sf);
@@ -258,7 +260,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
     }
     fold(j, std::false_type{});
   }
-  if (spin32) {
+  if constexpr (spin32) {
     Q0 = qc_to_double(C0);
     if (K >= 1) Q1 = qc_to_double(C1);
     if (K >= 2) Q2 = qc_to_double(C2);
@@ -633,6 +635,32 @@ __device__ __forceinline__ double wave_sum(double v) {
 // SURR: surrogate tracking; lanes with fallback[j] == 0 leave the spin to the
 // network (the caller rotates it), and waves without a fallback lane skip the
 // spin arithmetic altogether.
+// Sector bends and DKD/MK quadrupoles of the standard rings, with unrolled
+// bodies for their slice counts and Romberg depths: sector bends with 8
+// slices and 3 or 4 rows, MK quadrupoles with 4 slices and 3 rows, DKD
+// quadrupoles with 8 slices and 3 rows; other elements take the loop.
+// S32: the element's spin edges in single precision (mixed mode).
+template <int NT, bool S32>
+__device__ __forceinline__ Quat standard_thick(const DevElem& e, double& X, double& Px, double& Y,
+                                               double& Py, double& T, const Particle& p,
+                                               const TrackArgs& a, MKCache* mkc) {
+  if (e.kind == K_SBEND) {
+    if (e.nsl == 8 && e.K == 3) return thick_element<NT, 0, S32, false, true, 8, 3>(e, X, Px, Y, Py, T, p, a);
+    if (e.nsl == 8 && e.K == 2) return thick_element<NT, 0, S32, false, true, 8, 2>(e, X, Px, Y, Py, T, p, a);
+    return thick_element<NT, 0, S32>(e, X, Px, Y, Py, T, p, a);
+  }
+  if (e.orbit != M_MK) {
+    if (e.nsl == 8 && e.K == 2) return thick_element<NT, 2, S32, false, true, 8, 2>(e, X, Px, Y, Py, T, p, a);
+    return thick_element<NT, 2, S32>(e, X, Px, Y, Py, T, p, a);
+  }
+  if (e.nsl == 4 && e.K == 2) {
+    if (e.q.k1 >= 0.0) return thick_element<NT, 1, S32, false, true, 4, 2>(e, X, Px, Y, Py, T, p, a, mkc);
+    return thick_element<NT, 3, S32, false, true, 4, 2>(e, X, Px, Y, Py, T, p, a, mkc);
+  }
+  if (e.q.k1 >= 0.0) return thick_element<NT, 1, S32>(e, X, Px, Y, Py, T, p, a, mkc);
+  return thick_element<NT, 3, S32>(e, X, Px, Y, Py, T, p, a, mkc);
+}
+
 // EXT: the kernel also knows the drift-kick sector bend and the piece-wise
 // constant spin placements (kept out of the other instantiations so that
 // their register allocation is not shaped by code they never run).
@@ -738,34 +766,13 @@ track_kernel(const TrackArgs a) {
           else                    q = thick_ext<NT, 3>(e, X, Px, Y, Py, T, p, a);
         }
       } else switch (e.kind) {
-        // The slice counts and Romberg depths of the standard rings get
-        // unrolled bodies in the double-precision kernel: sector bends with 8
-        // slices and 3 or 4 rows, MK quadrupoles with 4 slices and 3 rows, DKD
-        // quadrupoles with 8 slices and 3 rows.  Other elements take the loop.
         case K_SBEND:
-          if (!MIXED && e.nsl == 8 && e.K == 3)
-            q = thick_element<NT, 0, MIXED, false, true, 8, 3>(e, X, Px, Y, Py, T, p, a);
-          else if (!MIXED && e.nsl == 8 && e.K == 2)
-            q = thick_element<NT, 0, MIXED, false, true, 8, 2>(e, X, Px, Y, Py, T, p, a);
-          else
-            q = thick_element<NT, 0, MIXED>(e, X, Px, Y, Py, T, p, a);
-          break;
         case K_QUAD:
-          if (e.orbit != M_MK) {
-            if (!MIXED && e.nsl == 8 && e.K == 2)
-              q = thick_element<NT, 2, MIXED, false, true, 8, 2>(e, X, Px, Y, Py, T, p, a);
-            else
-              q = thick_element<NT, 2, MIXED>(e, X, Px, Y, Py, T, p, a);
-          } else if (!MIXED && e.nsl == 4 && e.K == 2) {
-            if (e.q.k1 >= 0.0)
-              q = thick_element<NT, 1, MIXED, false, true, 4, 2>(e, X, Px, Y, Py, T, p, a, &mkc);
-            else
-              q = thick_element<NT, 3, MIXED, false, true, 4, 2>(e, X, Px, Y, Py, T, p, a, &mkc);
-          } else if (e.q.k1 >= 0.0) {
-            q = thick_element<NT, 1, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
-          } else {
-            q = thick_element<NT, 3, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
-          }
+          // the mixed kernel carries both instantiations; an element runs one
+          if (MIXED && (e.flags & F_SPIN32))
+            q = standard_thick<NT, MIXED>(e, X, Px, Y, Py, T, p, a, &mkc);
+          else
+            q = standard_thick<NT, false>(e, X, Px, Y, Py, T, p, a, &mkc);
           break;
         case K_THIN:
           q = thin_element<NT>(e, X, Px, Y, Py, p, a);
