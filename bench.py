@@ -102,6 +102,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--turns-per-step", type=int, default=100)
     ap.add_argument("--particles", type=int, default=1 << 20)
+    ap.add_argument("--precision", choices=("fp64", "mixed", "mixed_all"), default="fp64",
+                    help="precision of the timed launches (the headline is fp64; the others "
+                         "are for profiling the mixed-precision kernel on the same workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the FP64 FMA / bf16 MFMA / HBM copy microbenchmarks")
@@ -126,11 +129,17 @@ def parse():
                          "(default: --threshold, 1e-4 and 1e-2)")
     ap.add_argument("--band-train-per-energy", type=int, default=262144)
     ap.add_argument("--band-epochs", type=int, default=300)
-    ap.add_argument("--c3", action="store_true",
-                    help="full surrogate training run: 2^24 widened samples labelled by one "
-                         "double-precision turn, batch 65536")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the surrogate training leg (2^24 widened samples labelled by "
+                         "one double-precision turn, batch 65536)")
     ap.add_argument("--c3-samples", type=int, default=1 << 24)
     ap.add_argument("--c3-epochs", type=int, default=200)
+    ap.add_argument("--constant-frame", action="store_true",
+                    help="train the networks (C3 and the energy bands) about the design "
+                         "quaternion alone instead of the fitted affine frame")
+    ap.add_argument("--no-c0", action="store_true",
+                    help="skip the small-ring leg (1024 protons x 256 turns on the GPU and on "
+                         "the CPU oracle in full)")
     ap.add_argument("--c4", action="store_true",
                     help="full energy scan: 256 energies x 65536 particles, 16 bands")
     ap.add_argument("--c4-energies", type=int, default=256)
@@ -192,6 +201,44 @@ def cpu_baseline(ring, beam, z, s, a, n_sample, turns, n_1core, turns_1core):
             "host": host}
 
 
+def c0_leg(beam, stream, threads):
+    """The small ring in full: 1024 protons x 256 turns on the GPU (one launch,
+    HIP events) and on the double-precision oracle (all threads), with the
+    largest GPU-oracle differences at the end."""
+    import torch
+    import oracle
+    from paper_1501_03450_amd import SpinTracker
+    from workloads import gaussian_bunch, small_ring
+    from workloads.bunch import SEED_BASE
+    ring = small_ring()
+    n, turns = 1024, 256
+    z, s, a = gaussian_bunch(n, SEED_BASE, beam)
+    tr = SpinTracker(ring, beam, device=0, report_every=turns)
+    with torch.cuda.stream(stream):
+        tr.set_particles(z, s, a)
+    tr.track(4, stream=stream)                      # warm-up
+    with torch.cuda.stream(stream):
+        tr.set_particles(z, s, a)
+    ms = timed_tracking(tr, turns, 1, stream)[0]
+    zg, sg, ag = tr.read(stream=stream)
+    tr.close()
+    t0 = time.perf_counter()
+    o = oracle.track(ring, beam, z, s, a, turns=turns, extended=False, threads=threads)
+    dt = time.perf_counter() - t0
+    live = (ag == 1) & (o["alive"] == 1)
+    sig = o["z"][:, live].std(axis=1)
+    rel = np.abs(zg[:, live] - o["z"][:, live]) / np.maximum(np.abs(o["z"][:, live]), sig[:, None])
+    return {"workload": f"small_ring (129 elements: DKD quadrupoles 8 slices, exact bends 8 "
+                        f"slices, 3 Romberg rows, one snake), {n} protons x {turns} turns, fp64",
+            "unit": "particle-turns/s",
+            "gpu_value": n * turns / (ms / 1e3), "gpu_ms": ms,
+            "oracle_value": n * turns / dt, "oracle_seconds": dt, "oracle_threads": threads,
+            "survival": float((ag == 1).mean()),
+            "alive_identical": bool((ag == o["alive"]).all()),
+            "orbit_rel_diff_vs_double_oracle_max": float(rel.max()),
+            "spin_diff_vs_double_oracle_max": float(np.abs(sg[:, live] - o["spin"][:, live]).max())}
+
+
 def timed_tracking(tracker, turns, steps, stream):
     import torch
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
@@ -244,6 +291,21 @@ def mixed_leg(ring, beam, n, turns, stream):
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBPS = 8000.0
+
+
+def train_bytes_per_sample(n_in):
+    """HBM bytes one training sample needs between the three step kernels:
+    forward reads x and the target and writes the bf16 activations h1, h2 and
+    the output gradient; backward reads x, h1, h2 and the output gradient and
+    writes the bf16 gradients at the pre-activations of layers 2 and 3; the
+    weight-gradient kernel reads those four bf16 rows (the split partials of
+    the weight gradients are per batch, not per sample, and not counted)."""
+    x, t, h, dy = 4 * n_in, 16, 2 * 256, 16
+    forward = x + t + 2 * h + dy
+    backward = x + 2 * h + dy + 2 * h
+    weight_grad = 4 * h
+    return forward + backward + weight_grad
 
 
 def quantiles(e):
@@ -252,7 +314,26 @@ def quantiles(e):
             "frac_le_1e-6": float(np.mean(e <= 1e-6)), "frac_le_1e-4": float(np.mean(e <= 1e-4))}
 
 
-def c3_leg(ring, beam, n_samples, epochs, batch, lr):
+def error_histogram(e):
+    """Counts of the per-sample errors per decade, from below 1e-8 to above 1e-1."""
+    edges = [0.0] + [10.0 ** k for k in range(-8, 0)] + [np.inf]
+    counts, _ = np.histogram(e, bins=edges)
+    labels = ["<1e-8"] + [f"1e{k}..1e{k + 1}" for k in range(-8, -1)] + [">=1e-1"]
+    return dict(zip(labels, [int(c) for c in counts]))
+
+
+def frame_errors(sur, x, t):
+    """Largest component error per sample of the output frame alone (the
+    affine map normalised, no network), in double precision on the host."""
+    xh = x.cpu().numpy().astype(np.float64)
+    th = t.cpu().numpy().astype(np.float64)
+    lin = sur.lin if sur.lin is not None else np.zeros((4, sur.n_in))
+    u = sur.ref[None, :] + xh @ lin.T
+    q = u / np.linalg.norm(u, axis=1, keepdims=True)
+    return np.abs(q - th).max(axis=1)
+
+
+def c3_leg(ring, beam, n_samples, epochs, batch, lr, linear_frame=True):
     """Surrogate training: labels from one double-precision turn of a
     widened bunch, Adam on the library's kernels, held-out errors."""
     import torch
@@ -269,7 +350,11 @@ def c3_leg(ring, beam, n_samples, epochs, batch, lr):
     x, t = S.label_bunch(sur, ring, beam, z)
     t_label = time.perf_counter() - t0
     del z
-    S.set_scale(sur, S.frame_from_targets(t[:65536].cpu().numpy(), ref))
+    if linear_frame:
+        frame = S.fit_frame(sur, x, t)
+    else:
+        S.set_scale(sur, S.frame_from_targets(t[:65536].cpu().numpy(), ref))
+        frame = None
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     S.train(sur, x, t, epochs, batch, lr, log=lambda m: log(f"[bench] c3 {m}"))
@@ -290,6 +375,7 @@ def c3_leg(ring, beam, n_samples, epochs, batch, lr):
     del q
     zv, _, _ = gaussian_bunch(65536, SEED_BASE + 33, beam)
     xv, tv = S.label_bunch(sur, ring, beam, zv)
+    ev = S.component_errors(sur, xv, tv)
     out = {
         "workload": f"{n_samples} samples (bunch sigma x{widen:g}), one double-precision turn of "
                     f"rhic_like_ring each; MLP 6-256-256-256-4 SiLU, bf16 MFMA, batch {batch}, "
@@ -298,20 +384,29 @@ def c3_leg(ring, beam, n_samples, epochs, batch, lr):
         "train_samples_per_s": sps,
         "train_tflops": tflops,
         "train_mfma_frac_of_bf16_peak": tflops / MFMA_BF16_PEAK_TFLOPS,
+        "train_step_us": t_train / steps * 1e6,
+        "train_hbm_bytes_per_sample": train_bytes_per_sample(6),
+        "train_hbm_frac_of_8tbs": sps * train_bytes_per_sample(6) / (HBM_PEAK_GBPS * 1e9),
         "train_seconds": t_train,
         "infer_samples_per_s": x.shape[0] / t_infer,
         "infer_tflops": x.shape[0] / t_infer * S.flops_per_sample(6, False) / 1e12,
         "final_loss": sur.losses[-1],
         "output_frame_scale": [float(v) for v in sur.scale],
         "err_train_sample": quantiles(S.component_errors(sur, x[:65536], t[:65536])),
-        "err_heldout_base_bunch": quantiles(S.component_errors(sur, xv, tv)),
+        "err_heldout_base_bunch": quantiles(ev),
+        "err_heldout_histogram": error_histogram(ev),
+        "output_frame": "affine least-squares fit" if linear_frame else "design quaternion",
+        "frame_only_err_heldout": quantiles(frame_errors(sur, xv, tv)),
     }
+    if frame is not None:
+        out["frame_fit_resid_rms"] = frame["resid_rms"]
+        out["frame_fit_resid_max"] = frame["resid_max"]
     sur.close()
     return out
 
 
 def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_energy, epochs,
-             lr, n_bands, thresholds=None, n_streams=4, surrogate_streams=16):
+             lr, n_bands, thresholds=None, n_streams=4, surrogate_streams=16, linear_frame=True):
     """Energy scan with surrogate + fallback against plain double precision on
     the same bunches, plus the fallback fraction at looser thresholds."""
     from paper_1501_03450_amd import surrogate as S
@@ -325,7 +420,8 @@ def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_e
     nets, per = [], []
     for b, rng_ in enumerate(S.band_slices(n_energies, n_bands)):
         sur = S.train_band(ring, [beams[i] for i in rng_], train_per_energy,
-                           SEED_BASE + 3 + 1000 * (b + 1), epochs, 65536, lr, net_seed=b + 1)
+                           SEED_BASE + 3 + 1000 * (b + 1), epochs, 65536, lr, net_seed=b + 1,
+                           linear_frame=linear_frame)
         log(f"[bench] band {b + 1}/{n_bands}: final loss {sur.losses[-1]:.3e}")
         nets.append(sur)
         per += [sur] * len(rng_)
@@ -462,7 +558,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     stream = torch.cuda.Stream(device=dev)
-    tr = SpinTracker(ring, beam, device=0, precision="fp64", report_every=T)
+    tr = SpinTracker(ring, beam, device=0, precision=args.precision, report_every=T)
     with torch.cuda.stream(stream):
         tr.set_particles(z, s, a)
     torch.cuda.synchronize()
@@ -520,15 +616,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64 orbit, f32 spin",
         "data": "synthetic",
         "config": {
-            "workload": "rhic_like_ring_fp64",
+            "workload": f"rhic_like_ring_{args.precision}",
             "elements": summ["n_elements"],
             "circumference_m": round(summ["circumference_m"], 3),
             "particles": n,
             "turns_per_step": T,
-            "precision": "fp64",
+            "precision": args.precision,
             "quad": "MK, 4 slices", "bend": "exact, 8 slices", "romberg_rows": 4,
             "survival": survival,
             "final_polarization": [float(v) for v in pol[-1, :3]] if len(pol) else None,
@@ -573,14 +669,19 @@ def main():
         out["surrogate"] = scan_leg(ring, args.band_energies, args.scan_particles, args.scan_turns,
                                     args.audit_every, args.threshold, args.band_train_per_energy,
                                     args.band_epochs, args.lr, 1, thresholds, args.scan_streams,
-                                    args.surrogate_streams)
-    if args.c3:
-        out["c3_training"] = c3_leg(ring, beam, args.c3_samples, args.c3_epochs, 65536, args.lr)
+                                    args.surrogate_streams, not args.constant_frame)
+    if not args.no_c0:
+        out["c0_small_ring"] = c0_leg(beam, stream, max(1, min(CPU_SHARE_PER_GPU,
+                                                               host_cpu()["usable_cpus"])))
+    if not args.no_c3:
+        out["c3_training"] = c3_leg(ring, beam, args.c3_samples, args.c3_epochs, 65536, args.lr,
+                                    not args.constant_frame)
     if args.c4:
         out["c4_scan"] = scan_leg(ring, args.c4_energies, args.scan_particles, args.scan_turns,
                                   args.audit_every, args.threshold, args.band_train_per_energy,
                                   args.band_epochs, args.lr, max(1, args.c4_energies // 16),
-                                  thresholds, args.scan_streams, args.surrogate_streams)
+                                  thresholds, args.scan_streams, args.surrogate_streams,
+                                  not args.constant_frame)
     if args.compare_integrators:
         out["integrators"] = integrator_leg(beam)
     if not args.no_cpu_baseline:

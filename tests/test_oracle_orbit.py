@@ -137,9 +137,11 @@ def test_mk_nonlinear_part_is_fourth_order():
     e = quad(1.1, 0.08, "mk", 1, 1)
     J = _element_jacobian(e, np.zeros(6))
     u = np.array([1.0, 0.3, -0.7, 0.5, 0.0, 0.0])
+    wide = Beam(aperture=0.25)          # the largest amplitude leaves X > 0.05 m
     res = []
     for a in [4e-2, 2e-2, 1e-2]:
-        z1, _, _, _ = run([e], a * u)
+        z1, _, _, alive = run([e], a * u, beam=wide)
+        assert alive == 1
         res.append(np.abs(z1[:4] - J[:4, :4] @ (a * u[:4])).max())
     ratios = np.array(res[:-1]) / np.array(res[1:])
     assert np.all(np.abs(ratios - 8.0) < 0.2), ratios

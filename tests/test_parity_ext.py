@@ -11,10 +11,14 @@ import numpy as np
 import pytest
 
 import oracle
-from test_parity_fp64 import (BEAM, SPIN_TOL, assert_multiturn_parity, assert_parity, both,
+from test_parity_fp64 import (SPIN_TOL, assert_multiturn_parity, assert_parity, both,
                               orbit_rel_err)
 from workloads import Beam, gaussian_bunch, rhic_like_ring
 from workloads.lattice import drift, quad, rbend, sbend, snake, solenoid
+
+# A wide aperture: these rings are built on the small ring, whose δ tails
+# reach 0.1 m, and their bounds are set for whole bunches.
+BEAM = Beam(aperture=0.25)
 
 pytestmark = pytest.mark.gpu
 
@@ -170,7 +174,7 @@ def test_small_ring_with_turned_rectangular_bends():
 
 def test_low_energy_solenoid():
     # 1.2 GeV protons through the 2.1 m, 1.3 T solenoid: a large spin rotation
-    beam = Beam(gamma0=1.2 / 0.938272)
+    beam = Beam(gamma0=1.2 / 0.938272, aperture=0.25)
     brho = beam.beta0 * beam.gamma0 * 0.938272 / 0.299792458
     elems = [solenoid(2.1, 1.3 / brho, 8, 3)]
     z, s, a = gaussian_bunch(500, 1501034515, beam)

@@ -26,9 +26,11 @@ SEED_BASE = 1501034500
 class Beam:
     G: float = PROTON_G
     gamma0: float = 25.0
-    # Loss aperture on |X| and |Y| (m).  The small ring's dispersion reaches
-    # ~18 m, so the δ tails of the unmatched bunch swing out to ~0.1 m.
-    aperture: float = 0.25
+    # Loss aperture on |X| and |Y| (m).  On the RHIC-scale ring the bunch
+    # stays inside it for 1000 turns; on the small ring, whose dispersion
+    # reaches ~18 m, the δ tails of the unmatched bunch swing out to ~0.1 m
+    # and a sixth of the 1024-particle bunch is lost within 256 turns.
+    aperture: float = 0.05
 
     @property
     def beta0(self) -> float:
