@@ -32,13 +32,15 @@ import numpy as np
 
 # The surrogate scans run many small bunches at once, each on its own stream;
 # HIP maps streams onto at most GPU_MAX_HW_QUEUES hardware queues (4 by
-# default), so raise that to 16 before the runtime starts.
+# default), round robin in creation order, so raise that to 32 before the
+# runtime starts: the scans' streams (4 double-precision, then 16 per
+# surrogate scan) then land on queues of their own instead of sharing.
 try:
     _queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
 except ValueError:
     _queues = 4
-if _queues < 16:
-    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+if _queues < 32:
+    os.environ["GPU_MAX_HW_QUEUES"] = "32"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -134,9 +136,11 @@ def parse():
                          "one double-precision turn, batch 65536)")
     ap.add_argument("--c3-samples", type=int, default=1 << 24)
     ap.add_argument("--c3-epochs", type=int, default=200)
-    ap.add_argument("--constant-frame", action="store_true",
-                    help="train the networks (C3 and the energy bands) about the design "
-                         "quaternion alone instead of the fitted affine frame")
+    ap.add_argument("--c3-frame", choices=("affine", "design"), default="affine",
+                    help="output frame of the C3 network: the fitted affine map of the inputs, "
+                         "or the design quaternion with the targets' spread")
+    ap.add_argument("--band-frame", choices=("affine", "design"), default="design",
+                    help="output frame of the energy-band networks (as --c3-frame)")
     ap.add_argument("--no-c0", action="store_true",
                     help="skip the small-ring leg (1024 protons x 256 turns on the GPU and on "
                          "the CPU oracle in full)")
@@ -296,15 +300,16 @@ HBM_PEAK_GBPS = 8000.0
 
 def train_bytes_per_sample(n_in):
     """HBM bytes one training sample needs between the three step kernels:
-    forward reads x and the target and writes the bf16 activations h1, h2 and
-    the output gradient; backward reads x, h1, h2 and the output gradient and
-    writes the bf16 gradients at the pre-activations of layers 2 and 3; the
-    weight-gradient kernel reads those four bf16 rows (the split partials of
-    the weight gradients are per batch, not per sample, and not counted)."""
-    x, t, h, dy = 4 * n_in, 16, 2 * 256, 16
-    forward = x + t + 2 * h + dy
-    backward = x + 2 * h + dy + 2 * h
-    weight_grad = 4 * h
+    forward reads x and the target and writes the bf16 activations h1, h2,
+    the bf16 SiLU derivatives of layers 2 and 3 and dL/dy; backward reads x,
+    dL/dy and the two derivatives and writes the bf16 gradients at the
+    pre-activations of layers 2 and 3; the weight-gradient kernel reads h1,
+    h2 and those two gradients (the split partials of the weight gradients
+    are per batch, not per sample, and not counted)."""
+    x, t, row, dy = 4 * n_in, 16, 2 * 256, 16
+    forward = x + t + 4 * row + dy
+    backward = x + dy + 2 * row + 2 * row
+    weight_grad = 4 * row
     return forward + backward + weight_grad
 
 
@@ -443,7 +448,8 @@ def scan_leg(ring, n_energies, n_per, turns, audit_every, threshold, train_per_e
     return {
         "workload": f"{n_energies} energies (G*gamma0 from {gam[0] * beams[0].G:.4f} to "
                     f"{gam[-1] * beams[0].G:.4f}) x {n_per} particles x {turns} turns on "
-                    f"rhic_like_ring; {n_bands} band networks (7 inputs), audit after the first "
+                    f"rhic_like_ring; {n_bands} band networks (7 inputs, "
+                    f"{'affine' if linear_frame else 'design-quaternion'} output frame), audit after the first "
                     f"turn and every {audit_every}; bunches over {n_streams} streams (FP64) and "
                     f"{surrogate_streams} streams (surrogate)",
         "unit": "particle-turns/s",
@@ -669,19 +675,19 @@ def main():
         out["surrogate"] = scan_leg(ring, args.band_energies, args.scan_particles, args.scan_turns,
                                     args.audit_every, args.threshold, args.band_train_per_energy,
                                     args.band_epochs, args.lr, 1, thresholds, args.scan_streams,
-                                    args.surrogate_streams, not args.constant_frame)
+                                    args.surrogate_streams, args.band_frame == "affine")
     if not args.no_c0:
         out["c0_small_ring"] = c0_leg(beam, stream, max(1, min(CPU_SHARE_PER_GPU,
                                                                host_cpu()["usable_cpus"])))
     if not args.no_c3:
         out["c3_training"] = c3_leg(ring, beam, args.c3_samples, args.c3_epochs, 65536, args.lr,
-                                    not args.constant_frame)
+                                    args.c3_frame == "affine")
     if args.c4:
         out["c4_scan"] = scan_leg(ring, args.c4_energies, args.scan_particles, args.scan_turns,
                                   args.audit_every, args.threshold, args.band_train_per_energy,
                                   args.band_epochs, args.lr, max(1, args.c4_energies // 16),
                                   thresholds, args.scan_streams, args.surrogate_streams,
-                                  not args.constant_frame)
+                                  args.band_frame == "affine")
     if args.compare_integrators:
         out["integrators"] = integrator_leg(beam)
     if not args.no_cpu_baseline:

@@ -387,13 +387,21 @@ st_status st_mlp_targets(st_mlp* m, const double* d_q, int64_t n, const double* 
  * left by an earlier call or set by the caller is never rolled back again:
  * such a particle runs every turn in double precision.  It stays on the
  * double-precision path afterwards.  The orbit is the double-precision orbit
- * throughout.  d_fallback: device int32 [n], initialised by the caller (0 =
- * start on the network).  Polarization is recorded as in st_track; the
- * beam's report_every must then be a multiple of audit_every, so that every
- * report follows an audit.  Requires a lattice, particles and a network
- * created on the same device.  At most 2^31-1 particles; library scratch:
- * about 170 bytes per particle.  Within a turn the particles on the network
- * and those on the fallback path are processed in separate waves. */
+ * throughout, and the spin does not act on it, so the turns between two
+ * audits run as one launch of the orbit push that records every turn's
+ * network inputs, one inference over all of them, and one pass that rotates
+ * each particle by its turns' quaternions in turn order (the result is that
+ * of applying them turn by turn).  d_fallback: device int32 [n], initialised
+ * by the caller (0 = start on the network).  Polarization is recorded as in
+ * st_track; the beam's report_every must then be a multiple of audit_every,
+ * so that every report follows an audit.  Requires a lattice, particles and
+ * a network created on the same device.  At most 2^31-1 particles; library
+ * scratch: about 130 bytes per particle plus 48 bytes per particle and turn
+ * of one launch, at most 512 MiB for the latter (longer stretches between
+ * audits are split into several launches).  turns = 0 only reserves that
+ * scratch for the bound particles and this audit_every, so that later calls
+ * allocate nothing but the polarization history.  The particles on the
+ * network and those on the fallback path are processed in separate waves. */
 st_status st_track_surrogate(st_ctx* ctx, st_mlp* m, int64_t turns, int32_t audit_every,
                              double threshold, const double* center, const double* inv_scale,
                              double extra, int32_t* d_fallback, void* stream);

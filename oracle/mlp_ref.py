@@ -83,16 +83,19 @@ def loss(params, x, t, ref=None, scale=None, round_act=None, lin=None):
     return float(np.mean(np.sum((q - t) ** 2, axis=1)))
 
 
-def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None, lin=None):
+def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None, lin=None,
+             round_ds=None):
     """Gradients of L with respect to every parameter (same order).
 
-    With round_act and round_dz (both None: plain float64) the gradient
-    follows the GPU kernels' rounding points: the hidden activations rounded
-    as in forward(); the back-propagated dz of each hidden layer rounded
-    before it enters the next product (dz3 after its bias gradient is
-    summed, dz2 and dz1 before theirs), as the kernels hold them in bf16."""
+    With round_act, round_dz and round_ds (all None: plain float64) the
+    gradient follows the GPU kernels' rounding points: the hidden activations
+    rounded as in forward(); the back-propagated dz of each hidden layer
+    rounded before it enters the next product (dz3 after its bias gradient is
+    summed, dz2 and dz1 before theirs); the SiLU derivatives of layers 2 and 3
+    rounded as the forward pass hands them to the backward pass (bf16)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = params
     rd = round_dz if round_dz is not None else (lambda v: v)
+    rs = round_ds if round_ds is not None else (lambda v: v)
     q, (x, z1, h1, z2, h2, z3, h3, u) = forward(params, x, round_act=round_act, ref=ref,
                                                 scale=scale, lin=lin)
     B = x.shape[0]
@@ -102,11 +105,11 @@ def backward(params, x, t, ref=None, scale=None, round_act=None, round_dz=None, 
     dy = du * (np.ones(N_OUT) if scale is None else np.asarray(scale, dtype=np.float64))
     gW4 = dy.T @ h3
     gb4 = dy.sum(0)
-    dz3 = (dy @ W4) * dsilu(z3)
+    dz3 = (dy @ W4) * rs(dsilu(z3))
     gb3 = dz3.sum(0)
     dz3 = rd(dz3)
     gW3 = dz3.T @ h2
-    dz2 = rd((dz3 @ W3) * dsilu(z2))
+    dz2 = rd((dz3 @ W3) * rs(dsilu(z2)))
     gW2 = dz2.T @ h1
     gb2 = dz2.sum(0)
     dz1 = rd((dz2 @ W2) * dsilu(z1))

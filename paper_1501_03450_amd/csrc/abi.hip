@@ -48,8 +48,10 @@ struct st_ctx {
   size_t pol_cap = 0;          // doubles
   int64_t n_reports = 0;
   // surrogate tracking scratch
-  float* d_feat = nullptr;     // [n][8]
-  float* d_qnn = nullptr;      // [n][4]
+  float* d_feat = nullptr;     // [turns of a batch][n][8] network inputs
+  float* d_qnn = nullptr;      // [turns of a batch][n][4] network quaternions
+  int32_t* d_done = nullptr;   // turns completed in a multi-turn launch
+  int64_t feat_cap = 0;        // samples (turn, particle) d_feat and d_qnn hold
   double* d_q64 = nullptr;     // 4 × n
   double* d_ck = nullptr;      // checkpoint of the last audit: z (6 × n) then spin (3 × n)
   int32_t* d_ck_alive = nullptr;
@@ -68,6 +70,10 @@ struct st_ctx {
 // the device symbol); it uses the device address that hipGetSymbolAddress
 // returns, taken once per device by st_create.
 constexpr size_t kScratchDoubles = ST_NOALLOC_SCRATCH_BYTES / sizeof(double);
+
+// Device memory for the network inputs and quaternions of the turns that one
+// surrogate launch covers (48 bytes per particle and turn).
+constexpr size_t kSurrogateBatchBytes = (size_t)512 << 20;
 static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
@@ -469,7 +475,7 @@ st_status st_destroy(st_ctx* c) {
     if (c->d_pol) (void)hipFree(c->d_pol);
     for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
                     (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_failed, (void*)c->d_perm,
-                    (void*)c->d_rperm, (void*)c->d_pcount, (void*)c->d_poff})
+                    (void*)c->d_rperm, (void*)c->d_pcount, (void*)c->d_poff, (void*)c->d_done})
       if (p) (void)hipFree(p);
   }
   delete c;
@@ -685,24 +691,21 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
   if (c->beam.report_every > 0 && c->beam.report_every % audit_every != 0)
     return fail(c, ST_EINVAL, "report_every must be a multiple of audit_every");
   c->n_reports = 0;
-  if (turns == 0 || c->n == 0) return ST_OK;
+  if (c->n == 0) return ST_OK;
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   const int64_t n = c->n;
   if (n > c->surr_cap) {
-    for (void* p : {(void*)c->d_feat, (void*)c->d_qnn, (void*)c->d_q64, (void*)c->d_ck,
-                    (void*)c->d_ck_alive, (void*)c->d_ralive, (void*)c->d_failed, (void*)c->d_perm,
-                    (void*)c->d_rperm, (void*)c->d_pcount, (void*)c->d_poff})
+    for (void* p : {(void*)c->d_q64, (void*)c->d_ck, (void*)c->d_ck_alive, (void*)c->d_ralive,
+                    (void*)c->d_failed, (void*)c->d_perm, (void*)c->d_rperm, (void*)c->d_pcount,
+                    (void*)c->d_poff, (void*)c->d_done})
       if (p) (void)hipFree(p);
-    c->d_feat = nullptr; c->d_qnn = nullptr; c->d_q64 = nullptr; c->d_ck = nullptr;
-    c->d_ck_alive = nullptr; c->d_ralive = nullptr; c->d_failed = nullptr; c->d_perm = nullptr;
-    c->d_rperm = nullptr;
-    c->d_pcount = nullptr; c->d_poff = nullptr; c->surr_cap = 0;
+    c->d_q64 = nullptr; c->d_ck = nullptr; c->d_ck_alive = nullptr; c->d_ralive = nullptr;
+    c->d_failed = nullptr; c->d_perm = nullptr; c->d_rperm = nullptr; c->d_pcount = nullptr;
+    c->d_poff = nullptr; c->d_done = nullptr; c->surr_cap = 0;
     const size_t nparts = (size_t)((n + 255) / 256) * 3;
-    if ((e = hipMalloc(&c->d_feat, (size_t)n * 8 * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&c->d_qnn, (size_t)n * 4 * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&c->d_q64, (size_t)n * 4 * sizeof(double))) != hipSuccess ||
+    if ((e = hipMalloc(&c->d_q64, (size_t)n * 4 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->d_ck, (size_t)n * 9 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->d_ck_alive, (size_t)n * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_ralive, (size_t)n * sizeof(int32_t))) != hipSuccess ||
@@ -710,10 +713,26 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
         (e = hipMalloc(&c->d_perm, (size_t)n * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_rperm, (size_t)n * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_pcount, nparts * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&c->d_poff, nparts * sizeof(int32_t))) != hipSuccess)
+        (e = hipMalloc(&c->d_poff, nparts * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_done, (size_t)n * sizeof(int32_t))) != hipSuccess)
       return fail(c, ST_ENOMEM, std::string("surrogate scratch: ") + hipGetErrorString(e));
     c->surr_cap = n;
   }
+  // Turns between audits run as one launch of the orbit push; the network
+  // inputs and quaternions of all of them are held at once, up to
+  // kSurrogateBatchBytes (48 bytes per particle and turn).
+  const int64_t k_max = std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)audit_every, (int64_t)(kSurrogateBatchBytes / (48 * (size_t)n))));
+  if (k_max * n > c->feat_cap) {
+    if (c->d_feat) (void)hipFree(c->d_feat);
+    if (c->d_qnn) (void)hipFree(c->d_qnn);
+    c->d_feat = nullptr; c->d_qnn = nullptr; c->feat_cap = 0;
+    if ((e = hipMalloc(&c->d_feat, (size_t)(k_max * n) * 8 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&c->d_qnn, (size_t)(k_max * n) * 4 * sizeof(float))) != hipSuccess)
+      return fail(c, ST_ENOMEM, std::string("surrogate batch buffers: ") + hipGetErrorString(e));
+    c->feat_cap = k_max * n;
+  }
+  if (turns == 0) return ST_OK;      // the scratch is reserved for later calls
   const int bs = st::track_block_size();
   const int64_t nb = (n + bs - 1) / bs;
   const int rep_every = c->beam.report_every;
@@ -741,58 +760,91 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
                                 c->d_perm, s);
   };
   if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");
+  // particles on the network: the lanes the lane order puts first (the
+  // exclusive offset of the fallback key in the first block)
+  int32_t n_net = 0;
+  auto count_net = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(&n_net, c->d_poff + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (r == hipSuccess) r = hipStreamSynchronize(s);
+    return r;
+  };
+  // audits: after the first turn, so that particles the network cannot
+  // follow are found before a long replay, then every audit_every-th turn,
+  // and after the last turn of the call, so that no network turn goes
+  // unchecked
+  auto is_audit = [&](int64_t t) { return t % audit_every == 0 || t == 1 || t == turns; };
   int64_t last_audit = 0;
-  for (int64_t t = 1; t <= turns; ++t) {
+  for (int64_t t = 1; t <= turns;) {
+    if (!is_audit(t)) {
+      // the network turns up to the next audit (at most k_max of them): one
+      // launch pushes the orbits and writes every turn's network inputs, one
+      // inference covers them all, and each particle is then rotated by its
+      // turns' quaternions in order (the spin does not act on the orbit)
+      int64_t k = 1;
+      while (k < k_max && !is_audit(t + k)) ++k;
+      if ((e = count_net()) != hipSuccess) return hip_fail(c, e, "network count");
+      st::TrackArgs a = track_args(c);
+      a.turns = (int)k;
+      a.report_every = 0;
+      a.partials = nullptr;
+      a.fallback = d_fallback;
+      a.perm = c->d_perm;
+      a.feat = n_net > 0 ? c->d_feat : nullptr;
+      a.turns_done = n_net > 0 ? c->d_done : nullptr;
+      a.feat_n = n_net;
+      a.feat_n_in = st_mlp_inputs_of(m);
+      for (int i = 0; i < 6; ++i) { a.feat_center[i] = center[i]; a.feat_inv_scale[i] = inv_scale[i]; }
+      a.feat_extra = extra;
+      if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess)
+        return hip_fail(c, e, "surrogate turns");
+      if (n_net > 0) {
+        const st_status ms = st_mlp_infer(m, c->d_feat, c->d_qnn, k * n_net, stream);
+        if (ms != ST_OK) return fail(c, ms, std::string("network: ") + st_mlp_last_error(m));
+        if ((e = st::launch_surrogate_spin_turns(c->spin, c->d_perm, c->d_done, c->d_qnn, n_net, n,
+                                                 s)) != hipSuccess)
+          return hip_fail(c, e, "surrogate spin");
+      }
+      t += k;
+      continue;
+    }
     st_status ms = st_mlp_features(m, c->z, n, center, inv_scale, extra, c->d_feat, stream);
     if (ms == ST_OK) ms = st_mlp_infer(m, c->d_feat, c->d_qnn, n, stream);
     if (ms != ST_OK) return fail(c, ms, std::string("network: ") + st_mlp_last_error(m));
-    // audits: after the first turn, so that particles the network cannot
-    // follow are found before a long replay, then every audit_every-th turn,
-    // and after the last turn of the call, so that no network turn goes
-    // unchecked
-    const bool audit = t % audit_every == 0 || t == 1 || t == turns;
     st::TrackArgs a = track_args(c);
     a.turns = 1;
-    if (audit) {
-      a.qout = c->d_q64;
-      if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "audit turn");
-      if ((e = st::launch_audit(c->alive, d_fallback, c->d_failed, c->d_qnn, c->d_q64, n, threshold,
-                                (int32_t)t, s)) != hipSuccess)
-        return hip_fail(c, e, "audit");
-      // Roll the particles that failed back to the last checkpoint and replay
-      // the turns since then in double precision; the orbit is the same as on
-      // the surrogate path, so only their spins change.
-      if ((e = st::launch_replay_prepare(c->d_failed, c->z, c->spin, c->d_ck, c->d_ck + 6 * n,
-                                         c->d_ck_alive, c->d_ralive, n, s)) != hipSuccess)
-        return hip_fail(c, e, "rollback");
-      if ((e = st::launch_partition(1, c->d_failed, c->alive, d_fallback, n, c->d_pcount,
-                                    c->d_poff, c->d_rperm, s)) != hipSuccess)
-        return hip_fail(c, e, "replay order");
-      st::TrackArgs r = track_args(c);
-      r.alive = c->d_ralive;
-      r.perm = c->d_rperm;
-      r.turns = (int)(t - last_audit);
-      r.report_every = 0;
-      r.partials = nullptr;
-      if ((e = st::launch_track(r, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "replay");
-      if ((e = st::launch_replay_finish(c->d_failed, c->d_ralive, c->alive, n, s)) != hipSuccess)
-        return hip_fail(c, e, "replay status");
-      if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");
-      if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");
-      last_audit = t;
-    } else {
-      a.fallback = d_fallback;
-      a.perm = c->d_perm;
-      if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "surrogate turn");
-      if ((e = st::launch_surrogate_spin(c->spin, c->alive, d_fallback, c->d_qnn, n, s)) != hipSuccess)
-        return hip_fail(c, e, "surrogate spin");
-    }
+    a.qout = c->d_q64;
+    if ((e = st::launch_track(a, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "audit turn");
+    if ((e = st::launch_audit(c->alive, d_fallback, c->d_failed, c->d_qnn, c->d_q64, n, threshold,
+                              (int32_t)t, s)) != hipSuccess)
+      return hip_fail(c, e, "audit");
+    // Roll the particles that failed back to the last checkpoint and replay
+    // the turns since then in double precision; the orbit is the same as on
+    // the surrogate path, so only their spins change.
+    if ((e = st::launch_replay_prepare(c->d_failed, c->z, c->spin, c->d_ck, c->d_ck + 6 * n,
+                                       c->d_ck_alive, c->d_ralive, n, s)) != hipSuccess)
+      return hip_fail(c, e, "rollback");
+    if ((e = st::launch_partition(1, c->d_failed, c->alive, d_fallback, n, c->d_pcount,
+                                  c->d_poff, c->d_rperm, s)) != hipSuccess)
+      return hip_fail(c, e, "replay order");
+    st::TrackArgs r = track_args(c);
+    r.alive = c->d_ralive;
+    r.perm = c->d_rperm;
+    r.turns = (int)(t - last_audit);
+    r.report_every = 0;
+    r.partials = nullptr;
+    if ((e = st::launch_track(r, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "replay");
+    if ((e = st::launch_replay_finish(c->d_failed, c->d_ralive, c->alive, n, s)) != hipSuccess)
+      return hip_fail(c, e, "replay status");
+    if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");
+    if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");
+    last_audit = t;
     if (n_rep > 0 && t % rep_every == 0) {
       const int64_t rep = t / rep_every - 1;
       if ((e = st::launch_polarization_partials(c->spin, c->alive, n, c->d_partials + rep * nb * 4,
                                                 s)) != hipSuccess)
         return hip_fail(c, e, "polarization");
     }
+    ++t;
   }
   if (n_rep > 0 && (e = st::launch_reduce_polarization(c->d_partials, (int)nb, (int)n_rep, c->d_pol,
                                                        s)) != hipSuccess)

@@ -126,6 +126,17 @@ struct TrackArgs {
   // optional lane order: lane g works on particle perm[g] (a permutation of
   // 0..n-1), so that particles taking the same path share waves
   const int32_t* perm;
+  // surrogate tracking over several turns (null otherwise): the particles on
+  // the network are lanes g < feat_n (the lane order puts them first); such a
+  // lane writes its network inputs at the start of every turn,
+  // feat[(turn * feat_n + g) * feat_n_in + i] = (z_i - center_i) *
+  // inv_scale_i (i < 6) and extra (i = 6), and the number of turns it
+  // completes alive, turns_done[g]
+  float* feat;
+  int32_t* turns_done;
+  int64_t feat_n;
+  int32_t feat_n_in;
+  double feat_center[6], feat_inv_scale[6], feat_extra;
 };
 
 }  // namespace st

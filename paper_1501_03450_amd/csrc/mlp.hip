@@ -12,15 +12,13 @@
 //   forward        all four layers fused, activations kept in LDS; when
 //                  training it stores the two hidden activations the weight
 //                  gradients need (bf16, feature-major, copied out of LDS in
-//                  128-byte rows) and fuses the loss and dL/dy of the
-//                  normalised output
-//   backward_data  recomputes the pre-activations z1, z2, z3 of its tile
-//                  from the inputs and the stored bf16 activations with the
-//                  forward pass's own arithmetic (the same MFMA calls in the
-//                  same order, so the same bits), then dL/dy -> dz3 -> dz2 ->
-//                  dz1 through the transposed bf16 weights, with
-//                  per-workgroup partial sums of the bias and vector-layer
-//                  weight gradients
+//                  128-byte rows), silu'(z2) and silu'(z3) in bf16 (straight
+//                  from the accumulators), and fuses the loss, dL/dy of the
+//                  normalised output and the W4 and b4 gradient partials
+//   backward_data  dL/dy -> dz3 -> dz2 -> dz1 through the transposed bf16
+//                  weights, with z1 recomputed by the forward pass's vector
+//                  arithmetic and per-workgroup partial sums of the b3, b2, b1
+//                  and W1 gradients
 //   weight_grad    dW2, dW3 = dzᵀ hᵀ as split-K MFMA GEMMs over the batch
 //   reduce         fixed-order sum of the partials (deterministic)
 //   adam           fp32 master weights, then the bf16 copies W and Wᵀ
@@ -34,6 +32,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int W = kMlpWidth;       // 256
 constexpr int TM = 64;             // samples per workgroup
@@ -109,6 +108,36 @@ __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const flo
         // padded samples (beyond the batch) carry zero activations
         out_lds[(m0 + i) * LDA + n] = (__bf16)(m0 + i < rows ? silu(z) : 0.0f);
       }
+    }
+  }
+}
+
+// Training epilogue of layer 2: as hidden_epilogue, and silu'(z) rounded to
+// bf16 goes to HBM feature-major [256][ld] straight from the registers (a
+// lane holds four consecutive samples of one feature: one 8-byte store per
+// 16x16 tile); padded samples store zeros.
+__device__ __forceinline__ void hidden_epilogue_dsilu(const f32x4 acc[4][4], const float* bias,
+                                                      __bf16* out_lds, int rows, int n_base,
+                                                      int lane, __bf16* dsT, int64_t ld,
+                                                      int64_t b0) {
+  const int c = lane & 15, rq = 4 * (lane >> 4);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n = n_base + nt * 16 + c;
+    const float bn = bias[n];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int m0 = mt * 16 + rq;
+      bf16x4 d;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float z = acc[mt][nt][i] + bn;
+        const float sg = sigmoid(z);
+        const bool in = m0 + i < rows;
+        out_lds[(m0 + i) * LDA + n] = (__bf16)(in ? z * sg : 0.0f);
+        d[i] = (__bf16)(in ? sg * (1.0f + z * (1.0f - sg)) : 0.0f);
+      }
+      *reinterpret_cast<bf16x4*>(dsT + (size_t)n * ld + b0 + m0) = d;
     }
   }
 }
@@ -203,14 +232,20 @@ mlp_forward_kernel(const MlpArgs a) {
   zero_acc(acc);
   gemm_64x64(bufA, a.W2b, wv * 64, acc, lane);
   __syncthreads();
-  hidden_epilogue(acc, P + a.off.b2, bufA, rows, wv * 64, lane);
+  if (TRAIN)
+    hidden_epilogue_dsilu(acc, P + a.off.b2, bufA, rows, wv * 64, lane, a.dsT2, a.ld, b0);
+  else
+    hidden_epilogue(acc, P + a.off.b2, bufA, rows, wv * 64, lane);
   __syncthreads();
   if (TRAIN) store_feature_major(bufA, a.hT2, a.ld, b0, tid);
   // layer 3 (MFMA)
   zero_acc(acc);
   gemm_64x64(bufA, a.W3b, wv * 64, acc, lane);
   __syncthreads();
-  hidden_epilogue(acc, P + a.off.b3, bufA, rows, wv * 64, lane);
+  if (TRAIN)
+    hidden_epilogue_dsilu(acc, P + a.off.b3, bufA, rows, wv * 64, lane, a.dsT3, a.ld, b0);
+  else
+    hidden_epilogue(acc, P + a.off.b3, bufA, rows, wv * 64, lane);
   __syncthreads();
 
   // layer 4 (vector): thread t -> sample t % 64, output t / 64
@@ -227,8 +262,10 @@ mlp_forward_kernel(const MlpArgs a) {
   }
   __syncthreads();
 
+  // normalised output; when training, the loss and dL/dy (into ys, zero for
+  // padded samples)
   float l = 0.0f;
-  if (tid < TM && tid < rows) {
+  if (tid < TM) {
     const int m = tid;
     // frame base ref + lin x (zero columns past n_in: xs is zero-padded)
     float base[4];
@@ -247,8 +284,9 @@ mlp_forward_kernel(const MlpArgs a) {
     const float inv = 1.0f / ny;
     const float q[4] = {y0 * inv, y1 * inv, y2 * inv, y3 * inv};
     if (!TRAIN) {
-      for (int j = 0; j < 4; ++j) a.q_out[(b0 + m) * 4 + j] = q[j];
-    } else {
+      if (m < rows)
+        for (int j = 0; j < 4; ++j) a.q_out[(b0 + m) * 4 + j] = q[j];
+    } else if (m < rows) {
       const float* t = a.target + (b0 + m) * 4;
       float dq[4], qd = 0.0f;
       for (int j = 0; j < 4; ++j) {
@@ -257,28 +295,51 @@ mlp_forward_kernel(const MlpArgs a) {
         dq[j] = 2.0f * d * a.inv_loss_norm;
         qd += q[j] * dq[j];
       }
-      for (int j = 0; j < 4; ++j) a.dy[(b0 + m) * 4 + j] = a.out_scale[j] * ((dq[j] - q[j] * qd) * inv);
+      for (int j = 0; j < 4; ++j) ys[m][j] = a.out_scale[j] * ((dq[j] - q[j] * qd) * inv);
+    } else {
+      for (int j = 0; j < 4; ++j) ys[m][j] = 0.0f;
     }
   }
-  if (TRAIN) {
-    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
-    if (lane == 0) red[wv] = l;
-    __syncthreads();
-    if (tid == 0) a.loss_part[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * a.inv_loss_norm;
+  if (!TRAIN) return;
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+  if (lane == 0) red[wv] = l;
+  __syncthreads();
+  if (tid == 0) a.loss_part[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * a.inv_loss_norm;
+  const int blk = blockIdx.x;
+
+  // dL/dy to HBM for the backward pass; dW4 and db4 partials of this tile:
+  // thread k = feature k of h3 (bf16, as the output used it), samples in order
+  {
+    const int k = tid;
+    if (tid < TM && tid < rows)
+      for (int j = 0; j < 4; ++j) a.dy[(b0 + tid) * 4 + j] = ys[tid][j];
+    float gw[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < rows; ++m) {
+      const float h = (float)bufA[m * LDA + k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gw[j] = fmaf(ys[m][j], h, gw[j]);
+    }
+    for (int j = 0; j < 4; ++j) a.gpart_W4[((size_t)blk * 4 + j) * W + k] = gw[j];
+    if (tid < 4) {
+      float sb = 0.0f;
+      for (int m = 0; m < rows; ++m) sb += ys[m][tid];
+      a.gpart_b4[(size_t)blk * 4 + tid] = sb;
+    }
   }
 }
 
-// Backward through the layers for one tile of samples.  The pre-activations
-// are recomputed here rather than stored by the forward pass: z2 and z3 by
-// the forward pass's MFMA sums on the bf16 activations it stored for the
-// weight gradients (same operands, same order, so the same bits), z1 by its
-// vector loop.  z3 reaches the per-feature loop of the last layer through a
-// 16-sample chunk of LDS per wave; z2 is recomputed 32 samples at a time
-// while dz3 W3 is held, which keeps the kernel within two waves' registers.
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+#ifndef ST_MLP_BWD_WAVES
+#define ST_MLP_BWD_WAVES 2
+#endif
+// Backward through the layers for one tile of samples, from the forward
+// pass's dL/dy and silu'(z3), silu'(z2) (bf16): dz3 = (dL/dy W4) ⊙ silu'(z3),
+// dz2 = (dz3 W3) ⊙ silu'(z2) and dz1 = (dz2 W2) ⊙ silu'(z1), with z1 = W1 x +
+// b1 recomputed by the forward pass's vector arithmetic, and the
+// per-workgroup partial sums of the bias gradients b3, b2, b1 and of the W1
+// gradient.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ST_MLP_BWD_WAVES, ST_MLP_BWD_WAVES)))
 mlp_backward_data_kernel(const MlpArgs a) {
   __shared__ __align__(16) __bf16 bufA[TM * LDA];   // one buffer, as in the forward pass
-  __shared__ float zc[NT / 64][16][64];             // z3 of 16 samples x a wave's features
   __shared__ float xs[TM][kMlpMaxIn];
   __shared__ float dys[TM][4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -297,87 +358,64 @@ mlp_backward_data_kernel(const MlpArgs a) {
     const int m = i / 4, j = i % 4;
     dys[m][j] = m < rows ? a.dy[(b0 + m) * 4 + j] : 0.0f;
   }
-  load_feature_major(a.hT2, a.ld, b0, bufA, tid);
   __syncthreads();
-  if (tid < 4) {
-    float s = 0.0f;
-    for (int m = 0; m < rows; ++m) s += dys[m][tid];
-    a.gpart_b4[(size_t)blk * 4 + tid] = s;
-  }
 
-  // z3 - b3 = W3 h2, as in the forward pass
-  f32x4 acc[4][4];
-  zero_acc(acc);
-  gemm_64x64<2>(bufA, a.W3b, n_base, acc, lane);
-  __syncthreads();   // bufA: h2 -> dz3
-
-  // dz3 = (dy W4) ⊙ silu'(z3); dW4 and db3 partials.  Thread k = feature k
-  // runs through the samples in order, 16 at a time.
+  // dz3 = (dL/dy W4) ⊙ silu'(z3) in the accumulator layout (a lane: four
+  // consecutive samples of one feature, silu'(z3) one 8-byte load), its bias
+  // gradient partial before rounding, and dz3 in bf16 into LDS (zero past the
+  // batch, where dL/dy is zero)
   {
-    const int k = tid;
-    const float w0 = P[a.off.W4 + 0 * W + k], w1 = P[a.off.W4 + 1 * W + k];
-    const float w2 = P[a.off.W4 + 2 * W + k], w3 = P[a.off.W4 + 3 * W + k];
-    float gw[4] = {0.f, 0.f, 0.f, 0.f}, gb = 0.0f;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {   // unrolled: acc is indexed by mt
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        const float bn = P[a.off.b3 + n_base + nt * 16 + c];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) zc[wv][rq + i][nt * 16 + c] = acc[mt][nt][i] + bn;
-      }
-      __syncthreads();
-#pragma unroll 1
-      for (int u = 0; u < 16; ++u) {
-        const int m = mt * 16 + u;
-        float dz = 0.0f;
-        if (m < rows) {
-          const float z = zc[wv][u][lane];
-          const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
-          dz = dh * dsilu(z);
-          // the activation as the forward pass used it (bf16), so that dW4
-          // is the gradient of the loss the forward pass computed
-          const float h = (float)(__bf16)silu(z);
-          gw[0] = fmaf(dys[m][0], h, gw[0]);
-          gw[1] = fmaf(dys[m][1], h, gw[1]);
-          gw[2] = fmaf(dys[m][2], h, gw[2]);
-          gw[3] = fmaf(dys[m][3], h, gw[3]);
-          gb += dz;
-        }
-        bufA[m * LDA + k] = (__bf16)dz;
-      }
-      __syncthreads();   // zc is rewritten by the next chunk
-    }
-    for (int j = 0; j < 4; ++j) a.gpart_W4[((size_t)blk * 4 + j) * W + k] = gw[j];
-    a.gpart_b3[(size_t)blk * W + k] = gb;
-  }
-  store_feature_major(bufA, a.dzT3, a.ld, b0, tid);
-
-  // dz2 = (dz3 W3) ⊙ silu'(z2), z2 = W2 h1 + b2 as in the forward pass
-  zero_acc(acc);
-  gemm_64x64<2>(bufA, a.W3Tb, n_base, acc, lane);
-  __syncthreads();   // bufA: dz3 -> h1
-  load_feature_major(a.hT1, a.ld, b0, bufA, tid);
-  __syncthreads();
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    f32x4 z2[2][4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) z2[t][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    gemm_tiles<2, 2>(bufA + half * 32 * LDA, a.W2b, n_base, z2, lane);
+    float gb[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const float bn = P[a.off.b2 + n_base + nt * 16 + c];
+      const int n = n_base + nt * 16 + c;
+      const float w0 = P[a.off.W4 + 0 * W + n], w1 = P[a.off.W4 + 1 * W + n];
+      const float w2 = P[a.off.W4 + 2 * W + n], w3 = P[a.off.W4 + 3 * W + n];
+      const __bf16* dsrow = a.dsT3 + (size_t)n * a.ld + b0;
+      float sum = 0.0f;
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int mt = 0; mt < 4; ++mt) {
+        const bf16x4 d = *reinterpret_cast<const bf16x4*>(dsrow + mt * 16 + rq);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          acc[2 * half + t][nt][i] = acc[2 * half + t][nt][i] * dsilu(z2[t][nt][i] + bn);
+        for (int i = 0; i < 4; ++i) {
+          const int m = mt * 16 + rq + i;
+          const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
+          const float dz = dh * (float)d[i];
+          sum += dz;
+          bufA[m * LDA + n] = (__bf16)dz;
+        }
+      }
+      gb[nt] = sum;
+    }
+    // sum the four lane groups (samples rq = 0, 4, 8, 12 of every 16)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      gb[nt] += __shfl_xor(gb[nt], 16, 64);
+      gb[nt] += __shfl_xor(gb[nt], 32, 64);
+    }
+    if (lane < 16)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) a.gpart_b3[(size_t)blk * W + n_base + nt * 16 + c] = gb[nt];
+  }
+  __syncthreads();
+  store_feature_major(bufA, a.dzT3, a.ld, b0, tid);
+
+  // dz2 = (dz3 W3) ⊙ silu'(z2): a lane's four consecutive samples of one
+  // feature are one 8-byte load of the feature-major silu'(z2)
+  f32x4 acc[4][4];
+  zero_acc(acc);
+  gemm_64x64<2>(bufA, a.W3Tb, n_base, acc, lane);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const __bf16* dsrow = a.dsT2 + (size_t)(n_base + nt * 16 + c) * a.ld + b0;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x4 d = *reinterpret_cast<const bf16x4*>(dsrow + mt * 16 + rq);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[mt][nt][i] = acc[mt][nt][i] * (float)d[i];
     }
   }
-  __syncthreads();   // bufA: h1 -> dz2
+  __syncthreads();   // bufA: dz3 -> dz2
   store_grad_tile(acc, bufA, rows, n_base, lane);
   __syncthreads();
   store_feature_major(bufA, a.dzT2, a.ld, b0, tid);

@@ -30,6 +30,7 @@ struct st_mlp {
   std::vector<void*> scratch;
   __bf16 *hT[2] = {nullptr, nullptr};
   __bf16 *dzT[2] = {nullptr, nullptr};
+  __bf16 *dsT2 = nullptr, *dsT3 = nullptr;
   float *dy = nullptr, *loss_part = nullptr, *red_tmp = nullptr;
   float *gW1 = nullptr, *gb1 = nullptr, *gb2 = nullptr, *gb3 = nullptr, *gW4 = nullptr, *gb4 = nullptr;
   float *gW2 = nullptr, *gW3 = nullptr;
@@ -89,6 +90,8 @@ st_status ensure_scratch(st_mlp* m, int64_t ld) {
   hipError_t e = hipSuccess;
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->hT[l], (size_t)(W * ld));
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->dzT[l], (size_t)(W * ld));
+  if (e == hipSuccess) e = alloc(m, &m->dsT2, (size_t)(W * ld));
+  if (e == hipSuccess) e = alloc(m, &m->dsT3, (size_t)(W * ld));
   if (e == hipSuccess) e = alloc(m, &m->dy, (size_t)(ld * 4));
   if (e == hipSuccess) e = alloc(m, &m->loss_part, (size_t)nb);
   // multi-pass reduction buffers of the per-workgroup partials, one double
@@ -158,6 +161,8 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
   a.target = t;
   a.inv_loss_norm = 1.0f / (float)batch;
   a.loss_part = m->loss_part;
+  a.dsT2 = m->dsT2;
+  a.dsT3 = m->dsT3;
   a.dy = m->dy;
   a.hT1 = m->hT[0]; a.hT2 = m->hT[1];
   a.dzT2 = m->dzT[0]; a.dzT3 = m->dzT[1];

@@ -50,7 +50,7 @@ struct MlpArgs {
   const float* x;         // [batch][n_in]
   const float* target;    // [batch][4]
   float* q_out;           // [batch][4]
-  float* dy;              // [batch][4]
+  float* dy;              // [batch][4] dL/dy, from the forward pass to the backward
   float out_ref[4];       // output frame: u = out_ref + out_lin x + out_scale ⊙ y, q = u/|u|
   float out_scale[4];
   float out_lin[4][kMlpMaxIn];
@@ -60,6 +60,8 @@ struct MlpArgs {
   __bf16* hT2;
   __bf16* dzT2;           // [256][ld] gradients at the pre-activations
   __bf16* dzT3;
+  __bf16* dsT2;           // [256][ld] silu'(z2) and silu'(z3), from the forward pass
+  __bf16* dsT3;           //   to the backward
   float* gpart_W1;        // per-block partial gradients
   float* gpart_b1;
   float* gpart_b2;

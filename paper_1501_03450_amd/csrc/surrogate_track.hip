@@ -27,6 +27,31 @@ __global__ void __launch_bounds__(256) surrogate_spin_kernel(double* spin, const
   spin[j] = sx; spin[n + j] = sy; spin[2 * n + j] = sz;
 }
 
+// The same over the turns of a multi-turn launch, for the n_net particles on
+// the network (lanes g < n_net of the lane order perm): the particle that
+// completed turns_done[g] turns is rotated by the network's quaternion of each
+// of them (qnn [turn * n_net + g][4]), in turn order.
+__global__ void __launch_bounds__(256) surrogate_spin_turns_kernel(double* spin,
+                                                                   const int32_t* perm,
+                                                                   const int32_t* turns_done,
+                                                                   const float* qnn, int64_t n_net,
+                                                                   int64_t n) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= n_net) return;
+  const int k_end = turns_done[g];
+  if (k_end <= 0) return;
+  const int64_t j = perm[g];
+  double sx = spin[j], sy = spin[n + j], sz = spin[2 * n + j];
+  for (int k = 0; k < k_end; ++k) {
+    const float* f = qnn + ((int64_t)k * n_net + g) * 4;
+    Quat q = {f[0], f[1], f[2], f[3]};
+    const double inv = rsqrt_nr(fma(q.w, q.w, fma(q.x, q.x, fma(q.y, q.y, q.z * q.z))));
+    q.w *= inv; q.x *= inv; q.y *= inv; q.z *= inv;
+    qrotate(q, sx, sy, sz);
+  }
+  spin[j] = sx; spin[n + j] = sy; spin[2 * n + j] = sz;
+}
+
 // Audit: largest component difference between the network's quaternion and
 // the tracked one (sign aligned); above the threshold the particle falls back
 // (fallback[j] = turn) and is flagged in failed[j] for the rollback and
@@ -186,6 +211,15 @@ hipError_t launch_surrogate_spin(double* spin, const int32_t* alive, const int32
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(surrogate_spin_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spin,
                      alive, fallback, qnn, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_surrogate_spin_turns(double* spin, const int32_t* perm,
+                                       const int32_t* turns_done, const float* qnn, int64_t n_net,
+                                       int64_t n, hipStream_t s) {
+  if (n_net <= 0) return hipSuccess;
+  hipLaunchKernelGGL(surrogate_spin_turns_kernel, dim3((unsigned)((n_net + 255) / 256)), dim3(256), 0,
+                     s, spin, perm, turns_done, qnn, n_net, n);
   return hipGetLastError();
 }
 

@@ -690,7 +690,10 @@ track_kernel(const TrackArgs a) {
   }
   // Without reports the kernel has no barrier, so a wave with no live lane
   // (a replay of a few particles) may leave at once.
-  if (a.report_every == 0 && !__any(live)) return;
+  if (a.report_every == 0 && !__any(live)) {
+    if (SURR && a.turns_done && g < a.feat_n) a.turns_done[g] = 0;
+    return;
+  }
   const Particle p = make_particle(Pt, a);
   MKCache mkc{mk_slot, tid, __builtin_nan(""), __builtin_nan("")};
   Quat qturn = qident();
@@ -700,9 +703,21 @@ track_kernel(const TrackArgs a) {
   const ConstElem* tab = (const ConstElem*)(a.tab);
   const ConstSeq* seq = (const ConstSeq*)(a.seq);
 
+  int turns_done = 0;
   for (int t = 1; t <= a.turns; ++t) {
     const bool was_live = live;
     if (was_live) qturn = qident();
+    if (SURR && a.feat && live && !spin_lane) {
+      // the network's inputs at the start of this turn
+      float* f = a.feat + ((int64_t)(t - 1) * a.feat_n + g) * a.feat_n_in;
+      f[0] = (float)((X - a.feat_center[0]) * a.feat_inv_scale[0]);
+      f[1] = (float)((Px - a.feat_center[1]) * a.feat_inv_scale[1]);
+      f[2] = (float)((Y - a.feat_center[2]) * a.feat_inv_scale[2]);
+      f[3] = (float)((Py - a.feat_center[3]) * a.feat_inv_scale[3]);
+      f[4] = (float)((T - a.feat_center[4]) * a.feat_inv_scale[4]);
+      f[5] = (float)((Pt - a.feat_center[5]) * a.feat_inv_scale[5]);
+      if (a.feat_n_in == 7) f[6] = (float)a.feat_extra;
+    }
     for (int ie = 0; ie < a.n_elems; ++ie) {
       const DevElem e = load_elem(tab + seq[ie]);
       if (!live) continue;
@@ -794,6 +809,7 @@ track_kernel(const TrackArgs a) {
       }
       if (spin) qturn = qmul(q, qturn);
     }
+    if (was_live && live) ++turns_done;
     // A particle lost during this turn still receives the rotation of the
     // elements it completed before the loss.
     double sx = cold[0][tid], sy = cold[1][tid], sz = cold[2][tid];
@@ -818,6 +834,7 @@ track_kernel(const TrackArgs a) {
     }
   }
 
+  if (SURR && a.turns_done && g < a.feat_n) a.turns_done[g] = turns_done;
   if (valid && a.alive[j] == 1) {
     a.z[j] = X; a.z[n + j] = Px; a.z[2 * n + j] = Y; a.z[3 * n + j] = Py; a.z[4 * n + j] = T;
     a.spin[j] = cold[0][tid]; a.spin[n + j] = cold[1][tid]; a.spin[2 * n + j] = cold[2][tid];

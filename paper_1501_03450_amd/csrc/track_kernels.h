@@ -20,6 +20,12 @@ hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, bool ext, hipStr
 
 hipError_t launch_surrogate_spin(double* spin, const int32_t* alive, const int32_t* fallback,
                                  const float* qnn, int64_t n, hipStream_t s);
+// Network rotations of a multi-turn surrogate launch for the n_net particles
+// on the network, lanes g < n_net of the lane order perm (qnn [turn][n_net][4]
+// and turns_done [n_net] from the launch).
+hipError_t launch_surrogate_spin_turns(double* spin, const int32_t* perm,
+                                       const int32_t* turns_done, const float* qnn, int64_t n_net,
+                                       int64_t n, hipStream_t s);
 // Audit of the network quaternions against the tracked ones: failures get
 // fallback[j] = turn and failed[j] = 1; every other particle failed[j] = 0.
 hipError_t launch_audit(const int32_t* alive, int32_t* fallback, int32_t* failed, const float* qnn,

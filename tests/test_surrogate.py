@@ -119,7 +119,8 @@ def test_gradient_matches_the_cpu_reference_tensor_by_tensor(frame):
     torch.cuda.synchronize()
     p = _cpu_params(_params(m), n_in)
     g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64), ref, scale,
-                       round_act=M.bf16_round, round_dz=M.bf16_round, lin=lin)
+                       round_act=M.bf16_round, round_dz=M.bf16_round,
+                       round_ds=M.bf16_round, lin=lin)
     g_gpu = M.unflatten(g.cpu().numpy(), n_in)
     for k, (a, b) in enumerate(zip(g_gpu, g_cpu)):
         assert _rel_fro(a, b) <= 1e-2, (k, _rel_fro(a, b))
@@ -148,7 +149,8 @@ def test_gradient_of_a_large_ragged_batch_matches_the_cpu_reference(targets):
     torch.cuda.synchronize()
     p = _cpu_params(_params(m), n_in)
     g_cpu = M.backward(p, x.astype(np.float64), t.astype(np.float64), *FRAME,
-                       round_act=M.bf16_round, round_dz=M.bf16_round)
+                       round_act=M.bf16_round, round_dz=M.bf16_round,
+                       round_ds=M.bf16_round)
     errs = [_rel_fro(a, b) for a, b in zip(M.unflatten(g.cpu().numpy(), n_in), g_cpu)]
     print(f"{targets}: per-tensor relative errors", [f"{e:.1e}" for e in errs])
     assert max(errs) <= 1e-2, errs
@@ -495,3 +497,80 @@ def test_what_a_trained_network_gains_over_tracking_without_it():
     assert frac[True] < 0.5
     assert frac[False] > 0.95
     assert perr[True] < 1e-2
+
+
+def _qrot(q, s):
+    """S' = q S q* for unit quaternions q [4][n] (w, x, y, z) and vectors s [3][n]."""
+    w, v = q[0], q[1:]
+    t = 2.0 * np.cross(v.T, s.T).T
+    return s + w * t + np.cross(v.T, t.T).T
+
+
+def test_network_turns_rotate_by_the_networks_quaternions_along_the_double_precision_orbit():
+    # Twelve turns with audits after turns 1, 6 and 12 and no fallback: the
+    # turns in between run as multi-turn launches (four and five turns).  The
+    # spin must be the one obtained turn by turn: the double-precision
+    # one-turn rotation on the audit turns and the network's quaternion of
+    # the turn-start coordinates on the others, for the turns a particle
+    # completes.  Every fifth particle starts on the fallback path and gets
+    # the double-precision rotation every turn.  A line of matrix-kick
+    # quadrupoles and drifts with a snake, where the orbit-only push is the
+    # double-precision orbit bit for bit (bends would be crossed in one step
+    # there), and a 1 cm aperture that loses 7 % of the bunch over the twelve
+    # turns.
+    import math
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from paper_1501_03450_amd import binding as B
+    from paper_1501_03450_amd import surrogate as S
+    from workloads.lattice import drift, quad, snake
+    beam = Beam(aperture=0.01)
+    ring = [quad(1.0, 0.05, "mk", 4, 3), drift(2.0), quad(1.0, -0.05, "mk", 4, 3),
+            drift(2.0)] * 16 + [snake(math.pi, 0.0)]
+    z, s, a = gaussian_bunch(1500, 208, beam)
+    turns, every = 12, 6
+    m = B.st_mlp_create(0, 6, 256, seed=21)
+    ref = S.design_quaternion(ring, beam)
+    B.st_mlp_set_frame(m, ref, (0.05, 0.05, 0.05, 0.05))
+    inv = 1.0 / SIG
+    tr = SpinTracker(ring, beam)
+    tr.set_particles(z, s, a)
+    fb0 = np.zeros(1500, dtype=np.int32)
+    fb0[::5] = -1
+    fb = torch.as_tensor(fb0).cuda()
+    B.st_track_surrogate(tr.ctx, m, turns, every, 1e9, np.zeros(6), inv, 0.0, fb.data_ptr(),
+                         torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    zs, ss, as_ = tr.read()
+    tr.close()
+    np.testing.assert_array_equal(fb.cpu().numpy(), fb0)
+
+    # turn by turn
+    ft = SpinTracker(ring, beam)
+    ft.set_particles(z, s, a)
+    q64 = ft.enable_quaternions()
+    x = torch.empty((1500, 6), dtype=torch.float32, device="cuda")
+    qn = torch.empty((1500, 4), dtype=torch.float32, device="cuda")
+    spin = s.copy()
+    for t in range(1, turns + 1):
+        B.st_mlp_features(m, ft.z.data_ptr(), 1500, np.zeros(6), inv, 0.0, x.data_ptr())
+        B.st_mlp_infer(m, x.data_ptr(), qn.data_ptr(), 1500)
+        before = ft.alive.cpu().numpy() == 1
+        ft.track(1)
+        torch.cuda.synchronize()
+        after = ft.alive.cpu().numpy() == 1
+        full = before if (t % every == 0 or t == 1 or t == turns) else before & (fb0 != 0)
+        net = before & after & ~full
+        q = q64.cpu().numpy()
+        spin[:, full] = _qrot(q[:, full], spin[:, full])
+        q = qn.cpu().numpy().astype(np.float64).T
+        q = q / np.linalg.norm(q, axis=0)
+        spin[:, net] = _qrot(q[:, net], spin[:, net])
+    zf, _, af = ft.read()
+    ft.close()
+    B.st_mlp_destroy(m)
+    np.testing.assert_array_equal(as_, af)
+    np.testing.assert_array_equal(zs, zf)
+    lost = (af != 1).sum()
+    assert 50 < lost < 200
+    assert np.abs(ss - spin).max() <= 1e-12
