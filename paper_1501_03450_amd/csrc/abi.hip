@@ -760,11 +760,12 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
                                 c->d_perm, s);
   };
   if ((e = order()) != hipSuccess) return hip_fail(c, e, "lane order");
-  // particles on the network: the lanes the lane order puts first (the
-  // exclusive offset of the fallback key in the first block)
-  int32_t n_net = 0;
-  auto count_net = [&]() -> hipError_t {
-    hipError_t r = hipMemcpyAsync(&n_net, c->d_poff + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  // particles of the first key of a lane order (the exclusive offset of the
+  // second key in the first block): those on the network, or in a replay's
+  // order those that failed the audit
+  int32_t n_first = 0;
+  auto count_first = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(&n_first, c->d_poff + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (r == hipSuccess) r = hipStreamSynchronize(s);
     return r;
   };
@@ -782,7 +783,8 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
       // turns' quaternions in order (the spin does not act on the orbit)
       int64_t k = 1;
       while (k < k_max && !is_audit(t + k)) ++k;
-      if ((e = count_net()) != hipSuccess) return hip_fail(c, e, "network count");
+      if ((e = count_first()) != hipSuccess) return hip_fail(c, e, "network count");
+      const int32_t n_net = n_first;
       st::TrackArgs a = track_args(c);
       a.turns = (int)k;
       a.report_every = 0;
@@ -826,13 +828,19 @@ extern "C" st_status st_track_surrogate(st_ctx* c, st_mlp* m, int64_t turns, int
     if ((e = st::launch_partition(1, c->d_failed, c->alive, d_fallback, n, c->d_pcount,
                                   c->d_poff, c->d_rperm, s)) != hipSuccess)
       return hip_fail(c, e, "replay order");
-    st::TrackArgs r = track_args(c);
-    r.alive = c->d_ralive;
-    r.perm = c->d_rperm;
-    r.turns = (int)(t - last_audit);
-    r.report_every = 0;
-    r.partials = nullptr;
-    if ((e = st::launch_track(r, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "replay");
+    // the replay launch covers only the blocks of the failed particles'
+    // lanes (the lanes past them in the last block are not live in the replay)
+    if ((e = count_first()) != hipSuccess) return hip_fail(c, e, "replay count");
+    if (n_first > 0) {
+      st::TrackArgs r = track_args(c);
+      r.alive = c->d_ralive;
+      r.perm = c->d_rperm;
+      r.n_blocks = (int32_t)((n_first + st::track_block_size() - 1) / st::track_block_size());
+      r.turns = (int)(t - last_audit);
+      r.report_every = 0;
+      r.partials = nullptr;
+      if ((e = st::launch_track(r, c->nt, false, c->ext, s)) != hipSuccess) return hip_fail(c, e, "replay");
+    }
     if ((e = st::launch_replay_finish(c->d_failed, c->d_ralive, c->alive, n, s)) != hipSuccess)
       return hip_fail(c, e, "replay status");
     if ((e = checkpoint()) != hipSuccess) return hip_fail(c, e, "checkpoint");

@@ -574,3 +574,64 @@ def test_network_turns_rotate_by_the_networks_quaternions_along_the_double_preci
     lost = (af != 1).sum()
     assert 50 < lost < 200
     assert np.abs(ss - spin).max() <= 1e-12
+
+
+def _tracker_pair(ring, beam, z, s, a, fb0, turns, audit_every, threshold):
+    """(surrogate run, plain double-precision run) of the same bunch."""
+    import torch
+    from paper_1501_03450_amd import SpinTracker
+    from paper_1501_03450_amd import binding as B
+    m = B.st_mlp_create(0, 6, 256, seed=5)
+    tr = SpinTracker(ring, beam)
+    tr.set_particles(z, s, a)
+    fb = torch.as_tensor(fb0).cuda()
+    B.st_track_surrogate(tr.ctx, m, turns, audit_every, threshold, np.zeros(6), 1.0 / SIG, 0.0,
+                         fb.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    out = tr.read()
+    tr.close()
+    B.st_mlp_destroy(m)
+    ft = SpinTracker(ring, beam)
+    ft.set_particles(z, s, a)
+    ft.track(turns)
+    torch.cuda.synchronize()
+    ref = ft.read()
+    ft.close()
+    return out, ref, fb.cpu().numpy()
+
+
+def test_fallback_particles_get_the_double_precision_turn_bit_for_bit():
+    # Every particle starts on the fallback path; three turns, audits after
+    # turns 1 and 3 and a network turn between them, where the fallback lanes
+    # run the full double-precision turn inside the surrogate launch.  Orbit,
+    # spin and status must be the plain tracker's bit for bit.  A 2 cm
+    # aperture loses about a fifth of the bunch in drifts, bends and
+    # quadrupoles, so the partial turns of lost particles are covered too.
+    n = 1200
+    beam = Beam(aperture=0.02)
+    z, s, a = gaussian_bunch(n, 209, beam)
+    fb0 = np.full(n, -1, dtype=np.int32)
+    (zs, ss, as_), (z64, s64, a64), fb = _tracker_pair(rhic_like_ring(), beam, z, s, a, fb0, 3,
+                                                       1000, 1e9)
+    np.testing.assert_array_equal(fb, fb0)
+    assert 0.1 * n < (a64 != 1).sum() < 0.4 * n
+    np.testing.assert_array_equal(as_, a64)
+    np.testing.assert_array_equal(zs, z64)
+    np.testing.assert_array_equal(ss, s64)
+
+
+def test_replays_on_a_ring_with_bends_are_the_double_precision_turns_bit_for_bit():
+    # Threshold 0 with an audit every second turn: every particle fails the
+    # audit after turn 1 and is replayed (a launch over the failed lanes
+    # only), the survivors run turns 2 to 5 on the fallback path; on the
+    # RHIC-scale ring (sector bends, matrix-kick quadrupoles, thin
+    # sextupoles, snakes) the result must be the plain tracker's bit for bit.
+    beam = Beam(aperture=0.02)
+    z, s, a = gaussian_bunch(600, 210, beam)
+    fb0 = np.zeros(600, dtype=np.int32)
+    (zs, ss, as_), (z64, s64, a64), fb = _tracker_pair(rhic_like_ring(), beam, z, s, a, fb0, 5, 2,
+                                                       0.0)
+    assert (fb[a64 == 1] == 1).all()
+    np.testing.assert_array_equal(as_, a64)
+    np.testing.assert_array_equal(zs, z64)
+    np.testing.assert_array_equal(ss, s64)
