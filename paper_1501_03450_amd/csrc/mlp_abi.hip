@@ -24,7 +24,7 @@ struct st_mlp {
   float* adam_m = nullptr;
   float* adam_v = nullptr;
   float* grad = nullptr;
-  __bf16* wb = nullptr;             // W2, W3, W2ᵀ, W3ᵀ in bf16 (4 × 256²)
+  __bf16* wb = nullptr;             // W2, W3, W2ᵀ, W3ᵀ in bf16 (4 × 256²), then W4 split (16 × 256)
   // training scratch, sized for the largest batch seen
   int64_t cap_ld = 0;
   std::vector<void*> scratch;
@@ -136,6 +136,8 @@ st::MlpArgs base_args(st_mlp* m) {
   a.W3b_rw = m->wb + W2;
   a.W2Tb_rw = m->wb + 2 * W2;
   a.W3Tb_rw = m->wb + 3 * W2;
+  a.W4s = m->wb + 4 * W2;
+  a.W4s_rw = m->wb + 4 * W2;
   a.grad = m->grad;
   a.adam_m = m->adam_m;
   a.adam_v = m->adam_v;
@@ -233,7 +235,7 @@ st_status st_mlp_create(st_mlp** out, int device, int32_t n_in, int32_t width, u
   if (e == hipSuccess) e = hipMalloc(&m->adam_m, nbytes);
   if (e == hipSuccess) e = hipMalloc(&m->adam_v, nbytes);
   if (e == hipSuccess) e = hipMalloc(&m->grad, nbytes);
-  if (e == hipSuccess) e = hipMalloc(&m->wb, (size_t)4 * W * W * sizeof(__bf16));
+  if (e == hipSuccess) e = hipMalloc(&m->wb, ((size_t)4 * W * W + 16 * W) * sizeof(__bf16));
   if (e == hipSuccess) e = hipMemcpy(m->params, p.data(), nbytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(m->adam_m, 0, nbytes);
   if (e == hipSuccess) e = hipMemset(m->adam_v, 0, nbytes);

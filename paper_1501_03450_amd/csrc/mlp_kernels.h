@@ -47,6 +47,8 @@ struct MlpArgs {
   __bf16* W3b_rw;
   __bf16* W2Tb_rw;
   __bf16* W3Tb_rw;
+  const __bf16* W4s;      // bf16 [16][256]: W4 split into three bf16 parts (rows j, 4 + j,
+  __bf16* W4s_rw;         //   8 + j; rows 12-15 zero), W4 = hi + mid + lo to fp32 precision
   const float* x;         // [batch][n_in]
   const float* target;    // [batch][4]
   float* q_out;           // [batch][4]
