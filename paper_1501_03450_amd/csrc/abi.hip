@@ -551,7 +551,7 @@ st_status st_load_lattice(st_ctx* c, const st_element* els, int64_t n, const st_
   // series terms: cover the design angles with 10% margin; lanes beyond use sincos
   const double y = 1.21 * 0.25 * theta * theta;
   c->nt = 16;
-  for (int nt : {6, 8, 12, 16})
+  for (int nt : {5, 6, 8, 12, 16})
     if (series_ymax(nt) >= y) { c->nt = nt; break; }
   c->ymax = series_ymax(c->nt);
   c->beam = *b;

@@ -880,6 +880,7 @@ template <bool MIXED, bool SURR, bool EXT>
 hipError_t launch_nt(const TrackArgs& a, int nt, hipStream_t stream) {
   const dim3 grid((unsigned)a.n_blocks), block(kBlock);
   switch (nt) {
+    case 5:  hipLaunchKernelGGL((track_kernel<5, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;
     case 6:  hipLaunchKernelGGL((track_kernel<6, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;
     case 8:  hipLaunchKernelGGL((track_kernel<8, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;
     case 12: hipLaunchKernelGGL((track_kernel<12, MIXED, SURR, EXT>), grid, block, 0, stream, a); break;

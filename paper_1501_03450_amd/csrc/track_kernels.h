@@ -10,7 +10,7 @@ namespace st {
 int track_block_size();
 
 // nt: number of series terms of the double-precision quaternion half-angle
-// series (6, 8, 12, 16); mixed: the kernel with single-precision spin
+// series (5, 6, 8, 12, 16); mixed: the kernel with single-precision spin
 // arithmetic in the elements flagged for it.
 // ext: the lattice uses drift-kick (TEAPOT) bends or piece-wise constant
 // spin placements (run in double precision).
