@@ -344,6 +344,11 @@ __device__ __forceinline__ BendLane bend_lane(const BendParams& e, const BendSte
 // with W1 - W0 = (Px - Px(s))(Px + Px(s))/(W0 + W1), and
 // asin(Px/Pα) - asin(Px(s)/Pα) = asin((Px W1 - Px(s) W0)/Pα²): both
 // algebraically identical to the printed forms and free of cancellation.
+// YT = false leaves Y and T alone: they enter neither the next step nor Ω,
+// and the angle differences of the steps telescope, so a caller that steps
+// through a whole bend applies bend_yt once with the entrance and exit
+// values instead.
+template <bool YT = true>
 __device__ __forceinline__ void bend_step(const BendParams& e, const BendStep& k,
                                           const BendLane& bl, double& X, double& Px, double Py,
                                           double& Y, double& T, double& W0, double& r0,
@@ -355,14 +360,27 @@ __device__ __forceinline__ void bend_step(const BendParams& e, const BendStep& k
   double W1 = ps2n * r1;
   double dW = (Px - px1) * (Px + px1) * rcp_nr(W0 + W1);
   double X1 = fma(X, k.cs, fma(wme, k.omc, fma(Px, k.sn, dW)) * e.inv_eta_h);
-  double D = asin_small(fma(Px, W1, -px1 * W0) * invPa2);
-  Y = fma(Py, fma(D, e.inv_eta_h, k.s_eta), Y);
-  T += fma(-bl.ibh, D, bl.c0);
+  if constexpr (YT) {
+    double D = asin_small(fma(Px, W1, -px1 * W0) * invPa2);
+    Y = fma(Py, fma(D, e.inv_eta_h, k.s_eta), Y);
+    T += fma(-bl.ibh, D, bl.c0);
+  }
   wme += dW;
   X = X1;
   Px = px1;
   W0 = W1;
   r0 = r1;
+}
+
+// Y and T over a stretch of the bend of length k (BendStep) from the
+// horizontal momenta and Ps at its ends: the same angle difference and
+// updates as one step, bl being bend_lane(e, k, p).
+__device__ __forceinline__ void bend_yt(const BendParams& e, const BendStep& k, const BendLane& bl,
+                                        double Px0, double W0, double Px1, double W1, double Py,
+                                        double& Y, double& T, double invPa2) {
+  const double D = asin_small(fma(Px0, W1, -Px1 * W0) * invPa2);
+  Y = fma(Py, fma(D, e.inv_eta_h, k.s_eta), Y);
+  T += fma(-bl.ibh, D, bl.c0);
 }
 
 // Matrix-kick quadrupole constants of one particle (§3.3 eq. quadL over

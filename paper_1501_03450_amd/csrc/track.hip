@@ -174,9 +174,9 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   double r = KIND == 0 ? rsqrt_nr(ps2) : rsqrt_omega(ps2);
   double W = ps2 * r;
   double invPa2 = 0.0, wme = 0.0;
-  BendLane bl{0.0, 0.0};
+  // entrance Px and Ps of a bend: Y and T follow once from the two ends
+  const double Px_in = Px, W_in = W;
   if (KIND == 0) {
-    bl = bend_lane(el.b, el.b.slice, p);
     invPa2 = rcp_nr(Pa2);
     // W - η = (W² - η²)/(W + η) with W² - η² = (1 - η²) + (P² - 1) - Py² - Px²
     wme = (el.b.one_m_eta2 + ((p.c3 - Py * Py) - Px * Px)) * rcp_nr(W + el.b.eta);
@@ -245,7 +245,8 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
   for (int j = j0; j <= N; ++j) {
     if (j > 0) {
       if (KIND == 0) {
-        bend_step(el.b, el.b.slice, bl, X, Px, Py, Y, T, W, r, wme, Pa2, invPa2);
+        bend_step<false>(el.b, el.b.slice, BendLane{0.0, 0.0}, X, Px, Py, Y, T, W, r, wme, Pa2,
+                         invPa2);
       } else {
         if (KIND == 4) {
           teapot_slice(el.tp, X, Px, Y, Py, T, p);
@@ -260,6 +261,8 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
     }
     fold(j, std::false_type{});
   }
+  if (KIND == 0)
+    bend_yt(el.b, el.b.whole, bend_lane(el.b, el.b.whole, p), Px_in, W_in, Px, W, Py, Y, T, invPa2);
   if constexpr (spin32) {
     Q0 = qc_to_double(C0);
     if (K >= 1) Q1 = qc_to_double(C1);
