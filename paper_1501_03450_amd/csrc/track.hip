@@ -290,11 +290,12 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
 
 // Orbit only through a thick element (surrogate tracking, no spin): the
 // sector bend is an exact flow and is crossed in one step; quadrupoles keep
-// their slices.
+// their slices, and matrix-kick ones take their constants from the lane's
+// cache when one is passed.
 template <int KIND, bool Y4 = false>
 __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double& Px, double& Y,
                                             double& Py, double& T, const Particle& p,
-                                            const TrackArgs& a) {
+                                            const TrackArgs& a, MKCache* mkc = nullptr) {
   if (KIND == 0) {
     const double Pa2 = p.P2() - Py * Py;
     const double ps2 = fma(-Px, Px, Pa2);
@@ -312,7 +313,7 @@ __device__ __forceinline__ void thick_orbit(const DevElem& el, double& X, double
     return;
   }
   MKConst mc;
-  if (KIND == 1 || KIND == 3) mc = mk_const(el.q, p);
+  if (KIND == 1 || KIND == 3) mc = mk_cached(el.q, p, mkc);
   for (int j = 0; j < el.nsl; ++j) {
     if (KIND == 4) teapot_slice(el.tp, X, Px, Y, Py, T, p);
     else           quad_step2<KIND>(el.q, mc, X, Px, Y, Py, T, p, a);
@@ -747,9 +748,10 @@ track_kernel(const TrackArgs a) {
           else if (e.q.k1 >= 0.0) thick_orbit<1, true>(e, X, Px, Y, Py, T, p, a);
           else                    thick_orbit<3, true>(e, X, Px, Y, Py, T, p, a);
         } else if (e.kind == K_QUAD) {
+          MKCache* const c = EXT ? nullptr : &mkc;   // (the extended kernels keep no cache)
           if (e.orbit != M_MK)    thick_orbit<2>(e, X, Px, Y, Py, T, p, a);
-          else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a);
-          else                    thick_orbit<3>(e, X, Px, Y, Py, T, p, a);
+          else if (e.q.k1 >= 0.0) thick_orbit<1>(e, X, Px, Y, Py, T, p, a, c);
+          else                    thick_orbit<3>(e, X, Px, Y, Py, T, p, a, c);
         } else if (EXT && e.kind == K_RBEND) {
           rbend_rotate(e.rb.in, X, Px, Y, Py, T, p);
           rbend_fringe(e.rb, 1.0, X, Px, Y, Py, T, p);
