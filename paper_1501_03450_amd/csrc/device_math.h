@@ -120,6 +120,16 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(y, e, y);
 }
 
+// 1/sqrt(n2) for the squared norm of a quaternion that is a unit one up to
+// the extrapolation's small change: with e = n2 - 1 (exact for n2 near 1),
+// the binomial series 1 - e/2 + 3e²/8 - 5e³/16, whose first omitted term
+// 35e⁴/128 stays below 3e-17 for |e| <= 1e-4; a larger |e| takes rsqrt_nr.
+__device__ __forceinline__ double rsqrt_near_one(double n2) {
+  const double e = n2 - 1.0;
+  if (fabs(e) <= 1e-4) return fma(fma(fma(-0.3125, e, 0.375), e, -0.5), e, 1.0);
+  return rsqrt_nr(n2);
+}
+
 // 1/sqrt(x) where it only scales a precession vector: one Newton step from
 // the hardware estimate (measured within 2^-24.4 of 1/sqrt(x) on gfx950)
 // leaves a relative error below 5e-15, i.e. below 1e-15 rad in the rotation

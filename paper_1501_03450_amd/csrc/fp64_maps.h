@@ -94,19 +94,20 @@ __device__ __forceinline__ Particle make_particle(double Pt, const TrackArgs& a)
 }
 
 // With u = (Px² + Py²)/P², P/Ps = (1 - u)^(-1/2); g = P/Ps - 1 - u/2 is the
-// binomial series Σ_{k≥2} C(2k, k) (u/4)^k.  For u ≤ 2^-8 its terms through
-// u^6 leave less than 3e-18 of g; callers take a closed form beyond.
-constexpr double kSeriesMaxU = 0.00390625;
+// binomial series Σ_{k≥2} C(2k, k) (u/4)^k.  For u ≤ 2^-12 its terms through
+// u^4 leave less than 3e-19 (the first omitted one is 63/256 u^5); callers
+// take a closed form beyond.  Transverse momenta of the tracked bunches keep
+// u near 1e-8.
+constexpr double kSeriesMaxU = 1.0 / 4096.0;
 __device__ __forceinline__ double series_g(double u) {
-  constexpr double c2 = 3.0 / 8.0, c3 = 5.0 / 16.0, c4 = 35.0 / 128.0, c5 = 63.0 / 256.0,
-                   c6 = 231.0 / 1024.0;
-  return (u * u) * fma(u, fma(u, fma(u, fma(u, c6, c5), c4), c3), c2);
+  constexpr double c2 = 3.0 / 8.0, c3 = 5.0 / 16.0, c4 = 35.0 / 128.0;
+  return (u * u) * fma(u, fma(u, c4, c3), c2);
 }
 
 // Exact drift of length L (flow of -Ps + Pt/β0).  With e = P/Ps - 1 =
 // u/2 + g (series above), X and Y advance by L P(x,y) (1 + e)/P, and the
 // flight-time change L/β0 - L(1/β0 + Pt)/Ps is -L (1/β - 1/β0) - L e/β,
-// free of cancellation.  A lane with u > 2^-8 evaluates it as
+// free of cancellation.  A lane with u > 2^-12 evaluates it as
 // L (c1 - Px² - Py²) / (β0 Ps (Ps + 1 + β0 Pt)).
 __device__ __forceinline__ void drift(double L, double& X, double Px, double& Y, double Py,
                                       double& T, const Particle& p, double inv_beta0) {

@@ -284,7 +284,7 @@ __device__ __forceinline__ Quat thick_element(const DevElem& el, double& X, doub
       }
     }
   }
-  const double inv = rsqrt_nr(fma(Q0.w, Q0.w, fma(Q0.x, Q0.x, fma(Q0.y, Q0.y, Q0.z * Q0.z))));
+  const double inv = rsqrt_near_one(fma(Q0.w, Q0.w, fma(Q0.x, Q0.x, fma(Q0.y, Q0.y, Q0.z * Q0.z))));
   return {Q0.w * inv, Q0.x * inv, Q0.y * inv, Q0.z * inv};
 }
 
@@ -390,7 +390,7 @@ __device__ __forceinline__ Quat pwc_element(const DevElem& el, double& X, double
       }
     }
   }
-  const double inv = rsqrt_nr(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
+  const double inv = rsqrt_near_one(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
   return {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
 }
 
@@ -462,7 +462,7 @@ __device__ __forceinline__ Quat solenoid_element(const DevElem& el, double& X, d
     }
     Q = Q0;
   }
-  const double inv = rsqrt_nr(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
+  const double inv = rsqrt_near_one(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
   Q = {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
   solenoid_fringe(sp, -1.0, X, Px, Y, Py, p, wx, wy, wz);
   return qmul(rot(wx, wy, wz), qmul(Q, qin));
@@ -545,7 +545,7 @@ __device__ __forceinline__ Quat rbend_element(const DevElem& el, double& X, doub
     }
     Q = Q0;
   }
-  const double inv = rsqrt_nr(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
+  const double inv = rsqrt_near_one(fma(Q.w, Q.w, fma(Q.x, Q.x, fma(Q.y, Q.y, Q.z * Q.z))));
   Q = {Q.w * inv, Q.x * inv, Q.y * inv, Q.z * inv};
   X -= rb.xoff;
   const Quat qout = fringe_spin(-1.0);

@@ -20,11 +20,12 @@ def test_committed_traffic_record_is_for_the_committed_tracking_kernel():
     # The bench line's roofline.traffic comes from the rocprofv3 record under
     # profiles/, keyed by a hash of the tracking kernel's sources: it must be
     # the record of this kernel (else the bench reports null), and of the
-    # right size, above the 2 x 76 B of state per particle and within the
-    # spilled registers' share of it.
+    # right size: about the state a launch reads (76 B per particle: six
+    # coordinates, three spin components, the status) and writes back (68 B:
+    # Pt does not change), and within what spilled registers could add.
     sys.path.insert(0, ROOT)
     import bench
     traffic = bench.recorded_traffic(1 << 20, 100)
     assert traffic is not None
-    algorithmic = 2 * 76 * (1 << 20)
-    assert algorithmic < traffic < 2.5 * algorithmic
+    algorithmic = (76 + 68) * (1 << 20)
+    assert 0.99 * algorithmic < traffic < 2.5 * algorithmic
