@@ -299,18 +299,18 @@ HBM_PEAK_GBPS = 8000.0
 
 
 def train_bytes_per_sample(n_in):
-    """HBM bytes one training sample needs between the three step kernels:
-    forward reads x and the target and writes the bf16 activations h1, h2,
-    the bf16 SiLU derivatives of layers 2 and 3 and dL/dy; backward reads x,
-    dL/dy and the two derivatives and writes the bf16 gradients at the
-    pre-activations of layers 2 and 3; the weight-gradient kernel reads h1,
-    h2 and those two gradients (the split partials of the weight gradients
-    are per batch, not per sample, and not counted)."""
-    x, t, row, dy = 4 * n_in, 16, 2 * 256, 16
-    forward = x + t + 4 * row + dy
-    backward = x + dy + 2 * row + 2 * row
+    """HBM bytes one training sample needs between the two step kernels: the
+    fused forward-backward kernel reads x and the target, writes the bf16
+    activations h1, h2 and the bf16 SiLU derivative of layer 2 (read back by
+    its own backward half; the layer-3 derivative stays in registers) and
+    writes the bf16 gradients at the pre-activations of layers 2 and 3; the
+    weight-gradient kernel reads h1, h2 and those two gradients (the split
+    partials of the weight gradients are per batch, not per sample, and not
+    counted)."""
+    x, t, row = 4 * n_in, 16, 2 * 256
+    train = x + t + 2 * row + row + row + 2 * row
     weight_grad = 4 * row
-    return forward + backward + weight_grad
+    return train + weight_grad
 
 
 def quantiles(e):

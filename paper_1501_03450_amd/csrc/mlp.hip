@@ -14,17 +14,17 @@
 // precision too.
 //
 // Kernels (one batch, 64 samples per workgroup of four waves):
-//   forward        all four layers fused, activations kept in LDS; when
-//                  training it stores the two hidden activations the weight
-//                  gradients need and silu'(z2), silu'(z3) (bf16,
-//                  feature-major, straight from the accumulators), and fuses
-//                  the loss, dL/dy of the normalised output and the W4 and b4
-//                  gradient partials
-//   backward_data  dL/dy -> dz3 -> dz2 -> dz1 through the transposed bf16
-//                  weights, with z1 recomputed by the forward pass's
-//                  matrix-core products, dz3 and dz2 stored feature-major from
-//                  the accumulators, and per-workgroup partial sums of the b3,
-//                  b2, b1 and W1 gradients
+//   forward        inference: all four layers fused, activations kept in LDS
+//   forward<TRAIN> the training step's forward and backward passes of one
+//                  tile in one kernel: it stores the two hidden activations
+//                  the weight gradients need and silu'(z2) (bf16,
+//                  feature-major, straight from the accumulators), keeps
+//                  silu'(z3) in registers and dL/dy in LDS, fuses the loss,
+//                  then runs dL/dy -> dz3 -> dz2 -> dz1 through the transposed
+//                  bf16 weights with z1 recomputed by the same matrix-core
+//                  products, stores dz3 and dz2 feature-major, and forms the
+//                  per-workgroup partial sums of the b1..b4, W1 and W4
+//                  gradients
 //   weight_grad    dW2, dW3 = dzᵀ hᵀ as split-K MFMA GEMMs over the batch
 //   reduce         fixed-order sum of the partials (deterministic)
 //   adam           fp32 master weights, then the bf16 copies W and Wᵀ
@@ -154,13 +154,30 @@ __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const flo
   }
 }
 
+// silu'(z) of a wave's 64x64 tile kept in registers between the forward and
+// backward halves of the training kernel: the four bf16 values of
+// (nt, mt) (samples 16 mt + rq .. + 3 of feature 16 nt + c) packed two to a
+// 32-bit register.
+typedef uint32_t DsTile[4][4][2];
+
+__device__ __forceinline__ uint32_t pack_bf16x2(__bf16 lo, __bf16 hi) {
+  return (uint32_t)__builtin_bit_cast(unsigned short, lo) |
+         ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+}
+// element i (0..3) of a packed quadruple, as float
+__device__ __forceinline__ float ds_at(const uint32_t q[2], int i) {
+  const uint32_t w = q[i >> 1];
+  return __builtin_bit_cast(float, (i & 1) ? (w & 0xffff0000u) : (w << 16));
+}
+
 // Training epilogue of layers 2 and 3: as hidden_epilogue, and silu'(z)
-// rounded to bf16 goes to HBM feature-major [256][ld] the same way; padded
-// samples store zeros.
+// rounded to bf16 (zero for padded samples) either to HBM feature-major
+// [256][ld] from the registers (dsT set) or kept in registers for the
+// backward half of the kernel (ds).
 __device__ __forceinline__ void hidden_epilogue_dsilu(const f32x4 acc[4][4], const float* bias,
                                                       __bf16* out_lds, int rows, int n_base,
-                                                      int lane, __bf16* dsT, __bf16* hT,
-                                                      int64_t ld, int64_t b0) {
+                                                      int lane, __bf16* dsT, DsTile& ds,
+                                                      __bf16* hT, int64_t ld, int64_t b0) {
   const int c = lane & 15, rq = 4 * (lane >> 4);
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -179,7 +196,12 @@ __device__ __forceinline__ void hidden_epilogue_dsilu(const f32x4 acc[4][4], con
         out_lds[(m0 + i) * LDA + n] = h[i];
         d[i] = (__bf16)(in ? sg * (1.0f + z * (1.0f - sg)) : 0.0f);
       }
-      *reinterpret_cast<bf16x4*>(dsT + (size_t)n * ld + b0 + m0) = d;
+      if (dsT) {
+        *reinterpret_cast<bf16x4*>(dsT + (size_t)n * ld + b0 + m0) = d;
+      } else {
+        ds[nt][mt][0] = pack_bf16x2(d[0], d[1]);
+        ds[nt][mt][1] = pack_bf16x2(d[2], d[3]);
+      }
       if (hT) *reinterpret_cast<bf16x4*>(hT + (size_t)n * ld + b0 + m0) = h;
     }
   }
@@ -221,13 +243,27 @@ __device__ __forceinline__ void store_grad_tile(const f32x4 acc[4][4], __bf16* o
 
 // One activation buffer per workgroup (34 KB of LDS, so four workgroups fit
 // on a CU): each layer's GEMM reads it, a barrier, then the epilogue
-// overwrites it with the layer's output.  Compiled for four waves per SIMD
-// (128 registers; the GEMM loops unrolled by two, which keeps the training
-// kernel free of spills), so that four workgroups are resident per CU and
-// the whole batch of 1024 tiles of a 65536-sample batch is on the chip at
-// once.
+// overwrites it with the layer's output.  Inference is compiled for four
+// waves per SIMD (128 registers), so that four workgroups are resident per
+// CU and the whole batch of 1024 tiles of a 65536-sample batch is on the
+// chip at once.
+//
+// TRAIN: the same tile then runs the backward pass through the layers, with
+// silu'(z3) kept in registers from the forward epilogue (bf16, in the
+// accumulator layout the backward products use), silu'(z2) read back from
+// HBM and dL/dy in LDS: dz3 = (dL/dy W4) ⊙ silu'(z3), dz2 = (dz3 W3) ⊙
+// silu'(z2) and dz1 = (dz2 W2) ⊙ silu'(z1) with z1 recomputed by the same
+// matrix-core products as in the forward half.  h1, h2, dz2 and dz3 go to
+// HBM feature-major for the weight-gradient kernel; the bias, W1 and W4
+// gradient partials of the tile are formed here.  Two waves per SIMD (256
+// registers, 32 bytes per lane spilled; keeping silu'(z2) in registers as
+// well spilled 368, and three waves 228).
+#ifndef ST_MLP_TRAIN_WAVES
+#define ST_MLP_TRAIN_WAVES 2
+#endif
 template <bool TRAIN>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(TRAIN ? ST_MLP_TRAIN_WAVES : 4, TRAIN ? ST_MLP_TRAIN_WAVES : 4)))
 mlp_forward_kernel(const MlpArgs a) {
   __shared__ __align__(16) __bf16 bufA[TM * LDA];
   __shared__ float xs[TM][kMlpMaxIn];
@@ -258,11 +294,13 @@ mlp_forward_kernel(const MlpArgs a) {
   __syncthreads();
 
   // layer 2 (MFMA)
+  DsTile ds3;                         // silu'(z3) for the backward half
   zero_acc(acc);
   gemm_64x64<2>(bufA, a.W2b, wv * 64, acc, lane);
   __syncthreads();
   if (TRAIN)
-    hidden_epilogue_dsilu(acc, P + a.off.b2, bufA, rows, wv * 64, lane, a.dsT2, a.hT2, a.ld, b0);
+    hidden_epilogue_dsilu(acc, P + a.off.b2, bufA, rows, wv * 64, lane, a.dsT2, ds3, a.hT2, a.ld,
+                          b0);
   else
     hidden_epilogue(acc, P + a.off.b2, bufA, rows, wv * 64, lane, nullptr, 0, 0);
   __syncthreads();
@@ -271,7 +309,8 @@ mlp_forward_kernel(const MlpArgs a) {
   gemm_64x64<2>(bufA, a.W3b, wv * 64, acc, lane);
   __syncthreads();
   if (TRAIN)
-    hidden_epilogue_dsilu(acc, P + a.off.b3, bufA, rows, wv * 64, lane, a.dsT3, nullptr, a.ld, b0);
+    hidden_epilogue_dsilu(acc, P + a.off.b3, bufA, rows, wv * 64, lane, nullptr, ds3, nullptr, a.ld,
+                          b0);
   else
     hidden_epilogue(acc, P + a.off.b3, bufA, rows, wv * 64, lane, nullptr, 0, 0);
   __syncthreads();
@@ -342,14 +381,12 @@ mlp_forward_kernel(const MlpArgs a) {
   if (tid == 0) a.loss_part[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * a.inv_loss_norm;
   const int blk = blockIdx.x;
 
-  // dL/dy to HBM for the backward pass; dW4 and db4 partials of this tile.
+  // dW4 and db4 partials of this tile.
   // gW4[j][k] = sum over m of dL/dy[m][j] h3[m][k] on the bf16 matrix cores
   // with dL/dy in three parts (operand rows j, 4 + j, 8 + j; rows 12-15
   // zero; padded samples have dL/dy = 0): wave wv takes features 64 wv ..
   // 64 wv + 63, and the parts of row j come out in lane groups 0, 1 and 2
   {
-    if (tid < TM && tid < rows)
-      for (int j = 0; j < 4; ++j) a.dy[(b0 + tid) * 4 + j] = ys[tid][j];
     const int r = lane & 15, kb = 8 * (lane >> 4);
     f32x4 g[4];
 #pragma unroll
@@ -383,44 +420,10 @@ mlp_forward_kernel(const MlpArgs a) {
       a.gpart_b4[(size_t)blk * 4 + tid] = sb;
     }
   }
-}
+  __syncthreads();   // h3 in bufA read by every wave before dz3 replaces it
 
-// Three waves per SIMD: the kernel fits in 168 registers without spilling
-// (at four it spills 104 bytes per lane), and its GEMM loops unroll by four.
-// Timed on a 65536-sample batch: 77-78 us at three waves, 80-84 us at two,
-// 86 us at four.
-#ifndef ST_MLP_BWD_WAVES
-#define ST_MLP_BWD_WAVES 3
-#endif
-// Backward through the layers for one tile of samples, from the forward
-// pass's dL/dy and silu'(z3), silu'(z2) (bf16): dz3 = (dL/dy W4) ⊙ silu'(z3),
-// dz2 = (dz3 W3) ⊙ silu'(z2) and dz1 = (dz2 W2) ⊙ silu'(z1), with z1 = W1 x +
-// b1 recomputed by the forward pass's matrix-core products; dz3 and dz2 go to
-// HBM feature-major from the accumulators, and the per-workgroup partial sums
-// of the bias gradients b3, b2, b1 and of the W1 gradient are formed here.
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ST_MLP_BWD_WAVES, ST_MLP_BWD_WAVES)))
-mlp_backward_data_kernel(const MlpArgs a) {
-  __shared__ __align__(16) __bf16 bufA[TM * LDA];   // one buffer, as in the forward pass
-  __shared__ float xs[TM][kMlpMaxIn];
-  __shared__ float dys[TM][4];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t B = a.batch, b0 = (int64_t)blockIdx.x * TM;
-  const int rows = (int)min((int64_t)TM, B - b0);
-  const int nin = a.n_in;
-  const float* P = a.params;
-  const int blk = blockIdx.x;
+  // backward half
   const int n_base = wv * 64, c = lane & 15, rq = 4 * (lane >> 4);
-
-  for (int i = tid; i < TM * kMlpMaxIn; i += NT) {
-    const int m = i / kMlpMaxIn, k = i % kMlpMaxIn;
-    xs[m][k] = (m < rows && k < nin) ? a.x[(b0 + m) * nin + k] : 0.0f;
-  }
-  for (int i = tid; i < TM * 4; i += NT) {
-    const int m = i / 4, j = i % 4;
-    dys[m][j] = m < rows ? a.dy[(b0 + m) * 4 + j] : 0.0f;
-  }
-  __syncthreads();
-
   // dz3 = (dL/dy W4) ⊙ silu'(z3) in the accumulator layout (a lane: four
   // consecutive samples of one feature, silu'(z3) one 8-byte load), its bias
   // gradient partial before rounding, and dz3 in bf16 into LDS (zero past the
@@ -432,17 +435,15 @@ mlp_backward_data_kernel(const MlpArgs a) {
       const int n = n_base + nt * 16 + c;
       const float w0 = P[a.off.W4 + 0 * W + n], w1 = P[a.off.W4 + 1 * W + n];
       const float w2 = P[a.off.W4 + 2 * W + n], w3 = P[a.off.W4 + 3 * W + n];
-      const __bf16* dsrow = a.dsT3 + (size_t)n * a.ld + b0;
       float sum = 0.0f;
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
-        const bf16x4 d = *reinterpret_cast<const bf16x4*>(dsrow + mt * 16 + rq);
         bf16x4 v;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int m = mt * 16 + rq + i;
-          const float dh = w0 * dys[m][0] + w1 * dys[m][1] + w2 * dys[m][2] + w3 * dys[m][3];
-          const float dz = dh * (float)d[i];
+          const float dh = w0 * ys[m][0] + w1 * ys[m][1] + w2 * ys[m][2] + w3 * ys[m][3];
+          const float dz = dh * ds_at(ds3[nt][mt], i);
           sum += dz;
           v[i] = (__bf16)dz;
           bufA[m * LDA + n] = v[i];
@@ -465,9 +466,8 @@ mlp_backward_data_kernel(const MlpArgs a) {
 
   // dz2 = (dz3 W3) ⊙ silu'(z2): a lane's four consecutive samples of one
   // feature are one 8-byte load of the feature-major silu'(z2)
-  f32x4 acc[4][4];
   zero_acc(acc);
-  gemm_64x64<4>(bufA, a.W3Tb, n_base, acc, lane);
+  gemm_64x64<2>(bufA, a.W3Tb, n_base, acc, lane);
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     const __bf16* dsrow = a.dsT2 + (size_t)(n_base + nt * 16 + c) * a.ld + b0;
@@ -483,7 +483,7 @@ mlp_backward_data_kernel(const MlpArgs a) {
   __syncthreads();
   // dz1 = (dz2 W2) ⊙ silu'(z1), z1 = W1 x + b1 by the forward pass's products
   zero_acc(acc);
-  gemm_64x64<4>(bufA, a.W2Tb, n_base, acc, lane);
+  gemm_64x64<2>(bufA, a.W2Tb, n_base, acc, lane);
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     f32x4 z1[4];
@@ -707,11 +707,7 @@ hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s) {
-  const unsigned nb = (unsigned)((a.batch + TM - 1) / TM);
-  hipLaunchKernelGGL(mlp_backward_data_kernel, dim3(nb), dim3(NT), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+hipError_t launch_mlp_weight_grad(const MlpArgs& a, hipStream_t s) {
   // 4 tiles × 2 layers × n_splits splits; the kernel maps the linear block
   // index to (group, tile) so that each group stays on one XCD
   if (a.n_splits % 4 != 0) return hipErrorInvalidValue;

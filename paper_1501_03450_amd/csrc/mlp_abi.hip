@@ -30,8 +30,8 @@ struct st_mlp {
   std::vector<void*> scratch;
   __bf16 *hT[2] = {nullptr, nullptr};
   __bf16 *dzT[2] = {nullptr, nullptr};
-  __bf16 *dsT2 = nullptr, *dsT3 = nullptr;
-  float *dy = nullptr, *loss_part = nullptr, *red_tmp = nullptr;
+  __bf16* dsT2 = nullptr;
+  float *loss_part = nullptr, *red_tmp = nullptr;
   float *gW1 = nullptr, *gb1 = nullptr, *gb2 = nullptr, *gb3 = nullptr, *gW4 = nullptr, *gb4 = nullptr;
   float *gW2 = nullptr, *gW3 = nullptr;
 };
@@ -91,8 +91,6 @@ st_status ensure_scratch(st_mlp* m, int64_t ld) {
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->hT[l], (size_t)(W * ld));
   for (int l = 0; l < 2 && e == hipSuccess; ++l) e = alloc(m, &m->dzT[l], (size_t)(W * ld));
   if (e == hipSuccess) e = alloc(m, &m->dsT2, (size_t)(W * ld));
-  if (e == hipSuccess) e = alloc(m, &m->dsT3, (size_t)(W * ld));
-  if (e == hipSuccess) e = alloc(m, &m->dy, (size_t)(ld * 4));
   if (e == hipSuccess) e = alloc(m, &m->loss_part, (size_t)nb);
   // multi-pass reduction buffers of the per-workgroup partials, one double
   // buffer per tensor (all reduced together)
@@ -164,8 +162,6 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
   a.inv_loss_norm = 1.0f / (float)batch;
   a.loss_part = m->loss_part;
   a.dsT2 = m->dsT2;
-  a.dsT3 = m->dsT3;
-  a.dy = m->dy;
   a.hT1 = m->hT[0]; a.hT2 = m->hT[1];
   a.dzT2 = m->dzT[0]; a.dzT3 = m->dzT[1];
   a.gpart_W1 = m->gW1; a.gpart_b1 = m->gb1; a.gpart_b2 = m->gb2; a.gpart_b3 = m->gb3;
@@ -175,8 +171,8 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
   const int nb = (int)(ld / tile);
   const int64_t W = st::kMlpWidth;
   hipError_t e;
-  if ((e = st::launch_mlp_forward(a, true, s)) != hipSuccess) return hip_fail(m, e, "forward");
-  if ((e = st::launch_mlp_backward(a, s)) != hipSuccess) return hip_fail(m, e, "backward");
+  if ((e = st::launch_mlp_forward(a, true, s)) != hipSuccess) return hip_fail(m, e, "forward and backward");
+  if ((e = st::launch_mlp_weight_grad(a, s)) != hipSuccess) return hip_fail(m, e, "weight gradients");
   const st::MlpOffsets& o = m->off;
   // every tensor's partials (and the loss) reduced together, one launch per pass
   st::SumSegment red[] = {

@@ -52,7 +52,6 @@ struct MlpArgs {
   const float* x;         // [batch][n_in]
   const float* target;    // [batch][4]
   float* q_out;           // [batch][4]
-  float* dy;              // [batch][4] dL/dy, from the forward pass to the backward
   float out_ref[4];       // output frame: u = out_ref + out_lin x + out_scale ⊙ y, q = u/|u|
   float out_scale[4];
   float out_lin[4][kMlpMaxIn];
@@ -60,10 +59,9 @@ struct MlpArgs {
   float* loss_part;       // [blocks]
   __bf16* hT1;            // [256][ld] activations, feature-major
   __bf16* hT2;
+  __bf16* dsT2;           // [256][ld] silu'(z2) (bf16), from the forward half to the backward
   __bf16* dzT2;           // [256][ld] gradients at the pre-activations
   __bf16* dzT3;
-  __bf16* dsT2;           // [256][ld] silu'(z2) and silu'(z3), from the forward pass
-  __bf16* dsT3;           //   to the backward
   float* gpart_W1;        // per-block partial gradients
   float* gpart_b1;
   float* gpart_b2;
@@ -88,8 +86,11 @@ int mlp_tile();
 hipError_t launch_features(const double* z, int64_t n, const FeatureMap& f, int n_in, float* x,
                            hipStream_t s);
 hipError_t launch_targets(const double* q, int64_t n, const double* ref, float* t, hipStream_t s);
+// train: the fused forward and backward pass of one batch (activations, dz2,
+// dz3 and the per-tile partials); otherwise inference into q_out.
 hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s);
-hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s);
+// dW2, dW3 split-K partials from the feature-major activations and gradients.
+hipError_t launch_mlp_weight_grad(const MlpArgs& a, hipStream_t s);
 // Several independent column sums of row-major partials part[parts][len] into
 // out[len], reduced 64 rows per pass until one row is left; the segments
 // share one launch per pass.  tmp: the sum over segments of
