@@ -653,10 +653,24 @@ __global__ void __launch_bounds__(256) sum_partials_multi_kernel(const SumPass p
   }
 }
 
-__global__ void __launch_bounds__(256) adam_kernel(const MlpArgs a, float lr, float c1, float c2) {
+__global__ void __launch_bounds__(256) adam_kernel(const MlpArgs a, float lr, float c1, float c2,
+                                                   const AdamPending pend) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0 && pend.loss_rows > 0) {
+    float l = 0.0f;
+    for (int r = 0; r < pend.loss_rows; ++r) l += pend.loss_src[r];
+    *pend.loss_out = l;
+  }
   if (i >= a.n_params) return;
-  const float g = a.grad[i];
+  float g = a.grad[i];
+  for (int k = 0; k < pend.n; ++k) {
+    const int64_t e = i - pend.seg[k].off;
+    if (e >= 0 && e < pend.seg[k].len) {
+      g = 0.0f;
+      for (int r = 0; r < pend.seg[k].rows; ++r) g += pend.seg[k].src[(int64_t)r * pend.seg[k].len + e];
+      a.grad[i] = g;
+    }
+  }
   const float m = fmaf(kAdamBeta1, a.adam_m[i] - g, g);      // β1 m + (1 - β1) g
   const float v = fmaf(kAdamBeta2, a.adam_v[i] - g * g, g * g);
   a.adam_m[i] = m;
@@ -719,7 +733,8 @@ size_t sum_partials_tmp(int64_t len, int parts) {
   return parts > 64 ? 2 * (size_t)len * (size_t)((parts + 63) / 64) : 0;
 }
 
-hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tmp, hipStream_t s) {
+hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tmp, hipStream_t s,
+                                     int max_passes, SumLeft* left) {
   if (nseg < 0 || nseg > kMaxSumSegments) return hipErrorInvalidValue;
   struct State { const float* src; int rows; float* tmp; size_t half; int C; int gx; bool done; };
   State st[kMaxSumSegments];
@@ -733,6 +748,11 @@ hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tm
     off += sum_partials_tmp(g.len, g.parts);
   }
   for (int pass = 0;; ++pass) {
+    if (pass == max_passes) {
+      for (int k = 0; k < nseg; ++k)
+        if (left) left[k] = {st[k].src, segs[k].len, st[k].done ? 0 : st[k].rows};
+      return hipSuccess;
+    }
     SumPass p;
     p.nseg = 0;
     int64_t blocks = 0;
@@ -752,7 +772,11 @@ hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tm
       idx[p.nseg++] = k;
       blocks += (int64_t)st[k].gx * next;
     }
-    if (p.nseg == 0) return hipSuccess;
+    if (p.nseg == 0) {
+      if (left)
+        for (int k = 0; k < nseg; ++k) left[k] = {st[k].src, segs[k].len, 0};
+      return hipSuccess;
+    }
     hipLaunchKernelGGL(sum_partials_multi_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -768,9 +792,12 @@ hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tm
   }
 }
 
-hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s) {
+hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s,
+                       const AdamPending* pending) {
+  AdamPending none{};
+  const AdamPending& p = pending ? *pending : none;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.n_params + 255) / 256)), dim3(256), 0, s, a, lr,
-                     c1, c2);
+                     c1, c2, p);
   return hipGetLastError();
 }
 

@@ -148,8 +148,11 @@ st::MlpArgs base_args(st_mlp* m) {
 }
 
 // Forward, backward and the gradient reduction for one batch into m->grad.
+// With pend set, the reduction stops after its first pass and pend receives
+// what is left for the Adam kernel to add (the per-tile partials of a large
+// batch; the split-K weight partials are complete after one pass).
 st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t batch, float* d_loss,
-                           hipStream_t s) {
+                           hipStream_t s, st::AdamPending* pend = nullptr) {
   const int64_t tile = st::mlp_tile();
   const int64_t ld = (batch + tile - 1) / tile * tile;
   st_status st = ensure_scratch(m, ld);
@@ -182,8 +185,21 @@ st_status compute_gradient(st_mlp* m, const float* x, const float* t, int64_t ba
       {m->gW4, 4 * W, nb, m->grad + o.W4},       {m->gb4, 4, nb, m->grad + o.b4},
       {m->loss_part, 1, nb, d_loss}};
   const int nseg = d_loss ? 9 : 8;
-  if ((e = st::launch_sum_partials_multi(red, nseg, m->red_tmp, s)) != hipSuccess)
+  st::SumLeft left[9];
+  if ((e = st::launch_sum_partials_multi(red, nseg, m->red_tmp, s, pend ? 1 : (1 << 30), left)) !=
+      hipSuccess)
     return hip_fail(m, e, "gradient reduction");
+  if (pend) {
+    *pend = st::AdamPending{};
+    for (int k = 0; k < 8; ++k)
+      if (left[k].rows > 0)
+        pend->seg[pend->n++] = {left[k].src, red[k].out - m->grad, left[k].len, left[k].rows};
+    if (d_loss && left[8].rows > 0) {
+      pend->loss_src = left[8].src;
+      pend->loss_rows = left[8].rows;
+      pend->loss_out = d_loss;
+    }
+  }
   return ST_OK;
 }
 
@@ -416,11 +432,14 @@ st_status st_mlp_train_step(st_mlp* m, const float* d_x, const float* d_t, int64
   if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(m, ST_EINVAL, "learning rate must be > 0");
   DeviceGuard g(m->device);
   hipStream_t s = (hipStream_t)stream;
-  if ((st = compute_gradient(m, d_x, d_t, batch, d_loss, s)) != ST_OK) return st;
+  // the reduction's last pass (the per-tile partials of a large batch) runs
+  // inside the Adam kernel
+  st::AdamPending pend;
+  if ((st = compute_gradient(m, d_x, d_t, batch, d_loss, s, &pend)) != ST_OK) return st;
   m->step += 1;
   const float c1 = (float)(1.0 / (1.0 - std::pow((double)st::kAdamBeta1, (double)m->step)));
   const float c2 = (float)(1.0 / (1.0 - std::pow((double)st::kAdamBeta2, (double)m->step)));
-  hipError_t e = st::launch_adam(base_args(m), lr, c1, c2, s);
+  hipError_t e = st::launch_adam(base_args(m), lr, c1, c2, s, &pend);
   if (e != hipSuccess) return hip_fail(m, e, "adam");
   return ST_OK;
 }

@@ -103,7 +103,30 @@ struct SumSegment {
 };
 constexpr int kMaxSumSegments = 12;
 size_t sum_partials_tmp(int64_t len, int parts);
-hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tmp, hipStream_t s);
+// What a reduction stopped after `max_passes` passes still has to add: rows
+// partial rows of len values at src (rows == 0: the segment is complete in
+// its out).
+struct SumLeft {
+  const float* src;
+  int64_t len;
+  int rows;
+};
+hipError_t launch_sum_partials_multi(const SumSegment* segs, int nseg, float* tmp, hipStream_t s,
+                                     int max_passes = 1 << 30, SumLeft* left = nullptr);
+// Adam over the flat parameters, taking the gradient of the parameters at
+// [off, off + len) of a pending segment as the sum of its remaining rows (in
+// row order; written to grad as well), and the loss likewise.
+struct AdamPending {
+  int n;
+  struct {
+    const float* src;
+    int64_t off, len;
+    int rows;
+  } seg[kMaxSumSegments];
+  const float* loss_src;
+  int loss_rows;
+  float* loss_out;
+};
 // Least-squares fit of targets t [n][4] on the inputs augmented with a
 // constant, [1, x] (D = n_in + 1 columns), in double precision.  Pass 1:
 // per-block partial sums of the normal equations, D*D entries of [1,x][1,x]ᵀ
@@ -118,7 +141,8 @@ hipError_t launch_fit_normal(const float* x, const float* t, int64_t n, int n_in
                              hipStream_t s);
 hipError_t launch_fit_residual(const float* x, const float* t, int64_t n, int n_in,
                                const FitCoef& coef, double* partials, hipStream_t s);
-hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s);
+hipError_t launch_adam(const MlpArgs& a, float lr, float c1, float c2, hipStream_t s,
+                       const AdamPending* pending = nullptr);
 hipError_t launch_refresh_bf16(const MlpArgs& a, hipStream_t s);
 
 }  // namespace st

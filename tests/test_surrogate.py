@@ -247,22 +247,29 @@ def test_gradient_of_a_batch_is_the_weighted_mean_of_its_parts():
     B.st_mlp_destroy(m)
 
 
-def test_adam_step_is_the_textbook_update():
+@pytest.mark.parametrize("batch", [512, 70001])
+def test_adam_step_is_the_textbook_update(batch):
+    # 70001 samples are 1094 tiles: the train step leaves the last pass of
+    # the per-tile partial sums to the Adam kernel, the gradient call does it
+    # in the reduction kernel
     import torch
     from paper_1501_03450_amd import binding as B
     n_in = 6
     m = B.st_mlp_create(0, n_in, 256, seed=13)
-    x, t = _data(512, n_in, 3)
+    x, t = _data(batch, n_in, 3)
     dx, dt = _dev(x, np.float32), _dev(t, np.float32)
     n = B.st_mlp_params(m)
     p0 = _params(m).astype(np.float64)
     g = torch.zeros(n, dtype=torch.float32, device="cuda")
-    B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), 512, g.data_ptr())
-    B.st_mlp_train_step(m, dx.data_ptr(), dt.data_ptr(), 512, 1e-3)
+    loss_g = torch.zeros(1, dtype=torch.float32, device="cuda")
+    loss_t = torch.zeros(1, dtype=torch.float32, device="cuda")
+    B.st_mlp_gradient(m, dx.data_ptr(), dt.data_ptr(), batch, g.data_ptr(), loss_g.data_ptr())
+    B.st_mlp_train_step(m, dx.data_ptr(), dt.data_ptr(), batch, 1e-3, loss_t.data_ptr())
     torch.cuda.synchronize()
     p1 = _params(m).astype(np.float64)
     ref = M.adam_step(p0.copy(), np.zeros(n), np.zeros(n), g.cpu().numpy().astype(np.float64), 1, 1e-3)
     np.testing.assert_allclose(p1, ref, rtol=0, atol=1e-6)
+    assert abs(loss_t.item() - loss_g.item()) <= 1e-6 * loss_g.item()
     B.st_mlp_destroy(m)
 
 
