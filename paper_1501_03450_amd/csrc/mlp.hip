@@ -19,7 +19,7 @@
 //                  tile in one kernel: it stores the two hidden activations
 //                  the weight gradients need and silu'(z2) (bf16,
 //                  feature-major, straight from the accumulators), keeps
-//                  silu'(z3) in registers and dL/dy in LDS, fuses the loss,
+//                  silu'(z3) and dL/dy in LDS, fuses the loss,
 //                  then runs dL/dy -> dz3 -> dz2 -> dz1 through the transposed
 //                  bf16 weights with z1 recomputed by the same matrix-core
 //                  products, stores dz3 and dz2 feature-major, and forms the
@@ -154,29 +154,28 @@ __device__ __forceinline__ void hidden_epilogue(const f32x4 acc[4][4], const flo
   }
 }
 
-// silu'(z) of a wave's 64x64 tile kept in registers between the forward and
-// backward halves of the training kernel: the four bf16 values of
-// (nt, mt) (samples 16 mt + rq .. + 3 of feature 16 nt + c) packed two to a
-// 32-bit register.
-typedef uint32_t DsTile[4][4][2];
+// silu'(z3) of a wave's 64x64 tile kept in LDS between the forward and
+// backward halves of the training kernel, in the accumulator layout: lane
+// `lane` of the wave stores the four bf16 values of (nt, mt) (samples
+// 16 mt + rq .. + 3 of feature 16 nt + c) as one 8-byte word at
+// [(4 nt + mt) * 64 + lane] of the wave's 8 KB, and reads back only its own.
 
 __device__ __forceinline__ uint32_t pack_bf16x2(__bf16 lo, __bf16 hi) {
   return (uint32_t)__builtin_bit_cast(unsigned short, lo) |
          ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
 }
 // element i (0..3) of a packed quadruple, as float
-__device__ __forceinline__ float ds_at(const uint32_t q[2], int i) {
-  const uint32_t w = q[i >> 1];
+__device__ __forceinline__ float ds_at(uint2 q, int i) {
+  const uint32_t w = (i >> 1) ? q.y : q.x;
   return __builtin_bit_cast(float, (i & 1) ? (w & 0xffff0000u) : (w << 16));
 }
 
 // Training epilogue of layers 2 and 3: as hidden_epilogue, and silu'(z)
 // rounded to bf16 (zero for padded samples) either to HBM feature-major
-// [256][ld] from the registers (dsT set) or kept in registers for the
-// backward half of the kernel (ds).
+// [256][ld] from the registers (dsT set) or to the wave's LDS words (ds).
 __device__ __forceinline__ void hidden_epilogue_dsilu(const f32x4 acc[4][4], const float* bias,
                                                       __bf16* out_lds, int rows, int n_base,
-                                                      int lane, __bf16* dsT, DsTile& ds,
+                                                      int lane, __bf16* dsT, uint2* ds,
                                                       __bf16* hT, int64_t ld, int64_t b0) {
   const int c = lane & 15, rq = 4 * (lane >> 4);
 #pragma unroll
@@ -199,8 +198,7 @@ __device__ __forceinline__ void hidden_epilogue_dsilu(const f32x4 acc[4][4], con
       if (dsT) {
         *reinterpret_cast<bf16x4*>(dsT + (size_t)n * ld + b0 + m0) = d;
       } else {
-        ds[nt][mt][0] = pack_bf16x2(d[0], d[1]);
-        ds[nt][mt][1] = pack_bf16x2(d[2], d[3]);
+        ds[(nt * 4 + mt) * 64 + lane] = make_uint2(pack_bf16x2(d[0], d[1]), pack_bf16x2(d[2], d[3]));
       }
       if (hT) *reinterpret_cast<bf16x4*>(hT + (size_t)n * ld + b0 + m0) = h;
     }
@@ -249,15 +247,16 @@ __device__ __forceinline__ void store_grad_tile(const f32x4 acc[4][4], __bf16* o
 // chip at once.
 //
 // TRAIN: the same tile then runs the backward pass through the layers, with
-// silu'(z3) kept in registers from the forward epilogue (bf16, in the
-// accumulator layout the backward products use), silu'(z2) read back from
-// HBM and dL/dy in LDS: dz3 = (dL/dy W4) ⊙ silu'(z3), dz2 = (dz3 W3) ⊙
-// silu'(z2) and dz1 = (dz2 W2) ⊙ silu'(z1) with z1 recomputed by the same
-// matrix-core products as in the forward half.  h1, h2, dz2 and dz3 go to
-// HBM feature-major for the weight-gradient kernel; the bias, W1 and W4
-// gradient partials of the tile are formed here.  Two waves per SIMD (256
-// registers, 32 bytes per lane spilled; keeping silu'(z2) in registers as
-// well spilled 368, and three waves 228).
+// silu'(z3) kept in LDS from the forward epilogue (bf16, in the accumulator
+// layout the backward products use), silu'(z2) read back from HBM and dL/dy
+// in LDS: dz3 = (dL/dy W4) ⊙ silu'(z3), dz2 = (dz3 W3) ⊙ silu'(z2) and
+// dz1 = (dz2 W2) ⊙ silu'(z1) with z1 recomputed by the same matrix-core
+// products as in the forward half.  h1, h2, dz2 and dz3 go to HBM
+// feature-major for the weight-gradient kernel; the bias, W1 and W4 gradient
+// partials of the tile are formed here.  Two waves per SIMD, 180 registers
+// without spills and 68 KB of LDS (two workgroups per CU); with silu'(z3)
+// in registers instead the kernel spilled 32 bytes per lane, and with
+// silu'(z2) there as well 368.
 #ifndef ST_MLP_TRAIN_WAVES
 #define ST_MLP_TRAIN_WAVES 2
 #endif
@@ -269,7 +268,10 @@ mlp_forward_kernel(const MlpArgs a) {
   __shared__ float xs[TM][kMlpMaxIn];
   __shared__ float ys[TM][4];
   __shared__ float red[NT / 64];
+  // training: silu'(z3) of the four waves' tiles (32 KB; inference: unused)
+  __shared__ uint2 ds3s[TRAIN ? (NT / 64) * 16 * 64 : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint2* const ds3 = ds3s + (TRAIN ? wv * 16 * 64 : 0);
   const int64_t B = a.batch, b0 = (int64_t)blockIdx.x * TM;
   const int rows = (int)min((int64_t)TM, B - b0);
   const int nin = a.n_in;
@@ -294,7 +296,6 @@ mlp_forward_kernel(const MlpArgs a) {
   __syncthreads();
 
   // layer 2 (MFMA)
-  DsTile ds3;                         // silu'(z3) for the backward half
   zero_acc(acc);
   gemm_64x64<2>(bufA, a.W2b, wv * 64, acc, lane);
   __syncthreads();
@@ -443,7 +444,7 @@ mlp_forward_kernel(const MlpArgs a) {
         for (int i = 0; i < 4; ++i) {
           const int m = mt * 16 + rq + i;
           const float dh = w0 * ys[m][0] + w1 * ys[m][1] + w2 * ys[m][2] + w3 * ys[m][3];
-          const float dz = dh * ds_at(ds3[nt][mt], i);
+          const float dz = dh * ds_at(ds3[(nt * 4 + mt) * 64 + lane], i);
           sum += dz;
           v[i] = (__bf16)dz;
           bufA[m * LDA + n] = v[i];
