@@ -131,7 +131,8 @@ struct TrackArgs {
   // lane writes its network inputs at the start of every turn,
   // feat[(turn * feat_n + g) * feat_n_in + i] = (z_i - center_i) *
   // inv_scale_i (i < 6) and extra (i = 6), and the number of turns it
-  // completes alive, turns_done[g]
+  // completes alive, turns_done[g]; these lanes run on an orbit-only kernel,
+  // the lanes from feat_n on (the particles that fall back) on the full one
   float* feat;
   int32_t* turns_done;
   int64_t feat_n;

@@ -59,6 +59,9 @@ __device__ __forceinline__ DevElem load_elem(const ConstElem* p) {
 #ifndef ST_WAVES_PER_EU_WIDE
 #define ST_WAVES_PER_EU_WIDE 2
 #endif
+#ifndef ST_WAVES_PER_EU_ORBIT
+#define ST_WAVES_PER_EU_ORBIT 3
+#endif
 
 // Romberg spin integration through one thick element, fused with its orbit
 // slices (KIND: 0 sector bend, 1 MK quadrupole focusing in x, 3 MK
@@ -668,10 +671,12 @@ __device__ __forceinline__ Quat standard_thick(const DevElem& e, double& X, doub
 // EXT: the kernel also knows the drift-kick sector bend and the piece-wise
 // constant spin placements (kept out of the other instantiations so that
 // their register allocation is not shaped by code they never run).
-template <int NT, bool MIXED, bool SURR, bool EXT>
-__global__ void __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu((MIXED || SURR || EXT) ? ST_WAVES_PER_EU_WIDE : ST_WAVES_PER_EU)))
-track_kernel(const TrackArgs a) {
+// ORBIT: the network turns of the particles on the network, the first
+// a.feat_n lanes of the lane order: the orbit only, with the network's inputs
+// written at the start of each turn. With ORBIT false, SURR launches leave
+// those lanes to the ORBIT launch and take the particles that fall back.
+template <int NT, bool MIXED, bool SURR, bool EXT, bool ORBIT>
+__device__ __forceinline__ void track_body(const TrackArgs a) {
   __shared__ double red[kBlock / 64][4];
   // Cold per-lane data in LDS: the spin (touched once per turn) and the
   // orbit at the current element's entrance (read back only on a loss).
@@ -679,7 +684,7 @@ track_kernel(const TrackArgs a) {
   __shared__ double mk_slot[EXT ? 1 : kMKWords][kBlock];
   const int tid = threadIdx.x;
   const int64_t g = (int64_t)blockIdx.x * kBlock + tid;
-  const bool valid = g < a.n;
+  const bool valid = ORBIT ? g < a.feat_n : (g < a.n && !(SURR && g < a.feat_n));
   const int64_t j = (valid && a.perm) ? (int64_t)a.perm[g] : g;
   int32_t status = valid ? a.alive[j] : 0;
   bool live = status == 1;
@@ -695,13 +700,13 @@ track_kernel(const TrackArgs a) {
   // Without reports the kernel has no barrier, so a wave with no live lane
   // (a replay of a few particles) may leave at once.
   if (a.report_every == 0 && !__any(live)) {
-    if (SURR && a.turns_done && g < a.feat_n) a.turns_done[g] = 0;
+    if (ORBIT && a.turns_done && g < a.feat_n) a.turns_done[g] = 0;
     return;
   }
   const Particle p = make_particle(Pt, a);
   MKCache mkc{mk_slot, tid, __builtin_nan(""), __builtin_nan("")};
   Quat qturn = qident();
-  const bool spin_lane = !SURR || (valid && a.fallback[j] != 0);
+  const bool spin_lane = !ORBIT && (!SURR || (valid && a.fallback[j] != 0));
   // The lattice is read-only for the whole launch: reading it through the
   // constant address space lets the uniform loads go through the scalar cache.
   const ConstElem* tab = (const ConstElem*)(a.tab);
@@ -711,7 +716,7 @@ track_kernel(const TrackArgs a) {
   for (int t = 1; t <= a.turns; ++t) {
     const bool was_live = live;
     if (was_live) qturn = qident();
-    if (SURR && a.feat && live && !spin_lane) {
+    if (ORBIT && a.feat && live) {
       // the network's inputs at the start of this turn
       float* f = a.feat + ((int64_t)(t - 1) * a.feat_n + g) * a.feat_n_in;
       f[0] = (float)((X - a.feat_center[0]) * a.feat_inv_scale[0]);
@@ -839,16 +844,34 @@ track_kernel(const TrackArgs a) {
     }
   }
 
-  if (SURR && a.turns_done && g < a.feat_n) a.turns_done[g] = turns_done;
+  if (ORBIT && a.turns_done && g < a.feat_n) a.turns_done[g] = turns_done;
   if (valid && a.alive[j] == 1) {
     a.z[j] = X; a.z[n + j] = Px; a.z[2 * n + j] = Y; a.z[3 * n + j] = Py; a.z[4 * n + j] = T;
-    a.spin[j] = cold[0][tid]; a.spin[n + j] = cold[1][tid]; a.spin[2 * n + j] = cold[2][tid];
+    if (!ORBIT) {
+      a.spin[j] = cold[0][tid]; a.spin[n + j] = cold[1][tid]; a.spin[2 * n + j] = cold[2][tid];
+    }
     a.alive[j] = status;
     if (a.qout) {
       a.qout[j] = qturn.w; a.qout[n + j] = qturn.x; a.qout[2 * n + j] = qturn.y;
       a.qout[3 * n + j] = qturn.z;
     }
   }
+}
+
+template <int NT, bool MIXED, bool SURR, bool EXT>
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((MIXED || SURR || EXT) ? ST_WAVES_PER_EU_WIDE : ST_WAVES_PER_EU)))
+track_kernel(const TrackArgs a) {
+  track_body<NT, MIXED, SURR, EXT, false>(a);
+}
+
+// Without the spin arithmetic the orbit push needs about 140 registers, so
+// three waves share a SIMD (the LDS of three workgroups fits a CU).
+template <int NT, bool EXT>
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(ST_WAVES_PER_EU_ORBIT)))
+orbit_kernel(const TrackArgs a) {
+  track_body<NT, false, true, EXT, true>(a);
 }
 
 // Deterministic second pass of the polarization reduction: one block per
@@ -894,11 +917,37 @@ hipError_t launch_nt(const TrackArgs& a, int nt, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <bool EXT>
+hipError_t launch_orbit(const TrackArgs& a, int nt, hipStream_t stream) {
+  const dim3 grid((unsigned)((a.feat_n + kBlock - 1) / kBlock)), block(kBlock);
+  switch (nt) {
+    case 5:  hipLaunchKernelGGL((orbit_kernel<5, EXT>), grid, block, 0, stream, a); break;
+    case 6:  hipLaunchKernelGGL((orbit_kernel<6, EXT>), grid, block, 0, stream, a); break;
+    case 8:  hipLaunchKernelGGL((orbit_kernel<8, EXT>), grid, block, 0, stream, a); break;
+    case 12: hipLaunchKernelGGL((orbit_kernel<12, EXT>), grid, block, 0, stream, a); break;
+    default: hipLaunchKernelGGL((orbit_kernel<16, EXT>), grid, block, 0, stream, a); break;
+  }
+  return hipGetLastError();
+}
+
+// Surrogate turns: the particles on the network (the first a.feat_n lanes of
+// the lane order) on the orbit-only kernel, then the ones that fall back on
+// the full kernel, whose workgroups below a.feat_n leave at once.
+template <bool EXT>
+hipError_t launch_surrogate(const TrackArgs& a, int nt, hipStream_t stream) {
+  if (a.feat_n > 0) {
+    const hipError_t e = launch_orbit<EXT>(a, nt, stream);
+    if (e != hipSuccess) return e;
+  }
+  if (a.feat_n >= a.n) return hipSuccess;
+  return launch_nt<false, true, EXT>(a, nt, stream);
+}
+
 hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, bool ext, hipStream_t stream) {
   // the extended methods run in double precision only
-  if (ext) return a.fallback ? launch_nt<false, true, true>(a, nt, stream)
+  if (ext) return a.fallback ? launch_surrogate<true>(a, nt, stream)
                              : launch_nt<false, false, true>(a, nt, stream);
-  if (a.fallback) return launch_nt<false, true, false>(a, nt, stream);
+  if (a.fallback) return launch_surrogate<false>(a, nt, stream);
   return mixed ? launch_nt<true, false, false>(a, nt, stream)
                : launch_nt<false, false, false>(a, nt, stream);
 }

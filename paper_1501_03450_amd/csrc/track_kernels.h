@@ -16,7 +16,8 @@ int track_block_size();
 // spin placements (run in double precision).
 hipError_t launch_track(const TrackArgs& a, int nt, bool mixed, bool ext, hipStream_t stream);
 
-// a.fallback non-null selects the surrogate-tracking kernel.
+// a.fallback non-null selects surrogate tracking: an orbit-only launch for the
+// a.feat_n particles on the network, then the full kernel for the others.
 
 hipError_t launch_surrogate_spin(double* spin, const int32_t* alive, const int32_t* fallback,
                                  const float* qnn, int64_t n, hipStream_t s);
